@@ -1,0 +1,311 @@
+"""Python face of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+import this module.  It loads ``liboracle.so`` built from ``dd_oracle.c`` in
+this directory and never touches the HIP library.
+
+Every array here uses the natural layout:
+  links  complex128 (V, 4, 3, 3)
+  fields complex128 (ncol, nsite, 12), nsite = nt * L^3 on a slab [t0, t0+nt)
+         (local site index ((t - t0) mod T) * L^3 + spatial index)
+  propagators: 12 columns, S[j, s, c] = D^-1(s, x_src)_{c j}
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from collections import deque
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "dd_oracle.c")
+
+_c = ctypes
+_dp = _c.POINTER(_c.c_double)
+_ip = _c.POINTER(_c.c_int)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (C11, OpenMP, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def _configure(L):
+    L.ora_gamma.argtypes = [_c.c_void_p]
+    L.ora_block_apply.argtypes = [_c.c_int, _c.c_int, _c.c_int, _c.c_void_p, _c.c_double,
+                                  _c.c_int, _c.c_int, _c.c_int, _c.c_int,
+                                  _c.c_void_p, _c.c_void_p]
+    L.ora_gamma5.argtypes = [_c.c_long, _c.c_void_p, _c.c_void_p]
+    L.ora_solve.argtypes = [_c.c_int, _c.c_int, _c.c_int, _c.c_void_p, _c.c_double,
+                            _c.c_int, _c.c_int, _c.c_int, _c.c_void_p, _c.c_void_p,
+                            _c.c_double, _c.c_int, _c.c_int, _ip, _dp]
+    L.ora_solve.restype = _c.c_int
+    L.ora_pion.argtypes = [_c.c_int, _c.c_int, _c.c_int, _c.c_void_p, _c.c_int, _dp]
+    L.ora_link_grad.argtypes = [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int,
+                                _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_void_p]
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = _configure(_c.CDLL(LIB_PATH))
+    return _lib
+
+
+def use_library(path):
+    """Point this module at another build of the oracle (the mutation tests use
+    this to check that planted mistakes are caught).  Returns the previous one."""
+    global _lib
+    prev = lib()
+    _lib = _configure(_c.CDLL(path))
+    return prev
+
+
+def restore_library(prev):
+    global _lib
+    _lib = prev
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"] and a.dtype == np.complex128, (a.dtype, a.flags)
+    return a.ctypes.data_as(_c.c_void_p)
+
+
+def _links(U: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(U, dtype=np.complex128)
+
+
+def gamma_matrices() -> np.ndarray:
+    """(5, 4, 4): gamma_0..gamma_3 and gamma_5 of the oracle's chiral basis."""
+    g = np.zeros((5, 4, 4), dtype=np.complex128)
+    lib().ora_gamma(_ptr(g))
+    return g
+
+
+def _norm_dom(T: int, dom):
+    return (0, T) if dom is None else (int(dom[0]) % T, int(dom[1]))
+
+
+def block_apply(U, kappa, T, L, bc, dst, src, psi):
+    """P_dst D P_src psi for slabs dst, src ((t0, nt) or None = whole lattice).
+
+    psi: (ncol, nsrc, 12) or (nsrc, 12).  Returns the same rank on dst.
+    """
+    U = _links(U)
+    dt0, dnt = _norm_dom(T, dst)
+    st0, snt = _norm_dom(T, src)
+    L3 = L ** 3
+    one = psi.ndim == 2
+    p = np.ascontiguousarray(psi.reshape(-1, snt * L3, 12), dtype=np.complex128)
+    out = np.empty((p.shape[0], dnt * L3, 12), dtype=np.complex128)
+    for j in range(p.shape[0]):
+        lib().ora_block_apply(T, L, bc, _ptr(U), float(kappa), dt0, dnt, st0, snt,
+                              _ptr(p[j]), _ptr(out[j]))
+    return out[0] if one else out
+
+
+def apply_dirac(U, kappa, T, L, bc, psi, dom=None):
+    """D psi on the whole lattice (dom None) or D_Lambda psi on the slab dom."""
+    return block_apply(U, kappa, T, L, bc, dom, dom, psi)
+
+
+def gamma5(psi: np.ndarray) -> np.ndarray:
+    p = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.empty_like(p)
+    lib().ora_gamma5(p.size // 12, _ptr(p), _ptr(out))
+    return out
+
+
+def solve(U, kappa, T, L, bc, b, dom=None, tol=1e-12, maxit=100000, method=0):
+    """x = D_Lambda^-1 b column by column.  Returns (x, iters, relres, status).
+
+    method 0 = BiCGStab, 1 = CGNR.
+    """
+    U = _links(U)
+    t0, nt = _norm_dom(T, dom)
+    L3 = L ** 3
+    one = b.ndim == 2
+    bb = np.ascontiguousarray(b.reshape(-1, nt * L3, 12), dtype=np.complex128)
+    x = np.zeros_like(bb)
+    ncol = bb.shape[0]
+    it = (_c.c_int * ncol)()
+    rr = (_c.c_double * ncol)()
+    st = lib().ora_solve(T, L, bc, _ptr(U), float(kappa), t0, nt, ncol, _ptr(bb), _ptr(x),
+                         float(tol), int(maxit), int(method), it, rr)
+    return (x[0] if one else x), list(it), list(rr), st
+
+
+def slab_extract(T, L, field, dom):
+    """Restrict whole-lattice field(s) (..., V, 12) to the slab dom (compact)."""
+    t0, nt = _norm_dom(T, dom)
+    L3 = L ** 3
+    f = field.reshape(field.shape[:-2] + (T, L3, 12))
+    ts = [(t0 + k) % T for k in range(nt)]
+    return f[..., ts, :, :].reshape(field.shape[:-2] + (nt * L3, 12))
+
+
+def slab_insert(T, L, field, dom, part):
+    """Write the compact slab field part into the whole-lattice field (in place)."""
+    t0, nt = _norm_dom(T, dom)
+    L3 = L ** 3
+    f = field.reshape(field.shape[:-2] + (T, L3, 12))
+    p = part.reshape(part.shape[:-2] + (nt, L3, 12))
+    for k in range(nt):
+        f[..., (t0 + k) % T, :, :] = p[..., k, :, :]
+
+
+def domain_distances(T, bc, domains):
+    """Block distances of the slabs from slab 0 on the graph of non-zero D blocks.
+
+    Two slabs are adjacent when a time hop of D joins them: consecutive slabs,
+    and the last and first one across the time edge unless bc == 0.
+    """
+    n = len(domains)
+    adj = [set() for _ in range(n)]
+    for a in range(n):
+        ta0, tan = domains[a]
+        end = (ta0 + tan) % T  # first slice after slab a
+        for b in range(n):
+            if b != a and domains[b][0] % T == end:
+                if bc == 0 and ta0 + tan >= T:
+                    continue  # the hop across the time edge is absent
+                adj[a].add(b)
+                adj[b].add(a)
+    d = [None] * n
+    d[0] = 0
+    q = deque([0])
+    while q:
+        a = q.popleft()
+        for b in adj[a]:
+            if d[b] is None:
+                d[b] = d[a] + 1
+                q.append(b)
+    return d
+
+
+def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100000,
+                          method=0, eta=None):
+    """Factorised point-to-all propagator across time-slab domains.
+
+    domains: list of (t0, nt) partitioning [0, T); the source must lie in
+    domains[0].  With psi_0 = D_L0^-1 eta (first case, Eq. 13, factorised
+    term) and, outward by block distance d,
+        psi_k = - D_Lk^-1 sum_{j : d(j) = d(k) - 1} D_{Lk,Lj} psi_j
+    (second case, Eq. 14 with the overlap region empty, iterated over the
+    chain of regions), the result is S_fact = sum_k psi_k.  Returns
+    (S_fact (12, V, 12), per-domain solve info).
+    """
+    U = _links(U)
+    L3 = L ** 3
+    V = T * L3
+    if eta is None:
+        t, x, y, z = src
+        eta = np.zeros((12, V, 12), dtype=np.complex128)
+        s = ((t * L + z) * L + y) * L + x
+        for j in range(12):
+            eta[j, s, j] = 1.0
+    dist = domain_distances(T, bc, domains)
+    if any(dd is None for dd in dist):
+        raise ValueError("domains are not connected")
+    order = sorted(range(len(domains)), key=lambda k: dist[k])
+    psi = {}
+    info = {}
+    S = np.zeros((eta.shape[0], V, 12), dtype=np.complex128)
+    for k in order:
+        dk = domains[k]
+        if dist[k] == 0:
+            rhs = slab_extract(T, L, eta, dk)
+        else:
+            rhs = np.zeros((eta.shape[0], dk[1] * L3, 12), dtype=np.complex128)
+            for j in range(len(domains)):
+                if dist[j] == dist[k] - 1:
+                    rhs -= block_apply(U, kappa, T, L, bc, dk, domains[j], psi[j])
+        x, it, rr, st = solve(U, kappa, T, L, bc, rhs, dom=dk, tol=tol, maxit=maxit, method=method)
+        psi[k] = x
+        info[k] = dict(iters=it, relres=rr, status=st)
+        slab_insert(T, L, S, dk, x)
+    return S, info
+
+
+def exact_propagator(U, kappa, T, L, bc, src, tol=1e-12, maxit=100000, method=0):
+    """S_exact = D^-1 eta for the 12 point sources at src (whole lattice)."""
+    V = T * L ** 3
+    t, x, y, z = src
+    eta = np.zeros((12, V, 12), dtype=np.complex128)
+    s = ((t * L + z) * L + y) * L + x
+    for j in range(12):
+        eta[j, s, j] = 1.0
+    S, it, rr, st = solve(U, kappa, T, L, bc, eta, dom=None, tol=tol, maxit=maxit, method=method)
+    return S, dict(iters=it, relres=rr, status=st)
+
+
+def pion_correlator(T, L, S, t_src):
+    """C(t) = sum_xvec tr[S S^dagger] at sink time (t_src + t) mod T (Eq. 4, W_Pc)."""
+    S = np.ascontiguousarray(S, dtype=np.complex128)
+    C = (_c.c_double * T)()
+    lib().ora_pion(T, L, S.shape[0], _ptr(S), int(t_src), C)
+    return np.array(list(C))
+
+
+def link_grad(T, L, bc, dom, X, Y, coeff=1.0, grad=None):
+    """grad += coeff * d/dU [-2 Re <Y, D_Lambda X>] at fixed X, Y, shape (V, 4, 3, 3)."""
+    t0, nt = _norm_dom(T, dom)
+    V = T * L ** 3
+    if grad is None:
+        grad = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+    Xc = np.ascontiguousarray(X.reshape(-1, nt * L ** 3, 12), dtype=np.complex128)
+    Yc = np.ascontiguousarray(Y.reshape(-1, nt * L ** 3, 12), dtype=np.complex128)
+    lib().ora_link_grad(T, L, bc, t0, nt, Xc.shape[0], _ptr(Xc), _ptr(Yc), float(coeff), _ptr(grad))
+    return grad
+
+
+def domain_action(U, kappa, T, L, bc, dom, phi, tol=1e-13, method=0):
+    """S = phi^dagger (D_L^dagger D_L)^-1 phi = |Y|^2 with D_L^dagger Y = phi, X = D_L^-1 Y.
+
+    D_L^dagger = gamma_5 D_L gamma_5, so Y = gamma_5 D_L^-1 gamma_5 phi.
+    Returns (S, X, Y).
+    """
+    y5, *_ = solve(U, kappa, T, L, bc, gamma5(phi), dom=dom, tol=tol, method=method)
+    Y = gamma5(y5)
+    X, *_ = solve(U, kappa, T, L, bc, Y, dom=dom, tol=tol, method=method)
+    return float(np.vdot(Y, Y).real), X, Y
+
+
+def su3_generators() -> np.ndarray:
+    """T^a = lambda^a / 2 (Gell-Mann), shape (8, 3, 3)."""
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1] = -1j
+    lam[1][1, 0] = 1j
+    lam[2][0, 0] = 1
+    lam[2][1, 1] = -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2] = -1j
+    lam[4][2, 0] = 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2] = -1j
+    lam[6][2, 1] = 1j
+    lam[7][0, 0] = lam[7][1, 1] = 1 / np.sqrt(3)
+    lam[7][2, 2] = -2 / np.sqrt(3)
+    return lam / 2
+
+
+def su3_force(U, grad):
+    """F^a_mu(x) = dS/d omega^a for U -> exp(i omega^a T^a) U, from the gradient
+    g = dS/dRe U + i dS/dIm U:  F^a = Re tr[g^dagger i T^a U].  Shape (V, 4, 8)."""
+    Tg = su3_generators()
+    TU = np.einsum("aij,...jk->...aik", 1j * Tg, U)
+    return np.einsum("...ji,...aji->...a", np.conj(grad), TU).real

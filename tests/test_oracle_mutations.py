@@ -1,0 +1,75 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's C source (a flipped sign, a
+dropped factor, a transposed or misplaced link, a wrong index), builds it, points the
+oracle at the copy and requires that at least one of the named pins fails.  Nothing
+here touches the GPU library.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle as O
+import test_oracle_force as TF
+import test_oracle_operator as TO
+import test_oracle_solve as TS
+
+MUTATIONS = {
+    "projector sign": ("const double sg = (dir > 0) ? -1.0 : 1.0;",
+                       "const double sg = (dir > 0) ? 1.0 : -1.0;",
+                       [lambda: TO.test_free_field_plane_waves(-1, 0.125)]),
+    "antiperiodic sign dropped": ("if (mu == 0 && ((dir > 0 && t == T - 1) || (dir < 0 && t == 0))) ph = (double)bc;",
+                                  "if (mu == 0 && ((dir > 0 && t == T - 1) || (dir < 0 && t == 0))) ph = 1.0;",
+                                  [lambda: TO.test_free_field_plane_waves(-1, 0.125)]),
+    "backward link not daggered": ("W[a][b] = conj(u[3 * b + a]);", "W[a][b] = u[3 * a + b];",
+                                   [lambda: TO.test_gauge_covariance(-1)]),
+    "backward link at x": ("const long sn = (long)cn[0] * L3 + nsp;", "const long sn = s;",
+                           [lambda: TO.test_gauge_covariance(-1)]),
+    "mass normalisation": ("const double mass = 1.0 / (2.0 * kappa);", "const double mass = 1.0 / kappa;",
+                           [lambda: TO.test_free_field_plane_waves(1, 0.125)]),
+    "hop factor": ("res[a][col] -= 0.5 * ph * proj;", "res[a][col] -= ph * proj;",
+                   [lambda: TO.test_free_field_plane_waves(1, 0.125)]),
+    "gamma_k lower block sign": ("GAMMA[k + 1][2 + a][b] = I * sig[k][a][b];",
+                                 "GAMMA[k + 1][2 + a][b] = -I * sig[k][a][b];",
+                                 [TO.test_gamma_basis_and_clifford]),
+    # a wrong search direction only slows the solver down, because convergence is
+    # confirmed on the true residual; a wrong true residual breaks the guarantee
+    "true residual": ("cplx d = b[i] - tmp[i];", "cplx d = b[i] - 0.5 * tmp[i];",
+                      [lambda: TS.test_solver_vs_lu(-1, None, 0)]),
+    "bicgstab residual recursion sign": ("r[i] = s[i] - omega * t[i];", "r[i] = s[i] + omega * t[i];",
+                                         [lambda: TS.test_solver_vs_lu(-1, None, 0)]),
+    "cgnr without adjoint": ("    ora_gamma5(n / 12, in, tmp);\n    op_apply(A, tmp, out);\n    ora_gamma5(n / 12, out, out);",
+                             "    (void)tmp;\n    op_apply(A, in, out);",
+                             [lambda: TS.test_solver_vs_lu(-1, None, 1)]),
+    "correlator time direction": ("const int ts = mod(t_src + t, T);", "const int ts = mod(t_src - t, T);",
+                                  [TS.test_correlator_decays_away_from_source]),
+    "force wrap sign dropped": ("gout[3 * r + k] += coeff * ph * g[r][k];", "gout[3 * r + k] += coeff * g[r][k];",
+                                [lambda: TF.test_force_vs_finite_differences(-1, (5, 5))]),
+    "force outer product transposed": ("g[r][k] += a[s4][r] * conj(Xn[3 * s4 + k]) + Xx[3 * s4 + r] * conj(b[s4][k]);",
+                                       "g[r][k] += a[s4][k] * conj(Xn[3 * s4 + r]) + Xx[3 * s4 + r] * conj(b[s4][k]);",
+                                       [lambda: TF.test_force_vs_finite_differences(0, None)]),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new, pins = MUTATIONS[name]
+    src = open(O.SRC_PATH).read()
+    assert src.count(old) == 1, f"mutation anchor not found once: {name}"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", so, str(path), "-lm"])
+    prev = O.use_library(so)
+    try:
+        caught = 0
+        for pin in pins:
+            try:
+                pin()
+            except AssertionError:
+                caught += 1
+        assert caught > 0, f"planted mistake '{name}' passed every pin"
+    finally:
+        O.restore_library(prev)
