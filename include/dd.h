@@ -1,0 +1,239 @@
+/*
+ * dd.h -- C ABI of the MI355X (gfx950) Wilson-Dirac library for the factorised
+ * (domain-decomposed) quark propagator of M. Ce, L. Giusti, S. Schaefer,
+ * "Domain decomposition and multilevel integration for fermions",
+ * PoS LATTICE2016, arXiv:1612.06424.
+ *
+ * Every compute step runs in hand-written HIP kernels in libdd.so.
+ *
+ * ---------------------------------------------------------------- layouts
+ * Lattice T x L^3, site s = ((t*L + z)*L + y)*L + x (time slowest, x fastest);
+ * mu = 0 is time, mu = 1,2,3 are x,y,z.  Space is periodic; the time edge
+ * (hop between t = T-1 and t = 0) carries the factor time_bc.
+ *
+ * Links U: device array of complex numbers (interleaved re, im), structure of
+ *   arrays [4][9][V]: element (mu, k, s) is entry k = 3*row + col of U_mu(s).
+ *   complex128 for DD_FP64 / DD_MIXED entry points, complex64 for DD_FP32.
+ * Spinor fields: device array [ncol][12][nsite] of complex, component
+ *   c = 3*spin + colour, site fastest.  On a time slab (dd_domain) [t0, t0+nt)
+ *   (mod T) the field is compact: nsite = nt*L^3, local site
+ *   ((t - t0) mod T) * L^3 + spatial index.  On the whole lattice nsite = V.
+ * Propagators: 12 source columns j = 3*spin + colour, i.e. [12][12][nsite].
+ * Gamma matrices: chiral basis gamma_0 = [[0,-1],[-1,0]],
+ *   gamma_k = [[0,-i sigma_k],[i sigma_k,0]] (2x2 blocks), gamma_5 = diag(1,1,-1,-1).
+ *
+ * The operator (Sec. 5 fixes 2 kappa D = 1 - kappa D_hop; the projector form
+ * is the standard Wilson one):
+ *   D psi(x) = psi(x)/(2 kappa) - 1/2 sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+ *                                            + (1+gamma_mu) U_mu(x-mu)^+ psi(x-mu) ].
+ * The Dirichlet slab block D_Lambda = P_Lambda D P_Lambda (Sec. 3, Eq. 10;
+ * Sec. 5: Dirichlet conditions on the block operators) drops every hop that
+ * leaves the slab.
+ *
+ * ---------------------------------------------------------------- contract
+ * Ownership: every field / link pointer is device memory owned by the caller;
+ *   the library never frees or retains it past the call.  The context owns a
+ *   lazily grown device workspace, released by dd_destroy.  Host pointers
+ *   (stats, correlator output) are owned by the caller.
+ * Streams: all work is enqueued on the context's stream.  dd_apply_dirac,
+ *   dd_frontier_hop and dd_link_force return without synchronising; the
+ *   solvers, the propagators and the correlator synchronise before returning.
+ * Errors: a negative dd_status; the message is in dd_last_error(ctx).  No
+ *   exception crosses the ABI.  Arguments are validated: null or misaligned
+ *   (16 B) pointers, pointers not on the context's device, sizes, slabs
+ *   outside [0,T) or, for propagators, slabs that do not partition [0,T).
+ * Threads: one context per host thread.
+ */
+#ifndef DD_H
+#define DD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DD_MAX_RHS 12
+
+typedef struct dd_ctx dd_ctx;
+
+typedef enum {
+    DD_OK = 0,
+    DD_ERR_ARG = -1,         /* invalid argument (pointer, size, slab, parameter) */
+    DD_ERR_HIP = -2,         /* a HIP runtime call failed */
+    DD_ERR_NOMEM = -3,       /* workspace allocation failed */
+    DD_ERR_NOCONV = -4,      /* solver hit max_iter / max_outer; x holds the last iterate */
+    DD_ERR_BREAKDOWN = -5,   /* non-finite values (NaN/Inf) in the iteration */
+    DD_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+} dd_status;
+
+typedef enum {
+    DD_FP64 = 0,   /* complex128 everywhere */
+    DD_FP32 = 1,   /* complex64 (stencil entry points only) */
+    DD_MIXED = 2   /* solves: FP32 inner Krylov iterations, FP64 defect correction */
+} dd_precision;
+
+typedef enum {
+    DD_BICGSTAB = 0,  /* BiCGStab on D_Lambda x = b */
+    DD_CGNR = 1       /* CG on D^+ D x = D^+ b (converges wherever D is invertible) */
+} dd_solver_kind;
+
+typedef struct {
+    int T, L;      /* lattice extent T x L^3, L >= 2, T >= 2 */
+    int time_bc;   /* -1 antiperiodic, +1 periodic, 0 Dirichlet walls at t = 0 and T-1 */
+} dd_lattice;
+
+typedef struct {
+    int t0, nt;    /* time slab [t0, t0+nt) mod T, 1 <= nt < T */
+} dd_domain;
+
+typedef struct {
+    double tol;        /* stop when |b - D x| / |b| <= tol (true residual, FP64) per column */
+    int max_iter;      /* cap on Krylov iterations summed over restarts / inner solves */
+    int prec;          /* DD_FP64 or DD_MIXED */
+    double inner_tol;  /* DD_MIXED: relative residual reduction of each FP32 inner solve */
+    int max_outer;     /* DD_MIXED: cap on defect-correction cycles */
+    int solver;        /* dd_solver_kind */
+    int check_every;   /* iterations between host-side convergence reads (0: library default) */
+} dd_solver_params;
+
+typedef struct {
+    int nrhs;                           /* columns solved */
+    int iters;                          /* Krylov iterations (FP32 inner ones for DD_MIXED) */
+    int outer;                          /* defect-correction cycles (DD_MIXED), else 1 */
+    int restarts;                       /* BiCGStab restarts (breakdown or residual drift) */
+    double true_rel_resid[DD_MAX_RHS];  /* final |b - D x| / |b| per column, FP64 */
+    double ms;                          /* wall time of the call on the host clock */
+} dd_solve_stats;
+
+/* Create a context for lattice *lat on HIP stream `stream` (hipStream_t; NULL =
+ * the default stream) of the current device.  The workspace grows on demand. */
+dd_status dd_create(const dd_lattice* lat, void* stream, dd_ctx** out);
+void dd_destroy(dd_ctx* ctx);
+/* Last error message of this context ("" if none).  Valid until the next call. */
+const char* dd_last_error(const dd_ctx* ctx);
+
+/*
+ * out = D in (dom NULL) or D_Lambda in (slab dom), for nrhs columns.
+ * Sec. 5 (normalisation 2 kappa D = 1 - kappa D_hop), Sec. 3 Eq. 10 (blocks).
+ * prec DD_FP64: U, in, out complex128; DD_FP32: all complex64.  in and out
+ * must not overlap.  1 <= nrhs <= 4*DD_MAX_RHS.  Asynchronous.
+ */
+dd_status dd_apply_dirac(dd_ctx* ctx, const void* U, double kappa, const dd_domain* dom,
+                         int nrhs, const void* in, void* out, int prec);
+
+/*
+ * out += alpha * P_dst D P_src in: the off-diagonal frontier block between two
+ * disjoint slabs (D_dGamma / D_dGamma* of Sec. 3, Eq. 10).  Only time hops
+ * across the shared frontier slices contribute; the half-spinor projected
+ * message is 6 complex numbers per frontier site (Sec. 3.3).  in lives on
+ * src, out on dst (compact layouts).  FP64.  Asynchronous.
+ */
+dd_status dd_frontier_hop(dd_ctx* ctx, const void* U, const dd_domain* dst, const dd_domain* src,
+                          int nrhs, const void* in, void* out, double alpha);
+
+/*
+ * x = D_Lambda^-1 b (dom = slab) or D^-1 b (dom NULL), nrhs <= DD_MAX_RHS
+ * columns solved together (the "solutions of the Dirac equation" of Sec. 5).
+ * U, b, x complex128.  x is output only (the solve starts from zero).
+ * Returns DD_ERR_NOCONV with x = last iterate if a column misses tol.
+ * stats may be NULL.  Synchronises.
+ */
+dd_status dd_block_solve(dd_ctx* ctx, const void* U, double kappa, const dd_domain* dom, int nrhs,
+                         const void* b, void* x, const dd_solver_params* params,
+                         dd_solve_stats* stats);
+
+/*
+ * Factorised point-to-all propagator from the 12 spin-colour point sources at
+ * src = {t, x, y, z} across time slabs doms[0..ndom-1], which partition
+ * [0, T) with src in doms[0]:
+ *   psi_0 = D_L0^-1 eta                                   (Sec. 3.1, Eq. 13)
+ *   psi_k = -D_Lk^-1 sum_{j: d(j) = d(k)-1} D_{Lk,Lj} psi_j (Sec. 3.2, Eq. 14,
+ *            overlap Delta = 0, chained outward by block distance d on the
+ *            graph of non-zero blocks of D)
+ *   S_fact = sum_k psi_k.
+ * S_fact (and S_exact = D^-1 eta if not NULL) are complex128 [12][12][V].
+ * overlap must be 0 (a thicker overlap region is not built).  stats: NULL or
+ * ndom + 1 entries (per slab, then the whole-lattice solve).  Synchronises.
+ */
+dd_status dd_factorized_propagator(dd_ctx* ctx, const void* U, double kappa, const int src[4],
+                                   const dd_domain* doms, int ndom, int overlap,
+                                   const dd_solver_params* params, void* S_fact, void* S_exact,
+                                   dd_solve_stats* stats);
+
+/*
+ * Pion two-point function of a whole-lattice propagator S (complex128
+ * [ncol][12][V]) from a source on time slice t_src (Eq. 4, connected W_Pc):
+ *   C_host[t] = sum_xvec sum_{c,j} |S_cj((t_src + t) mod T, xvec)|^2, t = 0..T-1,
+ * summed in FP64 in a fixed order (bitwise reproducible).  Synchronises.
+ */
+dd_status dd_pion_correlator(dd_ctx* ctx, const void* S, int ncol, int t_src, double* C_host);
+
+/*
+ * Adjoint of x = D_Lambda^-1 b for a real loss with gradient grad_x
+ * (PyTorch convention g = dL/dRe + i dL/dIm): solves D_Lambda^+ lambda = grad_x
+ * (one extra solve, through gamma_5-hermiticity) and returns grad_b = lambda
+ * and grad_U += the link gradient -Re<lambda, dD x> (layout of U, complex128;
+ * links outside the slab or crossing its walls are left untouched).
+ * Synchronises.
+ */
+dd_status dd_block_solve_backward(dd_ctx* ctx, const void* U, double kappa, const dd_domain* dom,
+                                  int nrhs, const void* x, const void* grad_x, void* grad_b,
+                                  void* grad_U, const dd_solver_params* params,
+                                  dd_solve_stats* stats);
+
+/*
+ * Pseudofermion action of one slab and what its force needs:
+ *   Y = D_Lambda^-+ phi, X = D_Lambda^-1 Y, S = phi^+ (D^+ D)^-1 phi = |Y|^2.
+ * phi, X, Y complex128 [nrhs][12][nsite]; *S_host receives the sum over
+ * columns.  Synchronises.
+ */
+dd_status dd_domain_action(dd_ctx* ctx, const void* U, double kappa, const dd_domain* dom, int nrhs,
+                           const void* phi, void* X, void* Y, double* S_host,
+                           const dd_solver_params* params, dd_solve_stats* stats);
+
+/*
+ * grad_U += coeff * g with g the link gradient of F(U) = -2 Re<Y, D_Lambda(U) X>
+ * at fixed X, Y (PyTorch convention), per link
+ *   g_mu(x) = ph sum_spin [ ((1-gamma_mu) Y(x)) X(x+mu)^+ + X(x) ((1+gamma_mu) Y(x+mu))^+ ]
+ * (ph = time_bc on the time-edge link).  For S = |Y|^2 of dd_domain_action the
+ * force is coeff = 1.  X, Y complex128 [nrhs][12][nsite]; grad_U like U.
+ * Asynchronous.
+ */
+dd_status dd_link_force(dd_ctx* ctx, const dd_domain* dom, int nrhs, const void* X, const void* Y,
+                        double coeff, void* grad_U);
+
+/* One independent lattice of a batched solve (time_bc is normally 0: a
+ * Dirichlet domain standing on its own). */
+typedef struct {
+    dd_lattice lat;
+    const void* U;   /* complex128 [4][9][V_i] */
+    double kappa;
+    int nrhs;        /* <= DD_MAX_RHS */
+    const void* b;   /* complex128 [nrhs][12][V_i] */
+    void* x;         /* complex128 [nrhs][12][V_i], output */
+} dd_batch_item;
+
+/*
+ * Solve every item of an uneven batch of independent domains (prec DD_MIXED
+ * or DD_FP64, BiCGStab), all domains advancing together in shared launches
+ * (each launch covers every active domain), with the FP32 inner iterations
+ * captured once in a HIP graph and replayed.  stats: NULL or n entries.
+ * Synchronises.
+ */
+dd_status dd_block_solve_batched(dd_ctx* ctx, int n, const dd_batch_item* items,
+                                 const dd_solver_params* params, dd_solve_stats* stats);
+
+/*
+ * Kernel timing on the context stream.  With enable != 0 every stencil
+ * launch made by the library is bracketed by HIP events; dd_kernel_timing
+ * returns the summed milliseconds, launch count and algorithmic bytes
+ * (V*(48*ncol + 72)*sizeof(real) per launch) since the last reset.
+ * kind: 0 = FP64 stencil, 1 = FP32 stencil.
+ */
+dd_status dd_set_kernel_timing(dd_ctx* ctx, int enable);
+dd_status dd_kernel_timing(dd_ctx* ctx, int kind, double* ms, long long* launches, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DD_H */

@@ -1,0 +1,511 @@
+// abi.hip -- the extern "C" entry points declared in dd.h: argument
+// validation, workspace management, and the orchestration of the hot path
+// (stencil, solves, factorised propagator, correlator, adjoint) on the
+// context's stream.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <vector>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+dd_status fail(dd_ctx* c, dd_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+dd_status hip_fail(dd_ctx* c, hipError_t e, const char* what) {
+    return fail(c, DD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* workspace(dd_ctx* c, Slot s, size_t bytes, dd_status* st) {
+    Buffer& b = c->ws[s];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return b.ptr;
+    if (b.ptr) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        *st = fail(c, DD_ERR_NOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        return nullptr;
+    }
+    b.bytes = bytes;
+    return b.ptr;
+}
+
+Geo make_geo(const dd_lattice& lat, const dd_domain* dom) {
+    Geo g;
+    g.L = lat.L;
+    g.L2 = lat.L * lat.L;
+    g.L3 = g.L2 * lat.L;
+    g.T = lat.T;
+    g.vlink = lat.T * g.L3;
+    g.bc = lat.time_bc;
+    if (dom == nullptr) {
+        g.t0 = 0;
+        g.nt = lat.T;
+        g.whole = 1;
+    } else {
+        g.t0 = dom->t0;
+        g.nt = dom->nt;
+        g.whole = 0;
+    }
+    g.nsite = g.nt * g.L3;
+    return g;
+}
+
+// ---------------------------------------------------------------- timing
+void timing_begin(dd_ctx* c, hipEvent_t* ev) {
+    hipEvent_t a;
+    if (!c->event_pool.empty()) {
+        a = c->event_pool.back();
+        c->event_pool.pop_back();
+    } else if (hipEventCreate(&a) != hipSuccess) {
+        *ev = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, c->stream);
+    *ev = a;
+}
+
+void timing_end(dd_ctx* c, hipEvent_t start, int kind, double bytes) {
+    if (start == nullptr) return;
+    hipEvent_t b;
+    if (!c->event_pool.empty()) {
+        b = c->event_pool.back();
+        c->event_pool.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+        c->event_pool.push_back(start);
+        return;
+    }
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back(TimedLaunch{start, b, kind, bytes});
+    if (c->pending.size() >= 4096) timing_harvest(c);
+}
+
+void timing_harvest(dd_ctx* c) {
+    if (c->pending.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& t : c->pending) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            c->t_ms[t.kind] += ms;
+            c->t_count[t.kind] += 1;
+            c->t_bytes[t.kind] += t.bytes;
+        }
+        c->event_pool.push_back(t.start);
+        c->event_pool.push_back(t.stop);
+    }
+    c->pending.clear();
+}
+
+}  // namespace dd
+
+using namespace dd;
+
+namespace {
+
+bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align) {
+    if (p == nullptr || (reinterpret_cast<uintptr_t>(p) % align) != 0) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type != hipMemoryTypeDevice || a.device != c->device) return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) == hipSuccess) {
+        const char* lo = (const char*)base;
+        const char* q = (const char*)p;
+        if (q + bytes > lo + size) return false;
+    } else {
+        (void)hipGetLastError();
+    }
+    return true;
+}
+
+#define CHECK_PTR(c, p, bytes, align, name)                                                         \
+    do {                                                                                             \
+        if (!on_device(c, p, bytes, align))                                                          \
+            return fail(c, DD_ERR_ARG, std::string(name) +                                          \
+                                           ": null, misaligned, too small or not device memory of " \
+                                           "the context's device");                                 \
+    } while (0)
+
+dd_status check_dom(dd_ctx* c, const dd_domain* dom) {
+    if (dom == nullptr) return DD_OK;
+    if (dom->t0 < 0 || dom->t0 >= c->lat.T || dom->nt < 1 || dom->nt >= c->lat.T)
+        return fail(c, DD_ERR_ARG, "slab must satisfy 0 <= t0 < T and 1 <= nt < T");
+    return DD_OK;
+}
+
+dd_status check_params(dd_ctx* c, const dd_solver_params* p) {
+    if (p == nullptr) return fail(c, DD_ERR_ARG, "solver params are NULL");
+    if (!(p->tol > 0) || p->tol >= 1 || p->max_iter < 1)
+        return fail(c, DD_ERR_ARG, "need 0 < tol < 1 and max_iter >= 1");
+    if (p->prec != DD_FP64 && p->prec != DD_MIXED) return fail(c, DD_ERR_ARG, "solver prec must be DD_FP64 or DD_MIXED");
+    if (p->prec == DD_MIXED && (!(p->inner_tol > 0) || p->inner_tol >= 1 || p->max_outer < 1))
+        return fail(c, DD_ERR_ARG, "DD_MIXED needs 0 < inner_tol < 1 and max_outer >= 1");
+    if (p->solver != DD_BICGSTAB && p->solver != DD_CGNR) return fail(c, DD_ERR_ARG, "unknown solver kind");
+    return DD_OK;
+}
+
+dd_status check_kappa(dd_ctx* c, double kappa) {
+    if (!(kappa > 0) || !std::isfinite(kappa)) return fail(c, DD_ERR_ARG, "kappa must be positive and finite");
+    return DD_OK;
+}
+
+size_t vlink(const dd_lattice& l) { return (size_t)l.T * l.L * l.L * l.L; }
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_create(const dd_lattice* lat, void* stream, dd_ctx** out) {
+    if (out == nullptr) return DD_ERR_ARG;
+    *out = nullptr;
+    if (lat == nullptr || lat->T < 2 || lat->L < 2 || (lat->time_bc != -1 && lat->time_bc != 0 && lat->time_bc != 1))
+        return DD_ERR_ARG;
+    // index arithmetic is 32-bit: 144 * V complex numbers must fit
+    if ((double)lat->T * lat->L * lat->L * lat->L * 144.0 >= 2147483647.0) return DD_ERR_ARG;
+    dd_ctx* c = new (std::nothrow) dd_ctx();
+    if (c == nullptr) return DD_ERR_NOMEM;
+    c->lat = *lat;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return DD_ERR_HIP;
+    }
+    c->ws.resize(W_NSLOTS);
+    *out = c;
+    return DD_OK;
+}
+
+void dd_destroy(dd_ctx* c) {
+    if (c == nullptr) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& b : c->ws)
+        if (b.ptr) (void)hipFree(b.ptr);
+    for (auto& t : c->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->host_state) (void)hipHostFree(c->host_state);
+    if (c->host_dots) (void)hipHostFree(c->host_dots);
+    delete c;
+}
+
+const char* dd_last_error(const dd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+dd_status dd_apply_dirac(dd_ctx* c, const void* U, double kappa, const dd_domain* dom, int nrhs, const void* in,
+                         void* out, int prec) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e = check_dom(c, dom);
+    if (e != DD_OK) return e;
+    if ((e = check_kappa(c, kappa)) != DD_OK) return e;
+    if (nrhs < 1 || nrhs > 4 * DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs out of range");
+    if (prec != DD_FP64 && prec != DD_FP32) return fail(c, DD_ERR_ARG, "prec must be DD_FP64 or DD_FP32");
+    const Geo g = make_geo(c->lat, dom);
+    const size_t cs = prec == DD_FP64 ? 16 : 8;
+    const size_t fbytes = (size_t)nrhs * 12 * g.nsite * cs;
+    CHECK_PTR(c, U, 36 * vlink(c->lat) * cs, cs, "U");
+    CHECK_PTR(c, in, fbytes, cs, "in");
+    CHECK_PTR(c, out, fbytes, cs, "out");
+    const char* a = (const char*)in;
+    const char* b = (const char*)out;
+    if (a < b + fbytes && b < a + fbytes) return fail(c, DD_ERR_ARG, "in and out overlap");
+    if (prec == DD_FP64)
+        launch_dslash<double>(c, g, (const cpx<double>*)U, kappa, 0, EPI_STORE, (const cpx<double>*)in,
+                              (cpx<double>*)out, nullptr, nrhs, nullptr, nullptr);
+    else
+        launch_dslash<float>(c, g, (const cpx<float>*)U, kappa, 0, EPI_STORE, (const cpx<float>*)in,
+                             (cpx<float>*)out, nullptr, nrhs, nullptr, nullptr);
+    DD_HIP(c, hipGetLastError());
+    return DD_OK;
+}
+
+dd_status dd_frontier_hop(dd_ctx* c, const void* U, const dd_domain* dst, const dd_domain* src, int nrhs,
+                          const void* in, void* out, double alpha) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (dst == nullptr || src == nullptr) return fail(c, DD_ERR_ARG, "frontier hop needs two slabs");
+    dd_status e;
+    if ((e = check_dom(c, dst)) != DD_OK || (e = check_dom(c, src)) != DD_OK) return e;
+    if (nrhs < 1 || nrhs > 4 * DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs out of range");
+    const int T = c->lat.T;
+    for (int k = 0; k < dst->nt; k++) {
+        const int t = (dst->t0 + k) % T;
+        if (((t - src->t0) % T + T) % T < src->nt) return fail(c, DD_ERR_ARG, "frontier hop slabs overlap");
+    }
+    const int L3 = c->lat.L * c->lat.L * c->lat.L;
+    CHECK_PTR(c, U, 36 * vlink(c->lat) * 16, 16, "U");
+    CHECK_PTR(c, in, (size_t)nrhs * 12 * src->nt * L3 * 16, 16, "in");
+    CHECK_PTR(c, out, (size_t)nrhs * 12 * dst->nt * L3 * 16, 16, "out");
+    launch_frontier(c, c->lat, (const cpx<double>*)U, *dst, *src, nrhs, (const cpx<double>*)in, (cpx<double>*)out,
+                    alpha);
+    DD_HIP(c, hipGetLastError());
+    return DD_OK;
+}
+
+dd_status dd_block_solve(dd_ctx* c, const void* U, double kappa, const dd_domain* dom, int nrhs, const void* b,
+                         void* x, const dd_solver_params* p, dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_dom(c, dom)) != DD_OK || (e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK)
+        return e;
+    if (nrhs < 1 || nrhs > DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs must be in [1, 12]");
+    const Geo g = make_geo(c->lat, dom);
+    const size_t fbytes = (size_t)nrhs * 12 * g.nsite * 16;
+    CHECK_PTR(c, U, 36 * vlink(c->lat) * 16, 16, "U");
+    CHECK_PTR(c, b, fbytes, 16, "b");
+    CHECK_PTR(c, x, fbytes, 16, "x");
+    return solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)b, (cpx<double>*)x, *p, stats, 0);
+}
+
+dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const int src[4], const dd_domain* doms,
+                                   int ndom, int overlap, const dd_solver_params* p, void* S_fact, void* S_exact,
+                                   dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK) return e;
+    if (overlap != 0) return fail(c, DD_ERR_UNSUPPORTED, "overlap regions (Delta > 0) are not built");
+    if (src == nullptr || doms == nullptr || ndom < 2) return fail(c, DD_ERR_ARG, "need a source and >= 2 slabs");
+    const dd_lattice& lat = c->lat;
+    const int T = lat.T, L = lat.L, L3 = L * L * L;
+    if (src[0] < 0 || src[0] >= T || src[1] < 0 || src[1] >= L || src[2] < 0 || src[2] >= L || src[3] < 0 ||
+        src[3] >= L)
+        return fail(c, DD_ERR_ARG, "source outside the lattice");
+    // the slabs must partition [0, T)
+    std::vector<int> owner(T, -1);
+    for (int k = 0; k < ndom; k++) {
+        if ((e = check_dom(c, &doms[k])) != DD_OK) return e;
+        for (int j = 0; j < doms[k].nt; j++) {
+            const int t = (doms[k].t0 + j) % T;
+            if (owner[t] != -1) return fail(c, DD_ERR_ARG, "slabs overlap");
+            owner[t] = k;
+        }
+    }
+    for (int t = 0; t < T; t++)
+        if (owner[t] == -1) return fail(c, DD_ERR_ARG, "slabs do not cover [0, T)");
+    if (owner[src[0]] != 0) return fail(c, DD_ERR_ARG, "the source must lie in doms[0]");
+    // block distances on the graph of non-zero blocks of D (time hops between
+    // consecutive slabs; across the time edge only if time_bc != 0)
+    std::vector<std::vector<int>> adj(ndom);
+    for (int t = 0; t < T; t++) {
+        const int tn = (t + 1) % T;
+        if (tn == 0 && lat.time_bc == 0) continue;
+        const int a = owner[t], b = owner[tn];
+        if (a != b) {
+            if (std::find(adj[a].begin(), adj[a].end(), b) == adj[a].end()) adj[a].push_back(b);
+            if (std::find(adj[b].begin(), adj[b].end(), a) == adj[b].end()) adj[b].push_back(a);
+        }
+    }
+    std::vector<int> dist(ndom, -1), order;
+    std::deque<int> q;
+    dist[0] = 0;
+    q.push_back(0);
+    while (!q.empty()) {
+        const int a = q.front();
+        q.pop_front();
+        order.push_back(a);
+        for (int b : adj[a])
+            if (dist[b] < 0) {
+                dist[b] = dist[a] + 1;
+                q.push_back(b);
+            }
+    }
+    if ((int)order.size() != ndom) return fail(c, DD_ERR_ARG, "slabs are not connected by D");
+
+    const size_t V = vlink(lat);
+    CHECK_PTR(c, U, 36 * V * 16, 16, "U");
+    CHECK_PTR(c, S_fact, 144 * V * 16, 16, "S_fact");
+    if (S_exact) CHECK_PTR(c, S_exact, 144 * V * 16, 16, "S_exact");
+
+    // per-slab solutions psi_k, stored compactly one after the other
+    std::vector<size_t> base(ndom);
+    size_t tot = 0;
+    for (int k = 0; k < ndom; k++) {
+        base[k] = tot;
+        tot += (size_t)144 * doms[k].nt * L3;
+    }
+    cpx<double>* psi = (cpx<double>*)workspace(c, W_AUX2, tot * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    size_t maxslab = 0;
+    for (int k = 0; k < ndom; k++) maxslab = std::max(maxslab, (size_t)144 * doms[k].nt * L3);
+    cpx<double>* rhs = (cpx<double>*)workspace(c, W_AUX3, std::max(maxslab, S_exact ? 144 * V : 0) * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+
+    const int ssp = (src[3] * L + src[2]) * L + src[1];
+    dd_status worst = DD_OK;
+    for (int k : order) {
+        const dd_domain& dk = doms[k];
+        const int nsite = dk.nt * L3;
+        if (dist[k] == 0) {
+            const int tl = ((src[0] - dk.t0) % T + T) % T;
+            launch_point_source(c, nsite, tl * L3 + ssp, rhs);
+        } else {
+            launch_zero<double>(c, (size_t)144 * nsite, rhs);
+            for (int j = 0; j < ndom; j++)
+                if (dist[j] == dist[k] - 1 && std::find(adj[k].begin(), adj[k].end(), j) != adj[k].end())
+                    launch_frontier(c, lat, (const cpx<double>*)U, dk, doms[j], 12, psi + base[j], rhs, -1.0);
+        }
+        DD_HIP(c, hipGetLastError());
+        const Geo g = make_geo(lat, &dk);
+        e = solve(c, (const cpx<double>*)U, kappa, g, 12, rhs, psi + base[k], *p, stats ? &stats[k] : nullptr, 0);
+        if (e != DD_OK && e != DD_ERR_NOCONV) return e;
+        if (e == DD_ERR_NOCONV) worst = e;
+        launch_slab_scatter(c, lat, dk, 12, psi + base[k], (cpx<double>*)S_fact);
+    }
+    if (S_exact) {
+        launch_point_source(c, (int)V, src[0] * L3 + ssp, rhs);
+        const Geo g = make_geo(lat, nullptr);
+        e = solve(c, (const cpx<double>*)U, kappa, g, 12, rhs, (cpx<double>*)S_exact, *p,
+                  stats ? &stats[ndom] : nullptr, 0);
+        if (e != DD_OK && e != DD_ERR_NOCONV) return e;
+        if (e == DD_ERR_NOCONV) worst = e;
+    }
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    if (worst != DD_OK) return fail(c, worst, "a slab or whole-lattice solve did not converge: " + c->err);
+    return DD_OK;
+}
+
+dd_status dd_pion_correlator(dd_ctx* c, const void* S, int ncol, int t_src, double* C_host) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (ncol < 1 || ncol > 4 * DD_MAX_RHS) return fail(c, DD_ERR_ARG, "ncol out of range");
+    if (t_src < 0 || t_src >= c->lat.T) return fail(c, DD_ERR_ARG, "t_src outside [0, T)");
+    if (C_host == nullptr) return fail(c, DD_ERR_ARG, "C_host is NULL");
+    const size_t V = vlink(c->lat);
+    CHECK_PTR(c, S, (size_t)ncol * 12 * V * 16, 16, "S");
+    dd_status e = DD_OK;
+    double* partial = (double*)workspace(c, W_PART, (size_t)c->lat.T * 12 * ncol * 3 * sizeof(double), &e);
+    if (e != DD_OK) return e;
+    double* Cd = (double*)workspace(c, W_DOTS, (size_t)c->lat.T * sizeof(double), &e);
+    if (e != DD_OK) return e;
+    launch_pion(c, c->lat, ncol, (const cpx<double>*)S, t_src, partial, Cd);
+    DD_HIP(c, hipGetLastError());
+    DD_HIP(c, hipMemcpyAsync(C_host, Cd, sizeof(double) * c->lat.T, hipMemcpyDeviceToHost, c->stream));
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    return DD_OK;
+}
+
+dd_status dd_block_solve_backward(dd_ctx* c, const void* U, double kappa, const dd_domain* dom, int nrhs,
+                                  const void* x, const void* grad_x, void* grad_b, void* grad_U,
+                                  const dd_solver_params* p, dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_dom(c, dom)) != DD_OK || (e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK)
+        return e;
+    if (nrhs < 1 || nrhs > DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs must be in [1, 12]");
+    const Geo g = make_geo(c->lat, dom);
+    const size_t fbytes = (size_t)nrhs * 12 * g.nsite * 16;
+    CHECK_PTR(c, U, 36 * vlink(c->lat) * 16, 16, "U");
+    CHECK_PTR(c, x, fbytes, 16, "x");
+    CHECK_PTR(c, grad_x, fbytes, 16, "grad_x");
+    CHECK_PTR(c, grad_b, fbytes, 16, "grad_b");
+    if (grad_U) CHECK_PTR(c, grad_U, 36 * vlink(c->lat) * 16, 16, "grad_U");
+    // D^+ lambda = grad_x
+    e = solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)grad_x, (cpx<double>*)grad_b, *p, stats,
+              1);
+    if (e != DD_OK) return e;
+    // dL = -Re<lambda, dD x> = 1/2 d(-2 Re<lambda, D x>)
+    if (grad_U)
+        launch_link_force(c, g, nrhs, (const cpx<double>*)x, (const cpx<double>*)grad_b, 0.5, (cpx<double>*)grad_U);
+    DD_HIP(c, hipGetLastError());
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    return DD_OK;
+}
+
+dd_status dd_domain_action(dd_ctx* c, const void* U, double kappa, const dd_domain* dom, int nrhs, const void* phi,
+                           void* X, void* Y, double* S_host, const dd_solver_params* p, dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_dom(c, dom)) != DD_OK || (e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK)
+        return e;
+    if (nrhs < 1 || nrhs > DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs must be in [1, 12]");
+    const Geo g = make_geo(c->lat, dom);
+    const size_t fbytes = (size_t)nrhs * 12 * g.nsite * 16;
+    CHECK_PTR(c, U, 36 * vlink(c->lat) * 16, 16, "U");
+    CHECK_PTR(c, phi, fbytes, 16, "phi");
+    CHECK_PTR(c, X, fbytes, 16, "X");
+    CHECK_PTR(c, Y, fbytes, 16, "Y");
+    dd_solve_stats s2{};
+    e = solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)phi, (cpx<double>*)Y, *p, stats, 1);
+    if (e != DD_OK) return e;
+    e = solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)Y, (cpx<double>*)X, *p, &s2, 0);
+    if (stats) {
+        stats->iters += s2.iters;
+        stats->outer += s2.outer;
+        stats->restarts += s2.restarts;
+        stats->ms += s2.ms;
+        for (int j = 0; j < nrhs; j++) stats->true_rel_resid[j] = std::max(stats->true_rel_resid[j], s2.true_rel_resid[j]);
+    }
+    if (e != DD_OK) return e;
+    if (S_host) {
+        const int n = 12 * g.nsite;
+        double* partial = (double*)workspace(c, W_PART, (size_t)nrhs * ((n + kBlock - 1) / kBlock) * 3 * sizeof(double), &e);
+        if (e != DD_OK) return e;
+        double* dots = (double*)workspace(c, W_DOTS, sizeof(double) * 3 * nrhs, &e);
+        if (e != DD_OK) return e;
+        launch_norm2<double>(c, n, nrhs, (const cpx<double>*)Y, partial);
+        launch_finalize(c, FIN_STORE, nrhs, (n + kBlock - 1) / kBlock, partial, nullptr, dots);
+        DD_HIP(c, hipGetLastError());
+        std::vector<double> h(3 * nrhs);
+        DD_HIP(c, hipMemcpyAsync(h.data(), dots, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, c->stream));
+        DD_HIP(c, hipStreamSynchronize(c->stream));
+        double s = 0;
+        for (int j = 0; j < nrhs; j++) s += h[3 * j];
+        *S_host = s;
+    }
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    return DD_OK;
+}
+
+dd_status dd_link_force(dd_ctx* c, const dd_domain* dom, int nrhs, const void* X, const void* Y, double coeff,
+                        void* grad_U) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_dom(c, dom)) != DD_OK) return e;
+    if (nrhs < 1 || nrhs > 4 * DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs out of range");
+    const Geo g = make_geo(c->lat, dom);
+    const size_t fbytes = (size_t)nrhs * 12 * g.nsite * 16;
+    CHECK_PTR(c, X, fbytes, 16, "X");
+    CHECK_PTR(c, Y, fbytes, 16, "Y");
+    CHECK_PTR(c, grad_U, 36 * vlink(c->lat) * 16, 16, "grad_U");
+    launch_link_force(c, g, nrhs, (const cpx<double>*)X, (const cpx<double>*)Y, coeff, (cpx<double>*)grad_U);
+    DD_HIP(c, hipGetLastError());
+    return DD_OK;
+}
+
+dd_status dd_set_kernel_timing(dd_ctx* c, int enable) {
+    if (c == nullptr) return DD_ERR_ARG;
+    timing_harvest(c);
+    c->timing = enable ? 1 : 0;
+    c->t_ms[0] = c->t_ms[1] = 0;
+    c->t_count[0] = c->t_count[1] = 0;
+    c->t_bytes[0] = c->t_bytes[1] = 0;
+    return DD_OK;
+}
+
+dd_status dd_kernel_timing(dd_ctx* c, int kind, double* ms, long long* launches, double* bytes) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (kind < 0 || kind > 1) return fail(c, DD_ERR_ARG, "kind must be 0 (FP64) or 1 (FP32)");
+    timing_harvest(c);
+    if (ms) *ms = c->t_ms[kind];
+    if (launches) *launches = c->t_count[kind];
+    if (bytes) *bytes = c->t_bytes[kind];
+    return DD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+// dd_internal.h -- shared definitions of the HIP library (kernels, solvers, ABI).
+// gfx950 only: 64-lane wavefronts, 256 compute units in 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+
+namespace dd {
+
+constexpr int kBlock = 256;   // threads per workgroup for site-parallel kernels
+constexpr int kWave = 64;     // CDNA wavefront
+constexpr int kNumXcd = 8;    // MI355X: workgroups are dealt round-robin over 8 XCDs
+
+// Complex number with interleaved (re, im); 16-byte aligned for FP64 so that a
+// component load is one dwordx4, 8-byte aligned (dwordx2) for FP32.
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ inline cpx<R> mk(R a, R b) { return cpx<R>{a, b}; }
+template <typename R>
+__device__ inline cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ inline cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ inline cpx<R> operator-(cpx<R> a) { return {-a.re, -a.im}; }
+template <typename R>
+__device__ inline cpx<R> operator*(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ inline cpx<R> operator*(R s, cpx<R> a) { return {s * a.re, s * a.im}; }
+// conj(a) * b
+template <typename R>
+__device__ inline cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a
+template <typename R>
+__device__ inline cpx<R> imul(cpx<R> a) { return {-a.im, a.re}; }
+
+// Geometry of one field: a time slab [t0, t0+nt) of a T x L^3 lattice, or the
+// whole lattice (whole = 1, t0 = 0, nt = T).  Field sites are local, links global.
+struct Geo {
+    int L, L2, L3;   // L, L^2, L^3
+    int T;           // lattice time extent (link array covers T*L3 sites)
+    int t0, nt;      // slab
+    int nsite;       // nt * L3
+    int whole;       // 1: hops across the slab's time ends wrap (whole lattice)
+    int bc;          // time-edge factor for wrapping hops: -1, 0 (dropped), +1
+    int vlink;       // T * L3
+};
+
+// XCD-aware workgroup index: the hardware deals consecutive workgroup ids to
+// the 8 XCDs round-robin; remap so that each XCD (own L2) walks a contiguous
+// range of logical blocks, keeping stencil neighbours and shared links in one L2.
+__device__ inline int xcd_remap(int bid, int nblk) {
+    const int q = nblk / kNumXcd, r = nblk % kNumXcd;
+    const int xcd = bid % kNumXcd, loc = bid / kNumXcd;
+    return (xcd < r) ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
+}
+
+// ------------------------------------------------------------------ solver scalars
+// Per-column scalars of the Krylov iterations, kept on the device so that the
+// iteration runs without host round trips.
+struct ColState {
+    double rho_re, rho_im;      // <r^, r>
+    double alpha_re, alpha_im;
+    double omega_re, omega_im;
+    double beta_re, beta_im;
+    double rr;                  // |r|^2 (recursive)
+    double bb;                  // |b|^2 of the current system
+    double stop2;               // stop when rr <= stop2
+    double zz;                  // CGNR: |D^+ r|^2
+    double rh2;                 // |r^|^2 of the shadow residual
+    int active;                 // 1 while iterating
+    int iters;                  // iterations done by this column
+    int breakdown;              // 1: stalled (rho, <r^,v> or omega vanished), 2: non-finite
+    int pad;
+};
+
+// ------------------------------------------------------------------ context
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct TimedLaunch {
+    hipEvent_t start, stop;
+    int kind;
+    double bytes;
+};
+
+}  // namespace dd
+
+struct dd_ctx {
+    dd_lattice lat;
+    hipStream_t stream;
+    int device;
+    std::string err;
+    std::vector<dd::Buffer> ws;  // workspace slots, grown on demand
+    // kernel timing
+    int timing = 0;
+    std::vector<dd::TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    double t_ms[2] = {0, 0};
+    long long t_count[2] = {0, 0};
+    double t_bytes[2] = {0, 0};
+    // pinned host mirrors of per-column state and of small reductions
+    dd::ColState* host_state = nullptr;
+    double* host_dots = nullptr;
+    int host_n = 0;
+};
+
+namespace dd {
+
+// Workspace slots (each is one lazily grown device allocation).
+enum Slot {
+    W_R = 0, W_RH, W_P, W_V, W_S, W_T,          // Krylov vectors, FP64
+    W_R32, W_RH32, W_P32, W_V32, W_S32, W_T32,  // Krylov vectors, FP32
+    W_B32, W_X32, W_U32, W_RES64,
+    W_PART, W_STATE, W_STATE32, W_DOTS,
+    W_AUX0, W_AUX1, W_AUX2, W_AUX3, W_AUX4,
+    W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
+    W_NSLOTS
+};
+
+dd_status fail(dd_ctx* c, dd_status st, const std::string& msg);
+dd_status hip_fail(dd_ctx* c, hipError_t e, const char* what);
+void* workspace(dd_ctx* c, Slot s, size_t bytes, dd_status* st);
+
+#define DD_HIP(ctx, call)                                         \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::dd::hip_fail(ctx, e_, #call); \
+    } while (0)
+
+Geo make_geo(const dd_lattice& lat, const dd_domain* dom);
+
+// ---------------------------------------------------------------- stencil launchers
+// Epilogues fused into the stencil (one pass over the output):
+enum Epi {
+    EPI_STORE = 0,   // out = M in
+    EPI_DOT_AUX,     // out = M in; partial <aux, out>
+    EPI_TS,          // out = M in; partials <out, in>, |out|^2
+    EPI_RESID,       // out = aux - M in; partial |out|^2
+    EPI_NORM         // out = M in; partial |out|^2
+};
+
+// M = D (dag = 0) or D^+ = gamma5 D gamma5 (dag = 1) on the field geometry g.
+// partial: [ncol][nsb][3] doubles (nsb = site blocks); active: nullable per-column mask.
+template <typename R>
+void launch_dslash(dd_ctx* c, const Geo& g, const cpx<R>* U, double kappa, int dag, int epi,
+                   const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol,
+                   double* partial, const ColState* state);
+
+inline int site_blocks(int nsite) { return (nsite + kBlock - 1) / kBlock; }
+
+// ---------------------------------------------------------------- BLAS / reductions
+template <typename R>
+void launch_bicg_p(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* p, const cpx<R>* v,
+                   const ColState* st);
+template <typename R>
+void launch_bicg_s(dd_ctx* c, int n, int ncol, const cpx<R>* r, const cpx<R>* v, cpx<R>* s,
+                   const ColState* st);
+template <typename R>
+void launch_bicg_xr(dd_ctx* c, int n, int ncol, cpx<R>* x, cpx<R>* r, const cpx<R>* p,
+                    const cpx<R>* s, const cpx<R>* t, const cpx<R>* rh, double* partial,
+                    const ColState* st);
+template <typename R>
+void launch_cg_xr(dd_ctx* c, int n, int ncol, cpx<R>* x, cpx<R>* r, const cpx<R>* p,
+                  const cpx<R>* w, double* partial, const ColState* st);
+template <typename R>
+void launch_cg_p(dd_ctx* c, int n, int ncol, cpx<R>* p, const cpx<R>* z, const ColState* st);
+template <typename R>
+void launch_norm2(dd_ctx* c, int n, int ncol, const cpx<R>* a, double* partial);
+
+// finalize kinds (one block per column reduces its partials, then updates scalars)
+enum Fin {
+    FIN_ALPHA = 0,   // dots = <r^,v>        -> alpha = rho / <r^,v>
+    FIN_OMEGA,       // dots = <t,s>, |t|^2  -> omega
+    FIN_RHO,         // dots = <r^,r>, |r|^2 -> beta, rho, rr, convergence
+    FIN_CG_ALPHA,    // dots = |w|^2         -> alpha = zz / |w|^2
+    FIN_CG_RR,       // dots = |r|^2         -> rr, convergence
+    FIN_CG_BETA,     // dots = |z|^2         -> beta = zz_new / zz
+    FIN_CG_ZZ,       // dots = |z|^2         -> zz (start of a CG cycle)
+    FIN_INIT,        // dots = |r|^2 of a fresh residual -> rho = rr = rh2 = |r|^2,
+                     //   stop2 *= |r|^2, alpha = omega = 1, beta = 0, iters = 0
+    FIN_STORE        // dots -> out[col*3 + k] (plain reduction)
+};
+void launch_finalize(dd_ctx* c, int fin, int ncol, int nsb, const double* partial, ColState* st,
+                     double* out);
+
+template <typename R>
+void launch_copy_cols(dd_ctx* c, int n, int ncol, const cpx<R>* src, cpx<R>* dst, const ColState* st);
+void launch_to_f32_scaled(dd_ctx* c, int n, int ncol, const cpx<double>* src, cpx<float>* dst,
+                          const double* scale, const ColState* st);
+void launch_add_f32_scaled(dd_ctx* c, int n, int ncol, cpx<double>* x, const cpx<float>* e,
+                           const double* scale, const ColState* st);
+void launch_links_to_f32(dd_ctx* c, size_t n, const cpx<double>* src, cpx<float>* dst);
+template <typename R>
+void launch_gamma5(dd_ctx* c, int n, int ncol, const cpx<R>* in, cpx<R>* out);
+template <typename R>
+void launch_zero(dd_ctx* c, size_t n, cpx<R>* a);
+
+// frontier: out(dst) += alpha * P_dst D P_src in(src), time hops across the frontier
+void launch_frontier(dd_ctx* c, const dd_lattice& lat, const cpx<double>* U, const dd_domain& dst,
+                     const dd_domain& src, int ncol, const cpx<double>* in, cpx<double>* out,
+                     double alpha);
+// copy a compact slab field into / out of a whole-lattice field
+void launch_slab_scatter(dd_ctx* c, const dd_lattice& lat, const dd_domain& dom, int ncol,
+                         const cpx<double>* part, cpx<double>* whole);
+void launch_slab_gather(dd_ctx* c, const dd_lattice& lat, const dd_domain& dom, int ncol,
+                        const cpx<double>* whole, cpx<double>* part);
+void launch_point_source(dd_ctx* c, int nsite, int site, cpx<double>* eta);
+// pion correlator: per-slice partial sums then fixed-order reduction
+void launch_pion(dd_ctx* c, const dd_lattice& lat, int ncol, const cpx<double>* S, int t_src,
+                 double* partial, double* C);
+// link force: grad_U += coeff * g(X, Y) on the slab geometry
+void launch_link_force(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* X,
+                       const cpx<double>* Y, double coeff, cpx<double>* grad);
+
+// ---------------------------------------------------------------- timing
+void timing_begin(dd_ctx* c, hipEvent_t* ev);
+void timing_end(dd_ctx* c, hipEvent_t ev, int kind, double bytes);
+void timing_harvest(dd_ctx* c);
+
+// ---------------------------------------------------------------- solver
+dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol,
+                const cpx<double>* b, cpx<double>* x, const dd_solver_params& p,
+                dd_solve_stats* stats, int dag);
+
+}  // namespace dd

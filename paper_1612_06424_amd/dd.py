@@ -1,0 +1,339 @@
+"""Thin Python binding of libdd.so (C ABI in include/dd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libdd.so.  Fields are torch tensors on the GPU in the library's
+layouts (see include/dd.h):
+  links   complex128 / complex64  (4, 9, V)            [mu][3*row+col][site]
+  fields  complex128 / complex64  (ncol, 12, nsite)    [col][3*spin+colour][site]
+``pack_links`` / ``pack_field`` / ``unpack_field`` convert from the natural
+site-major arrays (V, 4, 3, 3) and (ncol, nsite, 12).
+
+Importing this module loads libdd.so and raises ImportError when it has not
+been built (``python -m paper_1612_06424_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1612_06424_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+DD_OK, DD_ERR_ARG, DD_ERR_HIP, DD_ERR_NOMEM, DD_ERR_NOCONV, DD_ERR_BREAKDOWN, DD_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+DD_FP64, DD_FP32, DD_MIXED = 0, 1, 2
+DD_BICGSTAB, DD_CGNR = 0, 1
+DD_MAX_RHS = 12
+
+EXPORTS = [
+    "dd_create", "dd_destroy", "dd_last_error", "dd_apply_dirac", "dd_frontier_hop", "dd_block_solve",
+    "dd_factorized_propagator", "dd_pion_correlator", "dd_block_solve_backward", "dd_domain_action",
+    "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing",
+]
+
+
+class dd_lattice(C.Structure):
+    _fields_ = [("T", C.c_int), ("L", C.c_int), ("time_bc", C.c_int)]
+
+
+class dd_domain(C.Structure):
+    _fields_ = [("t0", C.c_int), ("nt", C.c_int)]
+
+
+class dd_solver_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("prec", C.c_int), ("inner_tol", C.c_double),
+                ("max_outer", C.c_int), ("solver", C.c_int), ("check_every", C.c_int)]
+
+
+class dd_solve_stats(C.Structure):
+    _fields_ = [("nrhs", C.c_int), ("iters", C.c_int), ("outer", C.c_int), ("restarts", C.c_int),
+                ("true_rel_resid", C.c_double * DD_MAX_RHS), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return dict(nrhs=self.nrhs, iters=self.iters, outer=self.outer, restarts=self.restarts,
+                    true_rel_resid=list(self.true_rel_resid)[: self.nrhs], ms=self.ms)
+
+
+class dd_batch_item(C.Structure):
+    _fields_ = [("lat", dd_lattice), ("U", C.c_void_p), ("kappa", C.c_double), ("nrhs", C.c_int),
+                ("b", C.c_void_p), ("x", C.c_void_p)]
+
+
+_vp, _d, _i = C.c_void_p, C.c_double, C.c_int
+_sig = {
+    "dd_create": ([C.POINTER(dd_lattice), _vp, C.POINTER(_vp)], _i),
+    "dd_destroy": ([_vp], None),
+    "dd_last_error": ([_vp], C.c_char_p),
+    "dd_apply_dirac": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _i], _i),
+    "dd_frontier_hop": ([_vp, _vp, C.POINTER(dd_domain), C.POINTER(dd_domain), _i, _vp, _vp, _d], _i),
+    "dd_block_solve": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, C.POINTER(dd_solver_params),
+                        C.POINTER(dd_solve_stats)], _i),
+    "dd_factorized_propagator": ([_vp, _vp, _d, C.POINTER(C.c_int), C.POINTER(dd_domain), _i, _i,
+                                  C.POINTER(dd_solver_params), _vp, _vp, C.POINTER(dd_solve_stats)], _i),
+    "dd_pion_correlator": ([_vp, _vp, _i, _i, C.POINTER(C.c_double)], _i),
+    "dd_block_solve_backward": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, _vp,
+                                 C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
+    "dd_domain_action": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, C.POINTER(C.c_double),
+                          C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
+    "dd_link_force": ([_vp, C.POINTER(dd_domain), _i, _vp, _vp, _d, _vp], _i),
+    "dd_block_solve_batched": ([_vp, _i, C.POINTER(dd_batch_item), C.POINTER(dd_solver_params),
+                                C.POINTER(dd_solve_stats)], _i),
+    "dd_set_kernel_timing": ([_vp, _i], _i),
+    "dd_kernel_timing": ([_vp, _i, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double)], _i),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class DDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libdd status {status}: {msg}")
+        self.status = status
+
+
+def solver_params(tol=1e-10, max_iter=20000, prec=DD_FP64, inner_tol=1e-5, max_outer=50, solver=DD_BICGSTAB,
+                  check_every=0):
+    return dd_solver_params(float(tol), int(max_iter), int(prec), float(inner_tol), int(max_outer), int(solver),
+                            int(check_every))
+
+
+def _dom(dom):
+    if dom is None:
+        return None
+    return C.byref(dd_domain(int(dom[0]), int(dom[1])))
+
+
+def _ptr(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libdd context for a T x L^3 lattice on the current HIP stream."""
+
+    def __init__(self, T, L, time_bc=-1, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.T, self.L, self.time_bc = int(T), int(L), int(time_bc)
+        self.V = self.T * self.L ** 3
+        h = C.c_void_p()
+        st = _lib.dd_create(C.byref(dd_lattice(self.T, self.L, self.time_bc)), C.c_void_p(stream.cuda_stream),
+                            C.byref(h))
+        if st != DD_OK:
+            raise DDError(st, "dd_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=()):
+        if st != DD_OK and st not in allow:
+            raise DDError(st, _lib.dd_last_error(self._h).decode())
+        return st
+
+    def nsite(self, dom):
+        return self.V if dom is None else int(dom[1]) * self.L ** 3
+
+
+def apply_dirac(ctx, U, kappa, psi, dom=None, out=None):
+    """out = D psi (dom None) or D_Lambda psi; FP64 for complex128, FP32 for complex64."""
+    prec = DD_FP64 if psi.dtype == torch.complex128 else DD_FP32
+    if out is None:
+        out = torch.empty_like(psi)
+    ncol = psi.shape[0]
+    ctx._check(_lib.dd_apply_dirac(ctx._h, _ptr(U, psi.dtype, "U"), float(kappa), _dom(dom), ncol,
+                                   _ptr(psi, psi.dtype, "psi"), _ptr(out, psi.dtype, "out"), prec))
+    return out
+
+
+def frontier_hop(ctx, U, dst, src, psi, out, alpha=1.0):
+    """out += alpha P_dst D P_src psi (FP64)."""
+    ctx._check(_lib.dd_frontier_hop(ctx._h, _ptr(U, torch.complex128, "U"), _dom(dst), _dom(src), psi.shape[0],
+                                    _ptr(psi, torch.complex128, "psi"), _ptr(out, torch.complex128, "out"),
+                                    float(alpha)))
+    return out
+
+
+def block_solve(ctx, U, kappa, b, dom=None, params=None, x=None, allow_noconv=False):
+    """x = D_Lambda^-1 b for the columns of b (complex128, (ncol, 12, nsite)).  Returns (x, stats)."""
+    params = params or solver_params()
+    if x is None:
+        x = torch.empty_like(b)
+    stats = dd_solve_stats()
+    ctx._check(_lib.dd_block_solve(ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), _dom(dom), b.shape[0],
+                                   _ptr(b, torch.complex128, "b"), _ptr(x, torch.complex128, "x"),
+                                   C.byref(params), C.byref(stats)),
+               allow=(DD_ERR_NOCONV,) if allow_noconv else ())
+    return x, stats.as_dict()
+
+
+def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_fact=None, S_exact=None):
+    """S_fact (and S_exact) as complex128 (12, 12, V).  Returns (S_fact, S_exact or None, stats)."""
+    params = params or solver_params()
+    V = ctx.V
+    if S_fact is None:
+        S_fact = torch.empty((12, 12, V), dtype=torch.complex128, device=U.device)
+    if exact and S_exact is None:
+        S_exact = torch.empty((12, 12, V), dtype=torch.complex128, device=U.device)
+    srcarr = (C.c_int * 4)(*[int(v) for v in src])
+    darr = (dd_domain * len(doms))(*[dd_domain(int(a), int(b)) for a, b in doms])
+    stats = (dd_solve_stats * (len(doms) + 1))()
+    ctx._check(_lib.dd_factorized_propagator(
+        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), srcarr, darr, len(doms), 0, C.byref(params),
+        _ptr(S_fact, torch.complex128, "S_fact"),
+        _ptr(S_exact, torch.complex128, "S_exact") if exact else None, stats))
+    return S_fact, (S_exact if exact else None), [s.as_dict() for s in stats]
+
+
+def pion_correlator(ctx, S, t_src):
+    """C(t), t = 0..T-1, as a numpy float64 array."""
+    out = (C.c_double * ctx.T)()
+    ctx._check(_lib.dd_pion_correlator(ctx._h, _ptr(S, torch.complex128, "S"), S.shape[0], int(t_src), out))
+    return np.array(list(out))
+
+
+def block_solve_backward(ctx, U, kappa, x, grad_x, dom=None, params=None, grad_U=None):
+    """Returns (grad_b, grad_U, stats); grad_U accumulates into the given tensor."""
+    params = params or solver_params()
+    grad_b = torch.empty_like(grad_x)
+    if grad_U is None:
+        grad_U = torch.zeros_like(U)
+    stats = dd_solve_stats()
+    ctx._check(_lib.dd_block_solve_backward(
+        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), _dom(dom), x.shape[0], _ptr(x, torch.complex128, "x"),
+        _ptr(grad_x, torch.complex128, "grad_x"), _ptr(grad_b, torch.complex128, "grad_b"),
+        _ptr(grad_U, torch.complex128, "grad_U"), C.byref(params), C.byref(stats)))
+    return grad_b, grad_U, stats.as_dict()
+
+
+def domain_action(ctx, U, kappa, phi, dom=None, params=None):
+    """(S, X, Y, stats) with Y = D^-+ phi, X = D^-1 Y, S = |Y|^2."""
+    params = params or solver_params()
+    X = torch.empty_like(phi)
+    Y = torch.empty_like(phi)
+    S = C.c_double()
+    stats = dd_solve_stats()
+    ctx._check(_lib.dd_domain_action(ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), _dom(dom), phi.shape[0],
+                                     _ptr(phi, torch.complex128, "phi"), _ptr(X, torch.complex128, "X"),
+                                     _ptr(Y, torch.complex128, "Y"), C.byref(S), C.byref(params), C.byref(stats)))
+    return S.value, X, Y, stats.as_dict()
+
+
+def link_force(ctx, X, Y, coeff, grad_U, dom=None):
+    """grad_U += coeff * d/dU [-2 Re <Y, D X>]."""
+    ctx._check(_lib.dd_link_force(ctx._h, _dom(dom), X.shape[0], _ptr(X, torch.complex128, "X"),
+                                  _ptr(Y, torch.complex128, "Y"), float(coeff),
+                                  _ptr(grad_U, torch.complex128, "grad_U")))
+    return grad_U
+
+
+def block_solve_batched(ctx, items, params=None):
+    """items: list of dicts(T, L, time_bc, U, kappa, b, x).  Returns per-item stats."""
+    params = params or solver_params()
+    arr = (dd_batch_item * len(items))()
+    for k, it in enumerate(items):
+        arr[k] = dd_batch_item(dd_lattice(int(it["T"]), int(it["L"]), int(it.get("time_bc", 0))),
+                               _ptr(it["U"], torch.complex128, "U"), float(it["kappa"]), int(it["b"].shape[0]),
+                               _ptr(it["b"], torch.complex128, "b"), _ptr(it["x"], torch.complex128, "x"))
+    stats = (dd_solve_stats * len(items))()
+    ctx._check(_lib.dd_block_solve_batched(ctx._h, len(items), arr, C.byref(params), stats))
+    return [s.as_dict() for s in stats]
+
+
+def set_kernel_timing(ctx, enable):
+    ctx._check(_lib.dd_set_kernel_timing(ctx._h, int(bool(enable))))
+
+
+def kernel_timing(ctx, kind):
+    """(ms, launches, algorithmic bytes) of the stencil launches of kind 0 (FP64) or 1 (FP32)."""
+    ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
+    ctx._check(_lib.dd_kernel_timing(ctx._h, int(kind), C.byref(ms), C.byref(n), C.byref(b)))
+    return ms.value, n.value, b.value
+
+
+# ------------------------------------------------------------------ layout marshalling
+
+def pack_links(U_nat, dtype=torch.complex128, device="cuda"):
+    """(V, 4, 3, 3) natural links -> (4, 9, V) device tensor."""
+    t = torch.as_tensor(np.asarray(U_nat)).reshape(-1, 4, 9).permute(1, 2, 0).contiguous()
+    return t.to(device=device, dtype=dtype)
+
+
+def pack_field(f_nat, dtype=torch.complex128, device="cuda"):
+    """(ncol, nsite, 12) natural field -> (ncol, 12, nsite) device tensor."""
+    t = torch.as_tensor(np.asarray(f_nat))
+    if t.dim() == 2:
+        t = t[None]
+    return t.permute(0, 2, 1).contiguous().to(device=device, dtype=dtype)
+
+
+def unpack_field(f):
+    """(ncol, 12, nsite) device tensor -> (ncol, nsite, 12) numpy complex128."""
+    return f.detach().to("cpu", torch.complex128).permute(0, 2, 1).contiguous().numpy()
+
+
+def unpack_links(Ut):
+    """(4, 9, V) device tensor -> (V, 4, 3, 3) numpy complex128."""
+    return Ut.detach().to("cpu", torch.complex128).permute(2, 0, 1).contiguous().numpy().reshape(-1, 4, 3, 3)
+
+
+# ------------------------------------------------------------------ autograd
+
+class BlockSolveFn(torch.autograd.Function):
+    """x = D_Lambda(U)^-1 b, differentiable in U and b through the hand-written
+    adjoint solve (dd_block_solve_backward)."""
+
+    @staticmethod
+    def forward(fctx, U, b, ctx, kappa, dom, params):
+        x, _ = block_solve(ctx, U, kappa, b.contiguous(), dom, params)
+        fctx.save_for_backward(U, x)
+        fctx.dd = (ctx, kappa, dom, params)
+        return x
+
+    @staticmethod
+    def backward(fctx, grad_x):
+        U, x = fctx.saved_tensors
+        ctx, kappa, dom, params = fctx.dd
+        grad_b, grad_U, _ = block_solve_backward(ctx, U, kappa, x, grad_x.contiguous(), dom, params)
+        return grad_U, grad_b, None, None, None, None
+
+
+class DomainActionFn(torch.autograd.Function):
+    """S = phi^+ (D_Lambda^+ D_Lambda)^-1 phi with its link force from one extra
+    (adjoint) solve: forward solves D^+ Y = phi and D X = Y; backward needs no
+    further solve (grad_U = force(X, Y), grad_phi = 2 X)."""
+
+    @staticmethod
+    def forward(fctx, U, phi, ctx, kappa, dom, params):
+        S, X, Y, _ = domain_action(ctx, U, kappa, phi.contiguous(), dom, params)
+        fctx.save_for_backward(X, Y, U)
+        fctx.dd = (ctx, dom)
+        return torch.tensor(S, dtype=torch.float64, device=phi.device)
+
+    @staticmethod
+    def backward(fctx, gS):
+        X, Y, U = fctx.saved_tensors
+        ctx, dom = fctx.dd
+        g = float(gS.item())
+        grad_U = torch.zeros_like(U)
+        link_force(ctx, X, Y, g, grad_U, dom)
+        return grad_U, 2.0 * g * X, None, None, None, None

@@ -29,6 +29,54 @@ def site_index(T: int, L: int, t: int, x: int, y: int, z: int) -> int:
     return ((t * L + z) * L + y) * L + x
 
 
+def _expi_traceless_hermitian(q):
+    """exp(i Q) for traceless Hermitian 3x3 matrices Q given entry-wise:
+    q[i][j] are equally shaped complex arrays.  Returns the entries likewise.
+
+    Cayley-Hamilton form exp(iQ) = f0 + f1 Q + f2 Q^2 with the coefficients of
+    Morningstar and Peardon, Phys. Rev. D 69 (2004) 054501, Eqs. (23)-(34):
+    c0 = det Q, c1 = tr Q^2 / 2, theta = arccos(|c0| / c0_max),
+    u = sqrt(c1/3) cos(theta/3), w = sqrt(c1) sin(theta/3); negative c0 uses
+    f_j(-c0) = (-1)^j conj(f_j(c0)).  Exact up to rounding, fully vectorised.
+    """
+    q2 = [[q[i][0] * q[0][j] + q[i][1] * q[1][j] + q[i][2] * q[2][j] for j in range(3)] for i in range(3)]
+    c1 = 0.5 * (q2[0][0] + q2[1][1] + q2[2][2]).real
+    c0 = (q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1])
+          - q[0][1] * (q[1][0] * q[2][2] - q[1][2] * q[2][0])
+          + q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0])).real
+    neg = c0 < 0
+    c0max = 2.0 * (c1 / 3.0) ** 1.5
+    ratio = np.where(c0max > 0, np.abs(c0) / np.where(c0max > 0, c0max, 1.0), 0.0)
+    theta = np.arccos(np.clip(ratio, -1.0, 1.0))
+    u = np.sqrt(c1 / 3.0) * np.cos(theta / 3.0)
+    w = np.sqrt(c1) * np.sin(theta / 3.0)
+    small = np.abs(w) < 0.05
+    w2 = w * w
+    xi0 = np.where(small, 1 - w2 / 6 * (1 - w2 / 20 * (1 - w2 / 42)), np.sin(w) / np.where(small, 1.0, w))
+    e2iu = np.exp(2j * u)
+    emiu = np.exp(-1j * u)
+    cw = np.cos(w)
+    h0 = (u * u - w2) * e2iu + emiu * (8 * u * u * cw + 2j * u * (3 * u * u + w2) * xi0)
+    h1 = 2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * u * u - w2) * xi0)
+    h2 = e2iu - emiu * (cw + 3j * u * xi0)
+    den = 9 * u * u - w2
+    f0, f1, f2 = h0 / den, h1 / den, h2 / den
+    f0 = np.where(neg, np.conj(f0), f0)
+    f1 = np.where(neg, -np.conj(f1), f1)
+    f2 = np.where(neg, np.conj(f2), f2)
+    return [[f1 * q[i][j] + f2 * q2[i][j] + (f0 if i == j else 0.0) for j in range(3)] for i in range(3)]
+
+
+def expi_matrices(Q: np.ndarray) -> np.ndarray:
+    """exp(i Q) for an array (..., 3, 3) of traceless Hermitian matrices."""
+    e = _expi_traceless_hermitian([[np.ascontiguousarray(Q[..., i, j]) for j in range(3)] for i in range(3)])
+    out = np.empty(Q.shape, dtype=np.complex128)
+    for i in range(3):
+        for j in range(3):
+            out[..., i, j] = e[i][j]
+    return out
+
+
 def random_links(T: int, L: int, eps: float, seed: int) -> np.ndarray:
     """U = exp(i eps H) per link, H traceless Hermitian with Gaussian entries.
 
@@ -36,35 +84,27 @@ def random_links(T: int, L: int, eps: float, seed: int) -> np.ndarray:
     and H_ji = conj(H_ij); then H <- H - tr(H)/3, so E tr H^2 = 14.  The nine
     reals per link come from numpy PCG64 ``standard_normal((T,L,L,L,4,9))`` in
     the order (H00, H11, H22, Re H01, Im H01, Re H02, Im H02, Re H12, Im H12).
-    The exponential is exact through the eigen-decomposition of H (no
-    re-unitarisation is needed: tr H = 0 gives det U = 1).
+    The exponential is exact up to rounding (closed Cayley-Hamilton form);
+    tr H = 0 gives det U = 1.
     """
     rng = np.random.default_rng(seed)
-    V = T * L * L * L
-    out = np.empty((V, 4, 3, 3), dtype=np.complex128)
-    # chunked to bound host memory on large lattices
-    chunk = 1 << 18
-    g_all = rng.standard_normal((T, L, L, L, 4, 9)).reshape(V, 4, 9)
-    for lo in range(0, V, chunk):
-        g = g_all[lo:lo + chunk]
-        n = g.shape[0]
-        H = np.zeros((n, 4, 3, 3), dtype=np.complex128)
-        H[..., 0, 0] = g[..., 0]
-        H[..., 1, 1] = g[..., 1]
-        H[..., 2, 2] = g[..., 2]
-        H[..., 0, 1] = g[..., 3] + 1j * g[..., 4]
-        H[..., 0, 2] = g[..., 5] + 1j * g[..., 6]
-        H[..., 1, 2] = g[..., 7] + 1j * g[..., 8]
-        H[..., 1, 0] = np.conj(H[..., 0, 1])
-        H[..., 2, 0] = np.conj(H[..., 0, 2])
-        H[..., 2, 1] = np.conj(H[..., 1, 2])
-        tr = (g[..., 0] + g[..., 1] + g[..., 2]) / 3.0
-        for a in range(3):
-            H[..., a, a] -= tr
-        w, vec = np.linalg.eigh(H)
-        ph = np.exp(1j * eps * w)
-        out[lo:lo + n] = np.einsum("...ak,...k,...bk->...ab", vec, ph, np.conj(vec))
-    return out
+    n = T * L * L * L * 4
+    g = np.ascontiguousarray(rng.standard_normal((T, L, L, L, 4, 9)).reshape(n, 9).T)
+    out = np.empty((n, 3, 3), dtype=np.complex128)
+    chunk = 1 << 18  # bounds host memory on large lattices
+    for lo in range(0, n, chunk):
+        sl = slice(lo, min(n, lo + chunk))
+        tr = (g[0, sl] + g[1, sl] + g[2, sl]) / 3.0
+        d = [eps * (g[k, sl] - tr) + 0j for k in range(3)]
+        h01 = eps * (g[3, sl] + 1j * g[4, sl])
+        h02 = eps * (g[5, sl] + 1j * g[6, sl])
+        h12 = eps * (g[7, sl] + 1j * g[8, sl])
+        q = [[d[0], h01, h02], [np.conj(h01), d[1], h12], [np.conj(h02), np.conj(h12), d[2]]]
+        e = _expi_traceless_hermitian(q)
+        for i in range(3):
+            for j in range(3):
+                out[sl, i, j] = e[i][j]
+    return out.reshape(T * L * L * L, 4, 3, 3)
 
 
 def point_sources(T: int, L: int, t: int, x: int, y: int, z: int) -> np.ndarray:

@@ -1,0 +1,166 @@
+"""GPU parity of the solves, the factorised propagator, the pion correlator and the
+adjoint (link force) against the oracle, plus the error paths of the C ABI.
+
+Bars: FP64 results within 1e-10 of the oracle (relative field norm), mixed precision
+within 1e-6; the correlator gated on max_t |dC(t)| / max_t C(t).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import gaussian_field, lib, random_links, relerr, step
+from paper_1612_06424_amd.inputs import WORKLOADS, point_sources
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("T,L,bc,dom,kappa,eps", [
+    (16, 4, -1, None, 0.125, 0.3),
+    (16, 4, -1, (0, 8), 0.125, 0.3),
+    (12, 6, -1, (9, 5), 0.13, 0.3),
+    (8, 5, 0, None, 0.135, 0.2),
+])
+def test_block_solve_vs_oracle(prec, solver, T, L, bc, dom, kappa, eps):
+    dd = lib()
+    step(f"solve {prec} solver={solver} T={T} L={L} bc={bc} dom={dom}")
+    U = random_links(T, L, eps, 2000 + T)
+    nsite = (T if dom is None else dom[1]) * L ** 3
+    b = gaussian_field(nsite, 3, 2001)
+    ref, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=1e-13, method=solver)
+    assert st == 0
+    ctx = dd.Context(T, L, bc)
+    p = dd.solver_params(tol=1e-12 if prec == "fp64" else 1e-10, max_iter=20000,
+                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, inner_tol=1e-4, solver=solver)
+    x, stats = dd.block_solve(ctx, dd.pack_links(U), kappa, dd.pack_field(b), dom, p)
+    got = dd.unpack_field(x)
+    assert max(stats["true_rel_resid"]) <= p.tol
+    assert relerr(got, ref) < (1e-10 if prec == "fp64" else 1e-6)
+    # the residual also holds when measured by the oracle's own operator
+    Dx = O.apply_dirac(U, kappa, T, L, bc, got, dom)
+    assert relerr(Dx, b) <= 2 * p.tol
+
+
+def test_adjoint_solve_through_backward():
+    """grad_b of x = D^-1 b is D^-+ grad_x: check D^+ grad_b = grad_x with the oracle."""
+    dd = lib()
+    step("adjoint solve")
+    T, L, bc, kappa, dom = 12, 4, -1, 0.13, (2, 6)
+    U = random_links(T, L, 0.3, 2100)
+    nsite = dom[1] * L ** 3
+    b = gaussian_field(nsite, 2, 2101)
+    g = gaussian_field(nsite, 2, 2102)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U)
+    p = dd.solver_params(tol=1e-12)
+    x, _ = dd.block_solve(ctx, Ud, kappa, dd.pack_field(b), dom, p)
+    gb, gU, _ = dd.block_solve_backward(ctx, Ud, kappa, x, dd.pack_field(g), dom, p)
+    lam = dd.unpack_field(gb)
+    # D^+ = gamma5 D gamma5
+    Ddag_lam = O.gamma5(O.apply_dirac(U, kappa, T, L, bc, O.gamma5(lam), dom))
+    assert relerr(Ddag_lam, g) < 1e-11
+    # link gradient of the loss: grad_U = 1/2 * grad of -2 Re<lambda, D x>
+    ref = O.link_grad(T, L, bc, dom, dd.unpack_field(x), lam, coeff=0.5)
+    assert relerr(dd.unpack_links(gU), ref) < 1e-12
+
+
+def _workload_16x4():
+    w = WORKLOADS["16x4^3"]
+    return w, random_links(w["T"], w["L"], w["eps"], w["link_seed"])
+
+
+def test_factorised_propagator_and_correlator_16x4():
+    """The 16x4^3 workload: two slabs [0,8), [8,16), point source at the origin."""
+    dd = lib()
+    step("factorised propagator 16x4^3")
+    w, U = _workload_16x4()
+    T, L, bc, kappa = w["T"], w["L"], w["bc"], w["kappa"]
+    src = w["sources"][0]
+    Sf_ref, _ = O.factorized_propagator(U, kappa, T, L, bc, src, w["domains"], tol=1e-13)
+    Se_ref, _ = O.exact_propagator(U, kappa, T, L, bc, src, tol=1e-13)
+    ctx = dd.Context(T, L, bc)
+    p = dd.solver_params(tol=1e-13)
+    Sf, Se, stats = dd.factorized_propagator(ctx, dd.pack_links(U), kappa, src, w["domains"], p, exact=True)
+    assert relerr(dd.unpack_field(Sf), Sf_ref) < 1e-10
+    assert relerr(dd.unpack_field(Se), Se_ref) < 1e-10
+    Cf = dd.pion_correlator(ctx, Sf, src[0])
+    Ce = dd.pion_correlator(ctx, Se, src[0])
+    Cf_ref = O.pion_correlator(T, L, Sf_ref, src[0])
+    Ce_ref = O.pion_correlator(T, L, Se_ref, src[0])
+    assert np.abs(Cf - Cf_ref).max() / Cf_ref.max() < 1e-10
+    assert np.abs(Ce - Ce_ref).max() / Ce_ref.max() < 1e-10
+    # the contraction itself on identical input: exact to summation order
+    Cg = O.pion_correlator(T, L, dd.unpack_field(Se), src[0])
+    assert np.abs(Ce - Cg).max() / Cg.max() < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_factorised_four_slabs_with_wrap(prec):
+    """Four slabs on a ring (the middle slab reached from both sides), source off the origin."""
+    dd = lib()
+    step(f"factorised 4 slabs {prec}")
+    T, L, bc, kappa = 16, 4, -1, 0.13
+    U = random_links(T, L, 0.3, 2200)
+    doms = [(14, 4), (2, 4), (6, 4), (10, 4)]
+    src = (15, 1, 2, 3)
+    Sf_ref, _ = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=1e-13)
+    ctx = dd.Context(T, L, bc)
+    p = dd.solver_params(tol=1e-13 if prec == "fp64" else 1e-10,
+                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED)
+    Sf, _, _ = dd.factorized_propagator(ctx, dd.pack_links(U), kappa, src, doms, p)
+    assert relerr(dd.unpack_field(Sf), Sf_ref) < (1e-10 if prec == "fp64" else 1e-6)
+    C = dd.pion_correlator(ctx, Sf, src[0])
+    Cr = O.pion_correlator(T, L, Sf_ref, src[0])
+    assert np.abs(C - Cr).max() / Cr.max() < (1e-10 if prec == "fp64" else 1e-6)
+
+
+def test_domain_action_force_vs_oracle():
+    dd = lib()
+    step("domain action + force")
+    T, L, bc, kappa = 8, 4, 0, 0.13
+    U = random_links(T, L, 0.3, 2300)
+    phi = gaussian_field(T * L ** 3, 1, 2301)
+    S_ref, X_ref, Y_ref = O.domain_action(U, kappa, T, L, bc, None, phi[0])
+    g_ref = O.link_grad(T, L, bc, None, X_ref, Y_ref, coeff=1.0)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U).requires_grad_(True)
+    ph = dd.pack_field(phi).requires_grad_(True)
+    p = dd.solver_params(tol=1e-13)
+    S = dd.DomainActionFn.apply(Ud, ph, ctx, kappa, None, p)
+    S.backward()
+    assert abs(S.item() - S_ref) < 1e-10 * S_ref
+    assert relerr(dd.unpack_links(Ud.grad), g_ref) < 1e-10
+    assert relerr(dd.unpack_field(ph.grad)[0], 2 * X_ref) < 1e-10
+
+
+def test_error_paths():
+    dd = lib()
+    step("error paths")
+    T, L, bc = 8, 4, -1
+    U = random_links(T, L, 0.3, 2400)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U)
+    b = dd.pack_field(gaussian_field(T * L ** 3, 2, 2401))
+    # max_iter = 1 -> no convergence, stats filled
+    x, stats = dd.block_solve(ctx, Ud, 0.13, b, None, dd.solver_params(tol=1e-12, max_iter=1), allow_noconv=True)
+    with pytest.raises(dd.DDError) as e:
+        dd.block_solve(ctx, Ud, 0.13, b, None, dd.solver_params(tol=1e-12, max_iter=1))
+    assert e.value.status == dd.DD_ERR_NOCONV
+    assert stats["nrhs"] == 2 and max(stats["true_rel_resid"]) > 1e-12
+    # NaN in the source
+    bn = b.clone()
+    bn[0, 0, 3] = complex(float("nan"), 0.0)
+    with pytest.raises(dd.DDError) as e:
+        dd.block_solve(ctx, Ud, 0.13, bn)
+    assert e.value.status == dd.DD_ERR_BREAKDOWN
+    # a slab as long as the lattice, slabs that do not partition [0, T), host memory
+    with pytest.raises(dd.DDError) as e:
+        dd.apply_dirac(ctx, Ud, 0.13, b, dom=(0, T))
+    assert e.value.status == dd.DD_ERR_ARG
+    with pytest.raises(dd.DDError) as e:
+        dd.factorized_propagator(ctx, Ud, 0.13, (0, 0, 0, 0), [(0, 4), (5, 3)])
+    assert e.value.status == dd.DD_ERR_ARG
+    with pytest.raises(ValueError):
+        dd.apply_dirac(ctx, Ud, 0.13, b.cpu())
