@@ -1,0 +1,265 @@
+"""Benchmark of the Wilson-Dirac hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step is one pass over every part of the hot path on synthetic inputs
+already resident in HBM:
+  stencil   D on the whole 64x32^3 lattice (FP64 / FP32, 1 and 12 columns) and
+            D_Lambda on a 16x32^3 slab
+  solves    12 point sources on the 16x32^3 slab [0,16): plain FP64 BiCGStab and
+            FP32-inner / FP64-outer defect correction, both to a true residual 1e-10
+  factorised propagator across the four slabs [0,16) [16,32) [32,48) [48,64)
+            (mixed solves, frontier hops), then the pion correlator C(t)
+  batched   96 independent Dirichlet domains of uneven sizes, 12 sources each
+  force     S = phi^+ (D^+ D)^-1 phi on a 32x16^3 Dirichlet domain and its link
+            force through the hand-written adjoint (torch.autograd)
+The JSON line reports the aggregate algorithmic stencil bandwidth (value), the
+per-part timings, the roofline of the dominant kernel (timed with HIP events
+on the library's stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,batched,force")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one GPU's share of the "
+              "lattice is one time slab; see the design notes on sharding). Run with --gpus 1.", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1612_06424_amd.dd as dd
+    from paper_1612_06424_amd.inputs import WORKLOADS, batched_domains, gaussian_field, random_links
+
+    parts = set(args.parts.split(",")) if args.parts != "all" else {"stencil", "solve", "fact", "batched", "force"}
+    if args.no_batched:
+        parts.discard("batched")
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    # ------------------------------------------------------------ inputs
+    w = WORKLOADS["64x32^3"]
+    T, L, bc, kappa = w["T"], w["L"], w["bc"], w["kappa"]
+    V = T * L ** 3
+    t0 = time.time()
+    U_nat = random_links(T, L, w["eps"], w["link_seed"])
+    log(f"links 64x32^3 generated in {time.time() - t0:.1f}s")
+    U64 = dd.pack_links(U_nat, torch.complex128)
+    U32 = dd.pack_links(U_nat, torch.complex64)
+    del U_nat
+    ctx = dd.Context(T, L, bc)
+    g = torch.Generator(device=dev)
+    g.manual_seed(w["stencil_seed"])
+    psi12 = torch.randn((12, 12, V), dtype=torch.complex128, device=dev, generator=g)
+    psi12_32 = psi12.to(torch.complex64)
+    out12 = torch.empty_like(psi12)
+    out12_32 = torch.empty_like(psi12_32)
+    slab = (16, 16)
+    Vs = 16 * L ** 3
+    psis = psi12[:, :, :Vs].contiguous()
+    outs = torch.empty_like(psis)
+    # 12 point sources at the origin of the slab [0,16)
+    src = w["sources"][0]
+    eta = torch.zeros((12, 12, Vs), dtype=torch.complex128, device=dev)
+    s0 = ((src[0] * L + src[3]) * L + src[2]) * L + src[1]
+    for j in range(12):
+        eta[j, j, s0] = 1.0
+    dom0 = (0, 16)
+    p64 = dd.solver_params(tol=w["tol"], max_iter=20000, prec=dd.DD_FP64)
+    pmx = dd.solver_params(tol=w["tol"], max_iter=20000, prec=dd.DD_MIXED, inner_tol=3e-5, max_outer=30)
+
+    if "batched" in parts:
+        t0 = time.time()
+        bitems = []
+        for it in batched_domains(96):
+            Ti, Li = it["T"], it["L"]
+            Vi = Ti * Li ** 3
+            Ub = dd.pack_links(random_links(Ti, Li, it["eps"], it["link_seed"]))
+            b = torch.zeros((12, 12, Vi), dtype=torch.complex128, device=dev)
+            ts, xs, ys, zs = it["source"]
+            si = ((ts * Li + zs) * Li + ys) * Li + xs
+            for j in range(12):
+                b[j, j, si] = 1.0
+            bitems.append(dict(T=Ti, L=Li, time_bc=0, U=Ub, kappa=it["kappa"], b=b, x=torch.empty_like(b)))
+        bctx = dd.Context(8, 8, 0)
+        log(f"batched inputs: {len(bitems)} domains, {sum(b['b'].shape[2] for b in bitems)} sites "
+            f"({time.time() - t0:.1f}s)")
+    if "force" in parts:
+        wf = WORKLOADS["force-32x16^3"]
+        Uf = dd.pack_links(random_links(wf["T"], wf["L"], wf["eps"], wf["link_seed"]))
+        phi = dd.pack_field(gaussian_field(wf["T"] * wf["L"] ** 3, 1, wf["phi_seed"]))
+        fctx = dd.Context(wf["T"], wf["L"], wf["bc"])
+        pf = dd.solver_params(tol=wf["tol"], prec=dd.DD_MIXED, inner_tol=3e-5)
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed_stencil(fn, n=10):
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    def step(record):
+        ph = {}
+        if "stencil" in parts:
+            for name, fn, nsite, ncol, rb in [
+                ("D_fp64_1col", lambda: dd.apply_dirac(ctx, U64, kappa, psi12[:1], None, out12[:1]), V, 1, 8),
+                ("D_fp64_12col", lambda: dd.apply_dirac(ctx, U64, kappa, psi12, None, out12), V, 12, 8),
+                ("D_fp32_1col", lambda: dd.apply_dirac(ctx, U32, kappa, psi12_32[:1], None, out12_32[:1]), V, 1, 4),
+                ("D_fp32_12col", lambda: dd.apply_dirac(ctx, U32, kappa, psi12_32, None, out12_32), V, 12, 4),
+                ("Dslab_fp64_12col", lambda: dd.apply_dirac(ctx, U64, kappa, psis, slab, outs), Vs, 12, 8),
+            ]:
+                ms = timed_stencil(fn)
+                gbs = nsite * (48 * ncol + 72) * rb / ms / 1e6
+                ph[name] = dict(ms=ms, GBs=gbs, frac=gbs / HBM_PEAK_GBS)
+        if "solve" in parts:
+            x64, s64 = dd.block_solve(ctx, U64, kappa, eta, dom0, p64)
+            xmx, smx = dd.block_solve(ctx, U64, kappa, eta, dom0, pmx)
+            ph["solve_fp64"] = dict(ms=s64["ms"], iters=s64["iters"], max_true_rel_resid=max(s64["true_rel_resid"]))
+            ph["solve_mixed"] = dict(ms=smx["ms"], iters=smx["iters"], outer=smx["outer"],
+                                     max_true_rel_resid=max(smx["true_rel_resid"]))
+            if record:
+                ph["solve_mixed"]["rel_diff_vs_fp64"] = float((torch.linalg.vector_norm(xmx - x64) /
+                                                               torch.linalg.vector_norm(x64)).item())
+            del x64, xmx
+        if "fact" in parts:
+            t0 = time.perf_counter()
+            Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx)
+            C = dd.pion_correlator(ctx, Sf, src[0])
+            ph["factorised"] = dict(ms=(time.perf_counter() - t0) * 1e3,
+                                    slab_iters=[s["iters"] for s in fst[:4]],
+                                    max_true_rel_resid=max(max(s["true_rel_resid"]) for s in fst[:4]))
+            if record:
+                ph["factorised"]["C0"] = float(C[0])
+                ph["factorised"]["C32"] = float(C[32])
+            del Sf
+        if "batched" in parts:
+            t0 = time.perf_counter()
+            bst = dd.block_solve_batched(bctx, bitems, pmx)
+            ph["batched"] = dict(ms=(time.perf_counter() - t0) * 1e3, domains=len(bitems),
+                                 max_true_rel_resid=max(max(s["true_rel_resid"]) for s in bst))
+        if "force" in parts:
+            t0 = time.perf_counter()
+            Ug = Uf.clone().requires_grad_(True)
+            S = dd.DomainActionFn.apply(Ug, phi, fctx, wf["kappa"], None, pf)
+            S.backward()
+            torch.cuda.synchronize()
+            ph["force"] = dict(ms=(time.perf_counter() - t0) * 1e3, S=float(S.item()))
+        return ph
+
+    for i in range(args.warmup):
+        log(f"warmup step {i}")
+        step(False)
+    for c in (ctx,):
+        dd.set_kernel_timing(c, True)
+    torch.cuda.synchronize()
+    log("timed region")
+    t0 = time.perf_counter()
+    phases = []
+    for i in range(args.steps):
+        phases.append(step(i == args.steps - 1))
+        log(f"step {i}: {json.dumps({k: round(v.get('ms', 0), 2) for k, v in phases[-1].items()})}")
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t0) * 1e3
+    ms64, n64, b64 = dd.kernel_timing(ctx, 0)
+    ms32, n32, b32 = dd.kernel_timing(ctx, 1)
+    dd.set_kernel_timing(ctx, False)
+
+    value = (b64 + b32) / max(ms64 + ms32, 1e-9) / 1e6  # aggregate algorithmic stencil GB/s
+    dom_kind = 1 if ms32 >= ms64 else 0
+    dms, dn, db = (ms32, n32, b32) if dom_kind == 1 else (ms64, n64, b64)
+    achieved = (db / max(dn, 1)) / (dms / max(dn, 1)) / 1e6 if dn else 0.0
+    last = phases[-1]
+    out = {
+        "metric": "Dirac-stencil GB/s + 12-source domain solve ms (mixed vs FP64) at 64x32^3",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "64x32^3 Wilson-Dirac, antiperiodic time, eps=0.15, kappa=0.135; "
+                               "12-source solves on the 16x32^3 slab; 4-slab factorised propagator; "
+                               "96 uneven Dirichlet domains; 32x16^3 force",
+                   "lattice": [T, L, L, L], "kappa": kappa, "tol": w["tol"],
+                   "parts": sorted(parts)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_dslash<float>" if dom_kind == 1 else "k_dslash<double>",
+                     "launches": dn, "avg_launch_ms": round(dms / max(dn, 1), 5),
+                     "bytes_per_launch": round(db / max(dn, 1))},
+    }
+    if "solve" in parts:
+        out["domain_solve_ms_fp64"] = round(last["solve_fp64"]["ms"], 2)
+        out["domain_solve_ms_mixed"] = round(last["solve_mixed"]["ms"], 2)
+        out["mixed_speedup"] = round(last["solve_fp64"]["ms"] / last["solve_mixed"]["ms"], 3)
+    out["parts"] = last
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(T, L, bc, kappa, w)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(T, L, bc, kappa, w):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    the whole-lattice D apply on 64x32^3 for 4 of the 12 columns (scaled to GB/s with
+    the same algorithmic byte count as the GPU)."""
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    from paper_1612_06424_amd.inputs import gaussian_field, random_links
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    U = random_links(T, L, w["eps"], w["link_seed"])
+    ncol = 4
+    psi = gaussian_field(T * L ** 3, ncol, w["stencil_seed"])
+    O.apply_dirac(U, kappa, T, L, bc, psi[0])
+    t0 = time.perf_counter()
+    O.apply_dirac(U, kappa, T, L, bc, psi)
+    dt = time.perf_counter() - t0
+    V = T * L ** 3
+    gbs = V * (48 + 72) * 8 * ncol / dt / 1e9  # one column per apply: links re-read per column
+    return {"value": round(gbs, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle D apply, whole 64x32^3 lattice, FP64, {ncol} columns one at a time "
+                      f"({dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

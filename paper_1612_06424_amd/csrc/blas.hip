@@ -270,32 +270,60 @@ __global__ __launch_bounds__(kBlock) void k_copy_cols(int n, const cpx<R>* __res
     b[(size_t)col * n + i] = a[(size_t)col * n + i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_to_f32_scaled(int n, const cpx<double>* __restrict__ a,
-                                                          cpx<float>* __restrict__ b, const double* __restrict__ scale,
-                                                          const ColState* __restrict__ st) {
+
+// Reliable update helpers (columns selected by mask[col] != 0):
+//   x64 += xk; xk = 0        (xk in the Krylov precision)
+//   rk = (Rk) r64            (replace the recursive residual by the true one)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fold_x(int n, cpx<double>* __restrict__ x, cpx<R>* __restrict__ xk,
+                                                   const int* __restrict__ mask) {
     const int col = blockIdx.y;
-    if (st != nullptr && !st[col].active) return;
+    if (!mask[col]) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const size_t k = (size_t)col * n + i;
-    const double f = scale[col];
-    const cpx<double> v = a[k];
-    b[k] = cpx<float>{(float)(f * v.re), (float)(f * v.im)};
+    const cpx<R> e = xk[k];
+    const cpx<double> v = x[k];
+    x[k] = cd(v.re + (double)e.re, v.im + (double)e.im);
+    xk[k] = cpx<R>{R(0), R(0)};
+}
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_set_resid(int n, const cpx<double>* __restrict__ r64, cpx<R>* __restrict__ rk,
+                                                      const int* __restrict__ mask) {
+    const int col = blockIdx.y;
+    if (!mask[col]) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const size_t k = (size_t)col * n + i;
+    const cpx<double> v = r64[k];
+    rk[k] = cpx<R>{(R)v.re, (R)v.im};
+}
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_restart_dirs(int n, const cpx<R>* __restrict__ r, cpx<R>* __restrict__ rh,
+                                                         cpx<R>* __restrict__ p, cpx<R>* __restrict__ v,
+                                                         const int* __restrict__ mask) {
+    const int col = blockIdx.y;
+    if (mask[col] != 2) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const size_t k = (size_t)col * n + i;
+    rh[k] = r[k];
+    p[k] = cpx<R>{R(0), R(0)};
+    v[k] = cpx<R>{R(0), R(0)};
 }
 
-__global__ __launch_bounds__(kBlock) void k_add_f32_scaled(int n, cpx<double>* __restrict__ x,
-                                                           const cpx<float>* __restrict__ e,
-                                                           const double* __restrict__ scale,
-                                                           const ColState* __restrict__ st) {
+// CGNR reliable update: p += t - z; z = t (columns with mask != 0)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cg_shift(int n, cpx<R>* __restrict__ p, cpx<R>* __restrict__ z,
+                                                     const cpx<R>* __restrict__ t, const int* __restrict__ mask) {
     const int col = blockIdx.y;
-    if (st != nullptr && !st[col].active) return;
+    if (!mask[col]) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const size_t k = (size_t)col * n + i;
-    const double f = scale[col];
-    const cpx<float> v = e[k];
-    const cpx<double> xv = x[k];
-    x[k] = cd(xv.re + f * (double)v.re, xv.im + f * (double)v.im);
+    const cpx<R> tv = t[k];
+    p[k] = p[k] + tv - z[k];
+    z[k] = tv;
 }
 
 __global__ __launch_bounds__(kBlock) void k_links_to_f32(size_t n, const cpx<double>* __restrict__ a,
@@ -552,14 +580,6 @@ template <typename R>
 void launch_copy_cols(dd_ctx* c, int n, int ncol, const cpx<R>* src, cpx<R>* dst, const ColState* st) {
     hipLaunchKernelGGL(k_copy_cols<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, src, dst, st);
 }
-void launch_to_f32_scaled(dd_ctx* c, int n, int ncol, const cpx<double>* src, cpx<float>* dst,
-                          const double* scale, const ColState* st) {
-    hipLaunchKernelGGL(k_to_f32_scaled, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, src, dst, scale, st);
-}
-void launch_add_f32_scaled(dd_ctx* c, int n, int ncol, cpx<double>* x, const cpx<float>* e,
-                           const double* scale, const ColState* st) {
-    hipLaunchKernelGGL(k_add_f32_scaled, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, x, e, scale, st);
-}
 void launch_links_to_f32(dd_ctx* c, size_t n, const cpx<double>* src, cpx<float>* dst) {
     hipLaunchKernelGGL(k_links_to_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
                        n, src, dst);
@@ -617,6 +637,35 @@ void launch_link_force(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* X, 
     hipLaunchKernelGGL(k_link_force, dim3((unsigned)site_blocks(g.nsite)), dim3(kBlock), 0, c->stream, g, ncol, X, Y,
                        coeff, grad);
 }
+
+
+template <typename R>
+void launch_fold_x(dd_ctx* c, int n, int ncol, cpx<double>* x, cpx<R>* xk, const int* mask) {
+    hipLaunchKernelGGL(k_fold_x<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, x, xk, mask);
+}
+template <typename R>
+void launch_set_resid(dd_ctx* c, int n, int ncol, const cpx<double>* r64, cpx<R>* rk, const int* mask) {
+    hipLaunchKernelGGL(k_set_resid<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, r64, rk, mask);
+}
+template <typename R>
+void launch_restart_dirs(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* rh, cpx<R>* p, cpx<R>* v,
+                         const int* mask) {
+    hipLaunchKernelGGL(k_restart_dirs<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, r, rh, p, v, mask);
+}
+template void launch_fold_x<float>(dd_ctx*, int, int, cpx<double>*, cpx<float>*, const int*);
+template void launch_set_resid<float>(dd_ctx*, int, int, const cpx<double>*, cpx<float>*, const int*);
+template void launch_set_resid<double>(dd_ctx*, int, int, const cpx<double>*, cpx<double>*, const int*);
+template void launch_restart_dirs<float>(dd_ctx*, int, int, const cpx<float>*, cpx<float>*, cpx<float>*, cpx<float>*,
+                                         const int*);
+template void launch_restart_dirs<double>(dd_ctx*, int, int, const cpx<double>*, cpx<double>*, cpx<double>*,
+                                          cpx<double>*, const int*);
+
+template <typename R>
+void launch_cg_shift(dd_ctx* c, int n, int ncol, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask) {
+    hipLaunchKernelGGL(k_cg_shift<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, p, z, t, mask);
+}
+template void launch_cg_shift<float>(dd_ctx*, int, int, cpx<float>*, cpx<float>*, const cpx<float>*, const int*);
+template void launch_cg_shift<double>(dd_ctx*, int, int, cpx<double>*, cpx<double>*, const cpx<double>*, const int*);
 
 #define DD_INST(R)                                                                                           \
     template void launch_bicg_p<R>(dd_ctx*, int, int, const cpx<R>*, cpx<R>*, const cpx<R>*, const ColState*); \

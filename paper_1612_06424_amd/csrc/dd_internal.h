@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,14 @@ struct Buffer {
     size_t bytes = 0;
 };
 
+// Launch shape of the time-sweep stencil: workgroup size (spatial sites),
+// time-chunk length and whether workgroups are remapped to XCD-contiguous ranges.
+struct StencilSched {
+    int nt = 128;
+    int tc = 8;
+    int remap = 0;
+};
+
 struct TimedLaunch {
     hipEvent_t start, stop;
     int kind;
@@ -114,6 +123,9 @@ struct dd_ctx {
     double t_ms[2] = {0, 0};
     long long t_count[2] = {0, 0};
     double t_bytes[2] = {0, 0};
+    // autotuned stencil launch shapes, keyed by (precision, ncol, geometry)
+    std::map<std::string, dd::StencilSched> sched;
+    int autotune = 1;
     // pinned host mirrors of per-column state and of small reductions
     dd::ColState* host_state = nullptr;
     double* host_dots = nullptr;
@@ -162,6 +174,15 @@ void launch_dslash(dd_ctx* c, const Geo& g, const cpx<R>* U, double kappa, int d
                    const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol,
                    double* partial, const ColState* state);
 
+// Number of partial-sum slots per column written by one stencil launch.
+StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol);
+int stencil_slots(dd_ctx* c, const Geo& g, int kind, int ncol);
+StencilSched default_sched(const Geo& g);
+int stencil_blocks(const Geo& g, const StencilSched& sc);
+template <typename R>
+void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const cpx<R>* U, double kappa,
+                         int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol,
+                         double* partial, const ColState* st);
 inline int site_blocks(int nsite) { return (nsite + kBlock - 1) / kBlock; }
 
 // ---------------------------------------------------------------- BLAS / reductions
@@ -201,11 +222,16 @@ void launch_finalize(dd_ctx* c, int fin, int ncol, int nsb, const double* partia
 
 template <typename R>
 void launch_copy_cols(dd_ctx* c, int n, int ncol, const cpx<R>* src, cpx<R>* dst, const ColState* st);
-void launch_to_f32_scaled(dd_ctx* c, int n, int ncol, const cpx<double>* src, cpx<float>* dst,
-                          const double* scale, const ColState* st);
-void launch_add_f32_scaled(dd_ctx* c, int n, int ncol, cpx<double>* x, const cpx<float>* e,
-                           const double* scale, const ColState* st);
 void launch_links_to_f32(dd_ctx* c, size_t n, const cpx<double>* src, cpx<float>* dst);
+template <typename R>
+void launch_fold_x(dd_ctx* c, int n, int ncol, cpx<double>* x, cpx<R>* xk, const int* mask);
+template <typename R>
+void launch_set_resid(dd_ctx* c, int n, int ncol, const cpx<double>* r64, cpx<R>* rk, const int* mask);
+template <typename R>
+void launch_cg_shift(dd_ctx* c, int n, int ncol, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask);
+template <typename R>
+void launch_restart_dirs(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* rh, cpx<R>* p, cpx<R>* v,
+                         const int* mask);
 template <typename R>
 void launch_gamma5(dd_ctx* c, int n, int ncol, const cpx<R>* in, cpx<R>* out);
 template <typename R>

@@ -6,17 +6,19 @@
 // one-workgroup finalize kernels, so iterations run without host round trips;
 // the host reads the per-column state every `check_every` iterations.
 //
-// Convergence is always confirmed on the true FP64 residual |b - D x| / |b|.
-// BiCGStab cycles restart from the true residual (new shadow residual r^ = r)
-// after a breakdown or when the recursive residual has drifted.
-//
-// DD_MIXED: defect correction.  The outer loop computes r = b - D x in FP64,
-// solves D e = r / |r| with FP32 links and FP32 vectors to a relative residual
-// inner_tol (inner products accumulated in FP64), and adds |r| e to x in FP64.
+// Both methods (BiCGStab on D, CGNR = CG on D^+ D) use reliable updates: the
+// Krylov recursion runs in precision R (FP64, or FP32 links and vectors for
+// DD_MIXED with inner products accumulated in FP64), and whenever a column's
+// recursive residual has dropped by the factor delta the correction is folded
+// into the FP64 solution and the recursive residual is replaced by the true
+// FP64 residual b - D x.  Convergence is always decided on that true residual.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "dd_internal.h"
 
@@ -82,115 +84,337 @@ dd_status residual_to_host(dd_ctx* c, const Geo& g, const cpx<double>* U, double
                            const cpx<double>* b, const cpx<double>* x, cpx<double>* r, double* partial,
                            double* dots) {
     launch_dslash<double>(c, g, U, kappa, dag, EPI_RESID, x, r, b, ncol, partial, nullptr);
-    launch_finalize(c, FIN_STORE, ncol, site_blocks(g.nsite), partial, nullptr, dots);
+    launch_finalize(c, FIN_STORE, ncol, stencil_slots(c, g, 0, ncol), partial, nullptr, dots);
     DD_HIP(c, hipGetLastError());
     DD_HIP(c, hipMemcpyAsync(c->host_dots, dots, sizeof(double) * 3 * ncol, hipMemcpyDeviceToHost, c->stream));
     DD_HIP(c, hipStreamSynchronize(c->stream));
     return DD_OK;
 }
 
-// BiCGStab iterations for every active column until all are inactive or the
-// budget is spent.  Returns the lockstep iteration count in *done.
+void reset_host_state(dd_ctx* c, int ncol) { std::memset(c->host_state, 0, sizeof(ColState) * ncol); }
+
+// BiCGStab with reliable updates (Sleijpen & van der Vorst, Computing 56 (1996)
+// 141): the Krylov vectors live in precision R; whenever a column's recursive
+// residual has dropped by delta below the largest one seen since its last
+// update, or the recursion claims convergence, or it broke down, the host
+//   - folds the accumulated correction into the FP64 solution (R = float),
+//   - recomputes the true residual r = b - D x in FP64,
+//   - finishes the column if |r|/|b| <= tol, otherwise replaces the recursive
+//     residual by the true one and continues with the same search directions
+//     (a breakdown also takes a fresh shadow residual r^ = r).
+// Iteration counts are not inflated by restarts and the answer is checked in
+// FP64.  For R = double the correction goes straight into x.
 template <typename R>
-dd_status bicgstab_iterate(dd_ctx* c, const Geo& g, const cpx<R>* U, double kappa, int dag, int ncol,
-                           cpx<R>* x, const Vecs<R>& w, ColState* st, double* partial, int check_every,
-                           int budget, int* done) {
+dd_status bicgstab_reliable(dd_ctx* c, const Geo& g, const cpx<double>* U64, const cpx<R>* UK, double kappa,
+                            int dag, int ncol, const cpx<double>* b, cpx<double>* x, const std::vector<double>& bb,
+                            const dd_solver_params& p, double delta, const Vecs<R>& w, cpx<R>* xk,
+                            cpx<double>* r64, ColState* st, double* partial, double* dots, int* mask_dev,
+                            std::vector<double>& rel, int* total_out, int* updates_out, int* restarts_out, bool* nonfinite) {
     const int n = 12 * g.nsite;
-    const int nsb = site_blocks(g.nsite);
+    const size_t ntot = (size_t)n * ncol;
+    const bool fold = !std::is_same<R, double>::value;
+    const int check_every = p.check_every > 0 ? p.check_every : 8;
+    const int nsb = stencil_slots(c, g, sizeof(R) == 8 ? 0 : 1, ncol);
     const int nbe = (n + kBlock - 1) / kBlock;
-    int it = 0;
-    *done = 0;
-    while (it < budget) {
-        const int k = std::min(check_every, budget - it);
-        for (int j = 0; j < k; j++) {
+    const double tol = p.tol;
+    cpx<R>* xx = fold ? xk : reinterpret_cast<cpx<R>*>(x);
+    dd_status e;
+    launch_zero<double>(c, ntot, x);
+    if (fold) launch_zero<R>(c, ntot, xk);
+    e = residual_to_host(c, g, U64, kappa, dag, ncol, b, x, r64, partial, dots);
+    if (e != DD_OK) return e;
+    std::vector<int> done(ncol, 0), mask(ncol, 0), it_upd(ncol, 0);
+    std::vector<double> rrmax(ncol, 0.0), rrupd(ncol, 0.0);
+    int ndone = 0;
+    reset_host_state(c, ncol);
+    for (int j = 0; j < ncol; j++) {
+        const double rr = c->host_dots[3 * j];
+        if (!std::isfinite(rr)) *nonfinite = true;
+        rel[j] = bb[j] > 0 ? std::sqrt(rr / bb[j]) : 0.0;
+        done[j] = (bb[j] == 0 || rel[j] <= tol) ? 1 : 0;
+        ndone += done[j];
+        mask[j] = done[j] ? 0 : 2;
+        ColState& s = c->host_state[j];
+        s.active = !done[j];
+        s.rho_re = rr;
+        s.alpha_re = s.omega_re = 1.0;
+        s.rr = rr;
+        s.rh2 = rr;
+        s.bb = bb[j];
+        s.stop2 = 0.25 * tol * tol * bb[j];
+        rrmax[j] = rr;
+        rrupd[j] = rr;
+    }
+    if (*nonfinite) return DD_OK;
+    int total = 0, updates = 0;
+    if (ndone < ncol) {
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        launch_set_resid<R>(c, n, ncol, r64, w.r, mask_dev);
+        launch_restart_dirs<R>(c, n, ncol, w.r, w.rh, w.p, w.v, mask_dev);
+        e = push_state(c, st, ncol);
+        if (e != DD_OK) return e;
+        DD_HIP(c, hipStreamSynchronize(c->stream));  // mask.data() is pageable host memory
+    }
+    while (ndone < ncol && total < p.max_iter) {
+        const int k = std::min(check_every, p.max_iter - total);
+        for (int it = 0; it < k; it++) {
             launch_bicg_p<R>(c, n, ncol, w.r, w.p, w.v, st);
-            launch_dslash<R>(c, g, U, kappa, dag, EPI_DOT_AUX, w.p, w.v, w.rh, ncol, partial, st);
+            launch_dslash<R>(c, g, UK, kappa, dag, EPI_DOT_AUX, w.p, w.v, w.rh, ncol, partial, st);
             launch_finalize(c, FIN_ALPHA, ncol, nsb, partial, st, nullptr);
             launch_bicg_s<R>(c, n, ncol, w.r, w.v, w.s, st);
-            launch_dslash<R>(c, g, U, kappa, dag, EPI_TS, w.s, w.t, nullptr, ncol, partial, st);
+            launch_dslash<R>(c, g, UK, kappa, dag, EPI_TS, w.s, w.t, nullptr, ncol, partial, st);
             launch_finalize(c, FIN_OMEGA, ncol, nsb, partial, st, nullptr);
-            launch_bicg_xr<R>(c, n, ncol, x, w.r, w.p, w.s, w.t, w.rh, partial, st);
+            launch_bicg_xr<R>(c, n, ncol, xx, w.r, w.p, w.s, w.t, w.rh, partial, st);
             launch_finalize(c, FIN_RHO, ncol, nbe, partial, st, nullptr);
         }
-        it += k;
-        dd_status e = pull_state(c, st, ncol);
+        e = pull_state(c, st, ncol);
         if (e != DD_OK) return e;
-        int any = 0, mx = 0;
+        int mx = 0, ntrig = 0;
         for (int j = 0; j < ncol; j++) {
-            any |= c->host_state[j].active;
             mx = std::max(mx, c->host_state[j].iters);
+            mask[j] = 0;
+            if (done[j]) continue;
+            const ColState& s = c->host_state[j];
+            if (s.breakdown == 2) {
+                *nonfinite = true;
+                break;
+            }
+            // A low-precision recursion can lose bi-orthogonality and drift up or
+            // stall; such a column restarts (fresh shadow residual) from the true
+            // residual: 100x above the last update, or 400 iterations with less
+            // than a factor 2 of progress.
+            const bool diverged = s.rr > 1e4 * rrupd[j];
+            const bool stalled = s.iters - it_upd[j] > 400 && s.rr > 0.25 * rrupd[j];
+            if (s.breakdown || diverged || stalled) {
+                mask[j] = 2;
+                (*restarts_out)++;
+            }
+            else if (!s.active || s.rr <= delta * delta * rrmax[j]) mask[j] = 1;
+            else rrmax[j] = std::max(rrmax[j], s.rr);
+            ntrig += mask[j] != 0;
         }
-        *done = mx;
-        if (!any) break;
+        total = std::max(total + 1, mx);
+        if (*nonfinite) break;
+        if (ntrig == 0) continue;
+        // reliable update of the triggered columns
+        updates++;
+        static const bool dbg = std::getenv("DD_DEBUG") != nullptr;
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        if (fold) launch_fold_x<R>(c, n, ncol, x, xk, mask_dev);
+        e = residual_to_host(c, g, U64, kappa, dag, ncol, b, x, r64, partial, dots);
+        if (e != DD_OK) return e;
+        for (int j = 0; j < ncol; j++) {
+            if (!mask[j]) continue;
+            const double rr = c->host_dots[3 * j];
+            ColState& s = c->host_state[j];
+            if (!std::isfinite(rr)) {
+                *nonfinite = true;
+                break;
+            }
+            rel[j] = std::sqrt(rr / bb[j]);
+            if (dbg)
+                std::fprintf(stderr, "[dd] it %d col %d update type %d: recursive %.3e true %.3e (rrmax %.3e)\n", total, j,
+                             mask[j], std::sqrt(s.rr / bb[j]), rel[j], std::sqrt(rrmax[j] / bb[j]));
+            if (rel[j] <= tol) {
+                done[j] = 1;
+                ndone++;
+                s.active = 0;
+                mask[j] = 0;
+                continue;
+            }
+            s.active = 1;
+            s.rr = rr;
+            rrmax[j] = rr;
+            rrupd[j] = rr;
+            it_upd[j] = s.iters;
+            if (mask[j] == 2) {  // breakdown / drift: fresh shadow residual, directions reset
+                s.breakdown = 0;
+                s.rho_re = rr;
+                s.rho_im = 0;
+                s.rh2 = rr;
+                s.alpha_re = s.omega_re = 1.0;
+                s.alpha_im = s.omega_im = 0.0;
+                s.beta_re = s.beta_im = 0.0;
+            }
+        }
+        if (*nonfinite) break;
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        launch_set_resid<R>(c, n, ncol, r64, w.r, mask_dev);
+        launch_restart_dirs<R>(c, n, ncol, w.r, w.rh, w.p, w.v, mask_dev);
+        e = push_state(c, st, ncol);
+        if (e != DD_OK) return e;
+        DD_HIP(c, hipStreamSynchronize(c->stream));
     }
+    // whatever the exit, x must hold the full correction and rel the true residuals
+    if (fold) {
+        for (int j = 0; j < ncol; j++) mask[j] = 1;
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        launch_fold_x<R>(c, n, ncol, x, xk, mask_dev);
+    }
+    e = residual_to_host(c, g, U64, kappa, dag, ncol, b, x, r64, partial, dots);
+    if (e != DD_OK) return e;
+    for (int j = 0; j < ncol; j++) {
+        const double rr = c->host_dots[3 * j];
+        if (!std::isfinite(rr)) *nonfinite = true;
+        rel[j] = bb[j] > 0 ? std::sqrt(rr / bb[j]) : 0.0;
+    }
+    *total_out = total;
+    *updates_out = updates;
     return DD_OK;
 }
 
-// CGNR iterations (CG on A^+ A) for every active column.  Expects r = b - A x,
-// z = A^+ r, p = z and zz set.
+
+// CGNR (CG on A^+ A x = A^+ b) with reliable updates: the Krylov vectors live in
+// precision R; when a column's residual has dropped by delta, or the recursion
+// stopped, the host folds the correction into the FP64 solution, recomputes the
+// true FP64 residual r = b - A x, replaces the recursive r, recomputes
+// z = A^+ r and shifts the search direction by the change of z
+// (p <- p + z_new - z_old, which keeps its conjugate history).
 template <typename R>
-dd_status cgnr_iterate(dd_ctx* c, const Geo& g, const cpx<R>* U, double kappa, int dag, int ncol, cpx<R>* x,
-                       const Vecs<R>& w, ColState* st, double* partial, int check_every, int budget,
-                       int* done) {
+dd_status cgnr_reliable(dd_ctx* c, const Geo& g, const cpx<double>* U64, const cpx<R>* UK, double kappa, int dag,
+                        int ncol, const cpx<double>* b, cpx<double>* x, const std::vector<double>& bb,
+                        const dd_solver_params& p, double delta, const Vecs<R>& w, cpx<R>* xk, cpx<double>* r64,
+                        ColState* st, double* partial, double* dots, int* mask_dev, std::vector<double>& rel,
+                        int* total_out, int* updates_out, int* restarts_out, bool* nonfinite) {
     const int n = 12 * g.nsite;
-    const int nsb = site_blocks(g.nsite);
+    const size_t ntot = (size_t)n * ncol;
+    const bool fold = !std::is_same<R, double>::value;
+    const int check_every = p.check_every > 0 ? p.check_every : 8;
+    const int nsb = stencil_slots(c, g, sizeof(R) == 8 ? 0 : 1, ncol);
     const int nbe = (n + kBlock - 1) / kBlock;
+    const double tol = p.tol;
+    cpx<R>* xx = fold ? xk : reinterpret_cast<cpx<R>*>(x);
     cpx<R>* r = w.r;
-    cpx<R>* p = w.p;
+    cpx<R>* pp = w.p;
     cpx<R>* wv = w.v;
     cpx<R>* z = w.s;
-    int it = 0;
-    *done = 0;
-    while (it < budget) {
-        const int k = std::min(check_every, budget - it);
-        for (int j = 0; j < k; j++) {
-            launch_dslash<R>(c, g, U, kappa, dag, EPI_NORM, p, wv, nullptr, ncol, partial, st);
-            launch_finalize(c, FIN_CG_ALPHA, ncol, nsb, partial, st, nullptr);
-            launch_cg_xr<R>(c, n, ncol, x, r, p, wv, partial, st);
-            launch_finalize(c, FIN_CG_RR, ncol, nbe, partial, st, nullptr);
-            launch_dslash<R>(c, g, U, kappa, 1 - dag, EPI_NORM, r, z, nullptr, ncol, partial, st);
-            launch_finalize(c, FIN_CG_BETA, ncol, nsb, partial, st, nullptr);
-            launch_cg_p<R>(c, n, ncol, p, z, st);
-        }
-        it += k;
-        dd_status e = pull_state(c, st, ncol);
-        if (e != DD_OK) return e;
-        int any = 0, mx = 0;
-        for (int j = 0; j < ncol; j++) {
-            any |= c->host_state[j].active;
-            mx = std::max(mx, c->host_state[j].iters);
-        }
-        *done = mx;
-        if (!any) break;
-    }
-    return DD_OK;
-}
-
-// Start a Krylov cycle on the device for the columns flagged active in
-// host_state (stop2 holds the relative stopping factor): r already holds the
-// system's residual; sets r^ = r, p = v = 0 (BiCGStab) or z = A^+ r, p = z (CGNR).
-template <typename R>
-dd_status start_cycle(dd_ctx* c, const Geo& g, const cpx<R>* U, double kappa, int dag, int ncol, int kind,
-                      const Vecs<R>& w, ColState* st, double* partial) {
-    const int n = 12 * g.nsite;
-    dd_status e = push_state(c, st, ncol);
+    cpx<R>* tz = w.t;
+    dd_status e;
+    launch_zero<double>(c, ntot, x);
+    if (fold) launch_zero<R>(c, ntot, xk);
+    e = residual_to_host(c, g, U64, kappa, dag, ncol, b, x, r64, partial, dots);
     if (e != DD_OK) return e;
-    launch_norm2<R>(c, n, ncol, w.r, partial);
-    launch_finalize(c, FIN_INIT, ncol, (n + kBlock - 1) / kBlock, partial, st, nullptr);
-    if (kind == DD_BICGSTAB) {
-        launch_copy_cols<R>(c, n, ncol, w.r, w.rh, st);
-        launch_zero<R>(c, (size_t)n * ncol, w.p);
-        launch_zero<R>(c, (size_t)n * ncol, w.v);
-    } else {
-        launch_dslash<R>(c, g, U, kappa, 1 - dag, EPI_NORM, w.r, w.s, nullptr, ncol, partial, st);
-        launch_finalize(c, FIN_CG_ZZ, ncol, site_blocks(g.nsite), partial, st, nullptr);
-        launch_copy_cols<R>(c, n, ncol, w.s, w.p, st);
+    std::vector<int> done(ncol, 0), mask(ncol, 0);
+    std::vector<double> rrmax(ncol, 0.0);
+    int ndone = 0;
+    reset_host_state(c, ncol);
+    for (int j = 0; j < ncol; j++) {
+        const double rr = c->host_dots[3 * j];
+        if (!std::isfinite(rr)) *nonfinite = true;
+        rel[j] = bb[j] > 0 ? std::sqrt(rr / bb[j]) : 0.0;
+        done[j] = (bb[j] == 0 || rel[j] <= tol) ? 1 : 0;
+        ndone += done[j];
+        mask[j] = !done[j];
+        ColState& s = c->host_state[j];
+        s.active = !done[j];
+        s.rr = rr;
+        s.bb = bb[j];
+        s.stop2 = 0.25 * tol * tol * bb[j];
+        rrmax[j] = rr;
     }
-    DD_HIP(c, hipGetLastError());
+    if (*nonfinite) return DD_OK;
+    int total = 0, updates = 0;
+    if (ndone < ncol) {
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        launch_set_resid<R>(c, n, ncol, r64, r, mask_dev);
+        e = push_state(c, st, ncol);
+        if (e != DD_OK) return e;
+        launch_dslash<R>(c, g, UK, kappa, 1 - dag, EPI_NORM, r, z, nullptr, ncol, partial, st);
+        launch_finalize(c, FIN_CG_ZZ, ncol, nsb, partial, st, nullptr);
+        launch_copy_cols<R>(c, n, ncol, z, pp, st);
+        DD_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    while (ndone < ncol && total < p.max_iter) {
+        const int k = std::min(check_every, p.max_iter - total);
+        for (int it = 0; it < k; it++) {
+            launch_dslash<R>(c, g, UK, kappa, dag, EPI_NORM, pp, wv, nullptr, ncol, partial, st);
+            launch_finalize(c, FIN_CG_ALPHA, ncol, nsb, partial, st, nullptr);
+            launch_cg_xr<R>(c, n, ncol, xx, r, pp, wv, partial, st);
+            launch_finalize(c, FIN_CG_RR, ncol, nbe, partial, st, nullptr);
+            launch_dslash<R>(c, g, UK, kappa, 1 - dag, EPI_NORM, r, z, nullptr, ncol, partial, st);
+            launch_finalize(c, FIN_CG_BETA, ncol, nsb, partial, st, nullptr);
+            launch_cg_p<R>(c, n, ncol, pp, z, st);
+        }
+        e = pull_state(c, st, ncol);
+        if (e != DD_OK) return e;
+        int mx = 0, ntrig = 0;
+        for (int j = 0; j < ncol; j++) {
+            mx = std::max(mx, c->host_state[j].iters);
+            mask[j] = 0;
+            if (done[j]) continue;
+            const ColState& s = c->host_state[j];
+            if (s.breakdown == 2) {
+                *nonfinite = true;
+                break;
+            }
+            if (s.breakdown) (*restarts_out)++;
+            if (s.breakdown || !s.active || s.rr <= delta * delta * rrmax[j]) mask[j] = 1;
+            else rrmax[j] = std::max(rrmax[j], s.rr);
+            ntrig += mask[j];
+        }
+        total = std::max(total + 1, mx);
+        if (*nonfinite) break;
+        if (ntrig == 0) continue;
+        updates++;
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        if (fold) launch_fold_x<R>(c, n, ncol, x, xk, mask_dev);
+        e = residual_to_host(c, g, U64, kappa, dag, ncol, b, x, r64, partial, dots);
+        if (e != DD_OK) return e;
+        std::vector<int> keep_active(ncol, 0);
+        for (int j = 0; j < ncol; j++) {
+            ColState& s = c->host_state[j];
+            keep_active[j] = (!done[j] && !mask[j]) ? s.active : 0;
+            if (!mask[j]) continue;
+            const double rr = c->host_dots[3 * j];
+            if (!std::isfinite(rr)) {
+                *nonfinite = true;
+                break;
+            }
+            rel[j] = std::sqrt(rr / bb[j]);
+            if (rel[j] <= tol) {
+                done[j] = 1;
+                ndone++;
+                mask[j] = 0;
+                s.active = 0;
+                continue;
+            }
+            s.rr = rr;
+            s.breakdown = 0;
+            rrmax[j] = rr;
+        }
+        if (*nonfinite) break;
+        // recompute z = A^+ r for the updated columns only: mark them active
+        for (int j = 0; j < ncol; j++) c->host_state[j].active = mask[j];
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        launch_set_resid<R>(c, n, ncol, r64, r, mask_dev);
+        e = push_state(c, st, ncol);
+        if (e != DD_OK) return e;
+        launch_dslash<R>(c, g, UK, kappa, 1 - dag, EPI_NORM, r, tz, nullptr, ncol, partial, st);
+        launch_finalize(c, FIN_CG_ZZ, ncol, nsb, partial, st, nullptr);
+        launch_cg_shift<R>(c, n, ncol, pp, z, tz, mask_dev);
+        e = pull_state(c, st, ncol);  // picks up the new zz
+        if (e != DD_OK) return e;
+        for (int j = 0; j < ncol; j++) c->host_state[j].active = mask[j] ? 1 : keep_active[j];
+        e = push_state(c, st, ncol);
+        if (e != DD_OK) return e;
+        DD_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    if (fold) {
+        for (int j = 0; j < ncol; j++) mask[j] = 1;
+        DD_HIP(c, hipMemcpyAsync(mask_dev, mask.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, c->stream));
+        launch_fold_x<R>(c, n, ncol, x, xk, mask_dev);
+    }
+    e = residual_to_host(c, g, U64, kappa, dag, ncol, b, x, r64, partial, dots);
+    if (e != DD_OK) return e;
+    for (int j = 0; j < ncol; j++) {
+        const double rr = c->host_dots[3 * j];
+        if (!std::isfinite(rr)) *nonfinite = true;
+        rel[j] = bb[j] > 0 ? std::sqrt(rr / bb[j]) : 0.0;
+    }
+    *total_out = total;
+    *updates_out = updates;
     return DD_OK;
 }
-
-void reset_host_state(dd_ctx* c, int ncol) { std::memset(c->host_state, 0, sizeof(ColState) * ncol); }
 
 }  // namespace
 
@@ -200,13 +424,16 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
     const auto t_start = std::chrono::steady_clock::now();
     const int n = 12 * g.nsite;
     const size_t ntot = (size_t)n * ncol;
-    const int check_every = p.check_every > 0 ? p.check_every : 8;
     const int kind = p.solver;
     dd_status e = DD_OK;
     e = ensure_host(c, ncol);
     if (e != DD_OK) return e;
 
-    const size_t npart = (size_t)ncol * ((n + kBlock - 1) / kBlock) * 3;
+    // partial-sum slots: the larger of the vector kernels' and the stencils' counts
+    int slots = (n + kBlock - 1) / kBlock;
+    slots = std::max(slots, stencil_slots(c, g, 0, ncol));
+    if (p.prec == DD_MIXED) slots = std::max(slots, stencil_slots(c, g, 1, ncol));
+    const size_t npart = (size_t)ncol * slots * 3;
     double* partial = (double*)workspace(c, W_PART, npart * sizeof(double), &e);
     if (e != DD_OK) return e;
     ColState* st = (ColState*)workspace(c, W_STATE, sizeof(ColState) * ncol, &e);
@@ -219,7 +446,6 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
 
     Vecs<float> w32{};
     cpx<float>*U32 = nullptr, *x32 = nullptr;
-    double *scale_dn = nullptr, *scale_up = nullptr;
     if (p.prec == DD_MIXED) {
         e = get_vecs<float>(c, ntot, &w32);
         if (e != DD_OK) return e;
@@ -227,10 +453,6 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
         U32 = (cpx<float>*)workspace(c, W_U32, nl * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
         x32 = (cpx<float>*)workspace(c, W_X32, ntot * sizeof(cpx<float>), &e);
-        if (e != DD_OK) return e;
-        scale_dn = (double*)workspace(c, W_AUX0, sizeof(double) * ncol, &e);
-        if (e != DD_OK) return e;
-        scale_up = (double*)workspace(c, W_AUX1, sizeof(double) * ncol, &e);
         if (e != DD_OK) return e;
         launch_links_to_f32(c, nl, U, U32);
     }
@@ -247,80 +469,29 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
     int total = 0, outer = 0, restarts = 0;
     bool converged = false, nonfinite = false;
     const double tol = p.tol;
-    while (true) {
-        // true residual r = b - A x in FP64
-        e = residual_to_host(c, g, U, kappa, dag, ncol, b, x, w64.r, partial, dots);
+    {
+        int* mask_dev = (int*)workspace(c, W_AUX4, sizeof(int) * ncol, &e);
         if (e != DD_OK) return e;
-        int nact = 0;
-        std::vector<int> act(ncol, 0);
-        for (int j = 0; j < ncol; j++) {
-            const double rr = c->host_dots[3 * j];
-            if (!std::isfinite(rr)) nonfinite = true;
-            rel[j] = bb[j] > 0 ? std::sqrt(rr / bb[j]) : 0.0;
-            act[j] = (bb[j] > 0 && !(rel[j] <= tol)) ? 1 : 0;
-            nact += act[j];
-        }
-        if (nonfinite) break;
-        if (nact == 0) {
-            converged = true;
-            break;
-        }
-        if (total >= p.max_iter || (p.prec == DD_MIXED && outer >= p.max_outer)) break;
-        reset_host_state(c, ncol);
-        if (p.prec != DD_MIXED) {
-            // FP64 Krylov cycle from the true residual
-            for (int j = 0; j < ncol; j++) {
-                c->host_state[j].active = act[j];
-                c->host_state[j].bb = bb[j];
-                c->host_state[j].stop2 = 0.25 * tol * tol * bb[j] / std::max(c->host_dots[3 * j], 1e-300);
-            }
-            e = start_cycle<double>(c, g, U, kappa, dag, ncol, kind, w64, st, partial);
-            if (e != DD_OK) return e;
-            int done = 0;
-            if (kind == DD_BICGSTAB)
-                e = bicgstab_iterate<double>(c, g, U, kappa, dag, ncol, x, w64, st, partial, check_every,
-                                             p.max_iter - total, &done);
-            else
-                e = cgnr_iterate<double>(c, g, U, kappa, dag, ncol, x, w64, st, partial, check_every,
-                                         p.max_iter - total, &done);
-            if (e != DD_OK) return e;
-            total += done;
-            for (int j = 0; j < ncol; j++)
-                if (c->host_state[j].breakdown == 2) nonfinite = true;
-            if (nonfinite) break;
-            restarts += outer > 0 ? 1 : 0;
-            outer++;
-        } else {
-            // defect correction: e = A32^-1 (r / |r|), x += |r| e
-            std::vector<double> dn(ncol), up(ncol);
-            for (int j = 0; j < ncol; j++) {
-                const double rn = std::sqrt(c->host_dots[3 * j]);
-                dn[j] = act[j] ? 1.0 / rn : 0.0;
-                up[j] = act[j] ? rn : 0.0;
-                c->host_state[j].active = act[j];
-                c->host_state[j].bb = 1.0;
-                c->host_state[j].stop2 = p.inner_tol * p.inner_tol;
-            }
-            DD_HIP(c, hipMemcpyAsync(scale_dn, dn.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, c->stream));
-            DD_HIP(c, hipMemcpyAsync(scale_up, up.data(), sizeof(double) * ncol, hipMemcpyHostToDevice, c->stream));
-            launch_to_f32_scaled(c, n, ncol, w64.r, w32.r, scale_dn, nullptr);
-            launch_zero<float>(c, ntot, x32);
-            e = start_cycle<float>(c, g, U32, kappa, dag, ncol, kind, w32, st, partial);
-            if (e != DD_OK) return e;
-            int done = 0;
-            if (kind == DD_BICGSTAB)
-                e = bicgstab_iterate<float>(c, g, U32, kappa, dag, ncol, x32, w32, st, partial, check_every,
-                                            p.max_iter - total, &done);
-            else
-                e = cgnr_iterate<float>(c, g, U32, kappa, dag, ncol, x32, w32, st, partial, check_every,
-                                        p.max_iter - total, &done);
-            if (e != DD_OK) return e;
-            total += done;
-            launch_add_f32_scaled(c, n, ncol, x, x32, scale_up, nullptr);
-            // The scales live in pageable host vectors: make sure the copies are done.
-            DD_HIP(c, hipStreamSynchronize(c->stream));
-            outer++;
-        }
+        cpx<double>* r64 = (cpx<double>*)workspace(c, W_RES64, ntot * sizeof(cpx<double>), &e);
+        if (e != DD_OK) return e;
+        // reliable-update threshold: inner_tol for DD_MIXED, 0.1 for FP64
+        const double delta = p.prec == DD_MIXED ? p.inner_tol : 0.1;
+        if (kind == DD_BICGSTAB && p.prec == DD_MIXED)
+            e = bicgstab_reliable<float>(c, g, U, U32, kappa, dag, ncol, b, x, bb, p, delta, w32, x32, r64, st, partial,
+                                         dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+        else if (kind == DD_BICGSTAB)
+            e = bicgstab_reliable<double>(c, g, U, U, kappa, dag, ncol, b, x, bb, p, delta, w64, nullptr, r64, st,
+                                          partial, dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+        else if (p.prec == DD_MIXED)
+            e = cgnr_reliable<float>(c, g, U, U32, kappa, dag, ncol, b, x, bb, p, delta, w32, x32, r64, st, partial,
+                                     dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+        else
+            e = cgnr_reliable<double>(c, g, U, U, kappa, dag, ncol, b, x, bb, p, delta, w64, nullptr, r64, st, partial,
+                                      dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+        if (e != DD_OK) return e;
+        converged = !nonfinite;
+        for (int j = 0; j < ncol; j++)
+            if (!(rel[j] <= tol)) converged = false;
     }
     if (stats) {
         stats->nrhs = ncol;

@@ -1,0 +1,96 @@
+// tune.hip -- per-context autotuner of the stencil launch shape.
+//
+// The best (workgroup size, time-chunk length, XCD remap) depends on the
+// precision, the number of columns and the lattice geometry (how many
+// workgroups are resident per XCD against how much of the 4 MB L2 one time
+// slice of them touches).  The first launch for a new key times every
+// candidate on scratch buffers of the same size and keeps the fastest; later
+// launches reuse it.  Small problems use the default shape untimed.
+#include <chrono>
+#include <cstdio>
+#include <string>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+namespace {
+
+std::string key_of(const Geo& g, int kind, int ncol) {
+    return std::to_string(kind) + ":" + std::to_string(ncol) + ":" + std::to_string(g.L) + ":" +
+           std::to_string(g.T) + ":" + std::to_string(g.nt) + ":" + std::to_string(g.whole);
+}
+
+template <typename R>
+StencilSched tune(dd_ctx* c, const Geo& g, int ncol) {
+    StencilSched best = default_sched(g);
+    const size_t nf = (size_t)ncol * 12 * g.nsite, nl = (size_t)36 * g.vlink;
+    cpx<R>*in = nullptr, *out = nullptr, *U = nullptr;
+    if (hipMalloc(&in, nf * sizeof(cpx<R>)) != hipSuccess || hipMalloc(&out, nf * sizeof(cpx<R>)) != hipSuccess ||
+        hipMalloc(&U, nl * sizeof(cpx<R>)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (in) (void)hipFree(in);
+        if (out) (void)hipFree(out);
+        if (U) (void)hipFree(U);
+        return best;
+    }
+    (void)hipMemsetAsync(in, 0, nf * sizeof(cpx<R>), c->stream);
+    (void)hipMemsetAsync(U, 0, nl * sizeof(cpx<R>), c->stream);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int saved_timing = c->timing;
+    c->timing = 0;
+    float best_ms = 1e30f;
+    const int tcs[] = {4, 8, 16, 1 << 20};
+    for (int nt : {128, 256})
+        for (int tcv : tcs)
+            for (int remap : {0, 1}) {
+                StencilSched sc;
+                sc.nt = nt;
+                sc.tc = tcv > g.nt ? g.nt : tcv;
+                sc.remap = remap;
+                if (tcv != sc.tc && tcv != (1 << 20)) continue;  // same as a shorter candidate
+                for (int w = 0; w < 2; w++)
+                    launch_dslash_sched<R>(c, g, sc, U, 0.125, 0, EPI_STORE, in, out, nullptr, ncol, nullptr, nullptr);
+                (void)hipEventRecord(e0, c->stream);
+                for (int r = 0; r < 3; r++)
+                    launch_dslash_sched<R>(c, g, sc, U, 0.125, 0, EPI_STORE, in, out, nullptr, ncol, nullptr, nullptr);
+                (void)hipEventRecord(e1, c->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = sc;
+                }
+            }
+    c->timing = saved_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    (void)hipFree(U);
+    (void)hipGetLastError();
+    return best;
+}
+
+}  // namespace
+
+StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol) {
+    const std::string k = key_of(g, kind, ncol);
+    auto it = c->sched.find(k);
+    if (it != c->sched.end()) return it->second;
+    StencilSched sc = default_sched(g);
+    if (c->autotune && (size_t)g.nsite * ncol >= ((size_t)1 << 18))
+        sc = kind == 0 ? tune<double>(c, g, ncol) : tune<float>(c, g, ncol);
+    c->sched[k] = sc;
+    return sc;
+}
+
+int stencil_slots(dd_ctx* c, const Geo& g, int kind, int ncol) {
+    return stencil_blocks(g, stencil_sched(c, g, kind, ncol));
+}
+
+}  // namespace dd
