@@ -60,7 +60,7 @@ typedef enum {
     DD_ERR_ARG = -1,         /* invalid argument (pointer, size, slab, parameter) */
     DD_ERR_HIP = -2,         /* a HIP runtime call failed */
     DD_ERR_NOMEM = -3,       /* workspace allocation failed */
-    DD_ERR_NOCONV = -4,      /* solver hit max_iter / max_outer; x holds the last iterate */
+    DD_ERR_NOCONV = -4,      /* solver hit max_iter; x holds the last iterate */
     DD_ERR_BREAKDOWN = -5,   /* non-finite values (NaN/Inf) in the iteration */
     DD_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
 } dd_status;
@@ -68,7 +68,7 @@ typedef enum {
 typedef enum {
     DD_FP64 = 0,   /* complex128 everywhere */
     DD_FP32 = 1,   /* complex64 (stencil entry points only) */
-    DD_MIXED = 2   /* solves: FP32 inner Krylov iterations, FP64 defect correction */
+    DD_MIXED = 2   /* solves: FP32 Krylov recursion, FP64 solution and reliable updates */
 } dd_precision;
 
 typedef enum {
@@ -85,21 +85,28 @@ typedef struct {
     int t0, nt;    /* time slab [t0, t0+nt) mod T, 1 <= nt < T */
 } dd_domain;
 
+/*
+ * Krylov solves (both methods, both precisions) run the recursion in the
+ * working precision and keep the solution in FP64.  A column takes a reliable
+ * update when its recursive residual has dropped by the factor delta since
+ * the last one (or the recursion stopped): the correction is folded into the
+ * FP64 solution and the recursive residual is replaced by the true FP64
+ * residual b - D x.  Convergence is decided on that true residual only.
+ */
 typedef struct {
     double tol;        /* stop when |b - D x| / |b| <= tol (true residual, FP64) per column */
-    int max_iter;      /* cap on Krylov iterations summed over restarts / inner solves */
+    int max_iter;      /* cap on Krylov iterations (lockstep over the columns) */
     int prec;          /* DD_FP64 or DD_MIXED */
-    double inner_tol;  /* DD_MIXED: relative residual reduction of each FP32 inner solve */
-    int max_outer;     /* DD_MIXED: cap on defect-correction cycles */
     int solver;        /* dd_solver_kind */
-    int check_every;   /* iterations between host-side convergence reads (0: library default) */
+    double delta;      /* reliable-update threshold in (0, 1); 0: 0.1 (DD_FP64), 0.01 (DD_MIXED) */
+    int check_every;   /* iterations between host-side convergence reads (0: 8) */
 } dd_solver_params;
 
 typedef struct {
     int nrhs;                           /* columns solved */
-    int iters;                          /* Krylov iterations (FP32 inner ones for DD_MIXED) */
-    int outer;                          /* defect-correction cycles (DD_MIXED), else 1 */
-    int restarts;                       /* BiCGStab restarts (breakdown or residual drift) */
+    int iters;                          /* Krylov iterations (lockstep over the columns) */
+    int updates;                        /* rounds of reliable updates */
+    int restarts;                       /* columns restarted after a breakdown or a stalled recursion */
     double true_rel_resid[DD_MAX_RHS];  /* final |b - D x| / |b| per column, FP64 */
     double ms;                          /* wall time of the call on the host clock */
 } dd_solve_stats;
@@ -224,13 +231,22 @@ dd_status dd_block_solve_batched(dd_ctx* ctx, int n, const dd_batch_item* items,
 
 /*
  * Kernel timing on the context stream.  With enable != 0 every stencil
- * launch made by the library is bracketed by HIP events; dd_kernel_timing
- * returns the summed milliseconds, launch count and algorithmic bytes
- * (V*(48*ncol + 72)*sizeof(real) per launch) since the last reset.
- * kind: 0 = FP64 stencil, 1 = FP32 stencil.
+ * launch made by the library is bracketed by HIP events recorded on the
+ * context stream; enabling or disabling resets the counters.  Launches are
+ * accumulated per kernel instance, named as a profiler names the template
+ * instance, e.g. "k_dslash<float, 1, 4, 128>" (real type, dagger, fused
+ * epilogue, work-group size).  For each instance dd_kernel_timing returns the
+ * summed milliseconds, the launch count and the summed algorithmic bytes
+ *     V * ((48 + e) * ncol + 72) * sizeof(real)   per launch,
+ * with e = 24 for the epilogues that read one more field.  index runs over
+ * [0, count) from dd_kernel_timing_count, in first-launch order; name
+ * receives at most name_len - 1 characters and a terminating zero.  Reading
+ * the counters waits for the context stream.
  */
 dd_status dd_set_kernel_timing(dd_ctx* ctx, int enable);
-dd_status dd_kernel_timing(dd_ctx* ctx, int kind, double* ms, long long* launches, double* bytes);
+dd_status dd_kernel_timing_count(dd_ctx* ctx, int* count);
+dd_status dd_kernel_timing(dd_ctx* ctx, int index, char* name, int name_len, double* ms, long long* launches,
+                           double* bytes);
 
 #ifdef __cplusplus
 }

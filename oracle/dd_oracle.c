@@ -35,6 +35,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -79,6 +82,16 @@ static void init_gamma(void)
 }
 
 /* Exported for the tests of the Clifford algebra: g[mu][4][4], mu=0..3, 4 = gamma_5. */
+/* Number of host threads the parallel loops below use. */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void ora_gamma(cplx *g)
 {
     init_gamma();

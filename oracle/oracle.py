@@ -42,6 +42,8 @@ _lib = None
 
 
 def _configure(L):
+    L.ora_threads.argtypes = []
+    L.ora_threads.restype = _c.c_int
     L.ora_gamma.argtypes = [_c.c_void_p]
     L.ora_block_apply.argtypes = [_c.c_int, _c.c_int, _c.c_int, _c.c_void_p, _c.c_double,
                                   _c.c_int, _c.c_int, _c.c_int, _c.c_int,
@@ -115,6 +117,11 @@ def block_apply(U, kappa, T, L, bc, dst, src, psi):
         lib().ora_block_apply(T, L, bc, _ptr(U), float(kappa), dt0, dnt, st0, snt,
                               _ptr(p[j]), _ptr(out[j]))
     return out[0] if one else out
+
+
+def threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(lib().ora_threads())
 
 
 def apply_dirac(U, kappa, T, L, bc, psi, dom=None):

@@ -79,8 +79,15 @@ void timing_begin(dd_ctx* c, hipEvent_t* ev) {
     *ev = a;
 }
 
-void timing_end(dd_ctx* c, hipEvent_t start, int kind, double bytes) {
+void timing_end(dd_ctx* c, hipEvent_t start, const std::string& name, double bytes) {
     if (start == nullptr) return;
+    int entry = -1;
+    for (size_t i = 0; i < c->timing_entries.size(); i++)
+        if (c->timing_entries[i].name == name) entry = (int)i;
+    if (entry < 0) {
+        c->timing_entries.push_back(TimingEntry{name, 0, 0, 0});
+        entry = (int)c->timing_entries.size() - 1;
+    }
     hipEvent_t b;
     if (!c->event_pool.empty()) {
         b = c->event_pool.back();
@@ -90,7 +97,7 @@ void timing_end(dd_ctx* c, hipEvent_t start, int kind, double bytes) {
         return;
     }
     (void)hipEventRecord(b, c->stream);
-    c->pending.push_back(TimedLaunch{start, b, kind, bytes});
+    c->pending.push_back(TimedLaunch{start, b, entry, bytes});
     if (c->pending.size() >= 4096) timing_harvest(c);
 }
 
@@ -100,9 +107,10 @@ void timing_harvest(dd_ctx* c) {
     for (auto& t : c->pending) {
         float ms = 0;
         if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
-            c->t_ms[t.kind] += ms;
-            c->t_count[t.kind] += 1;
-            c->t_bytes[t.kind] += t.bytes;
+            TimingEntry& te = c->timing_entries[t.entry];
+            te.ms += ms;
+            te.launches += 1;
+            te.bytes += t.bytes;
         }
         c->event_pool.push_back(t.start);
         c->event_pool.push_back(t.stop);
@@ -156,8 +164,7 @@ dd_status check_params(dd_ctx* c, const dd_solver_params* p) {
     if (!(p->tol > 0) || p->tol >= 1 || p->max_iter < 1)
         return fail(c, DD_ERR_ARG, "need 0 < tol < 1 and max_iter >= 1");
     if (p->prec != DD_FP64 && p->prec != DD_MIXED) return fail(c, DD_ERR_ARG, "solver prec must be DD_FP64 or DD_MIXED");
-    if (p->prec == DD_MIXED && (!(p->inner_tol > 0) || p->inner_tol >= 1 || p->max_outer < 1))
-        return fail(c, DD_ERR_ARG, "DD_MIXED needs 0 < inner_tol < 1 and max_outer >= 1");
+    if (!(p->delta >= 0) || p->delta >= 1) return fail(c, DD_ERR_ARG, "solver delta must lie in [0, 1)");
     if (p->solver != DD_BICGSTAB && p->solver != DD_CGNR) return fail(c, DD_ERR_ARG, "unknown solver kind");
     return DD_OK;
 }
@@ -446,7 +453,7 @@ dd_status dd_domain_action(dd_ctx* c, const void* U, double kappa, const dd_doma
     e = solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)Y, (cpx<double>*)X, *p, &s2, 0);
     if (stats) {
         stats->iters += s2.iters;
-        stats->outer += s2.outer;
+        stats->updates += s2.updates;
         stats->restarts += s2.restarts;
         stats->ms += s2.ms;
         for (int j = 0; j < nrhs; j++) stats->true_rel_resid[j] = std::max(stats->true_rel_resid[j], s2.true_rel_resid[j]);
@@ -492,19 +499,32 @@ dd_status dd_set_kernel_timing(dd_ctx* c, int enable) {
     if (c == nullptr) return DD_ERR_ARG;
     timing_harvest(c);
     c->timing = enable ? 1 : 0;
-    c->t_ms[0] = c->t_ms[1] = 0;
-    c->t_count[0] = c->t_count[1] = 0;
-    c->t_bytes[0] = c->t_bytes[1] = 0;
+    c->timing_entries.clear();
     return DD_OK;
 }
 
-dd_status dd_kernel_timing(dd_ctx* c, int kind, double* ms, long long* launches, double* bytes) {
-    if (c == nullptr) return DD_ERR_ARG;
-    if (kind < 0 || kind > 1) return fail(c, DD_ERR_ARG, "kind must be 0 (FP64) or 1 (FP32)");
+dd_status dd_kernel_timing_count(dd_ctx* c, int* count) {
+    if (c == nullptr || count == nullptr) return DD_ERR_ARG;
     timing_harvest(c);
-    if (ms) *ms = c->t_ms[kind];
-    if (launches) *launches = c->t_count[kind];
-    if (bytes) *bytes = c->t_bytes[kind];
+    *count = (int)c->timing_entries.size();
+    return DD_OK;
+}
+
+dd_status dd_kernel_timing(dd_ctx* c, int index, char* name, int name_len, double* ms, long long* launches,
+                           double* bytes) {
+    if (c == nullptr) return DD_ERR_ARG;
+    timing_harvest(c);
+    if (index < 0 || index >= (int)c->timing_entries.size())
+        return fail(c, DD_ERR_ARG, "timing index out of range");
+    const TimingEntry& te = c->timing_entries[index];
+    if (name != nullptr && name_len > 0) {
+        const size_t k = std::min((size_t)name_len - 1, te.name.size());
+        std::memcpy(name, te.name.data(), k);
+        name[k] = 0;
+    }
+    if (ms) *ms = te.ms;
+    if (launches) *launches = te.launches;
+    if (bytes) *bytes = te.bytes;
     return DD_OK;
 }
 

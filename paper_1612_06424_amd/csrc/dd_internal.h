@@ -104,8 +104,16 @@ struct StencilSched {
 
 struct TimedLaunch {
     hipEvent_t start, stop;
-    int kind;
+    int entry;  // index into dd_ctx::timing_entries
     double bytes;
+};
+
+// Accumulated HIP-event time of one kernel instance.
+struct TimingEntry {
+    std::string name;  // the instance as a profiler names it, e.g. "k_dslash<float, 1, 4, 128>"
+    double ms = 0;
+    long long launches = 0;
+    double bytes = 0;
 };
 
 }  // namespace dd
@@ -120,9 +128,7 @@ struct dd_ctx {
     int timing = 0;
     std::vector<dd::TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
-    double t_ms[2] = {0, 0};
-    long long t_count[2] = {0, 0};
-    double t_bytes[2] = {0, 0};
+    std::vector<dd::TimingEntry> timing_entries;
     // autotuned stencil launch shapes, keyed by (precision, ncol, geometry)
     std::map<std::string, dd::StencilSched> sched;
     int autotune = 1;
@@ -256,7 +262,7 @@ void launch_link_force(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* X,
 
 // ---------------------------------------------------------------- timing
 void timing_begin(dd_ctx* c, hipEvent_t* ev);
-void timing_end(dd_ctx* c, hipEvent_t ev, int kind, double bytes);
+void timing_end(dd_ctx* c, hipEvent_t ev, const std::string& name, double bytes);
 void timing_harvest(dd_ctx* c);
 
 // ---------------------------------------------------------------- solver

@@ -466,7 +466,7 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
         if (!std::isfinite(bb[j])) return fail(c, DD_ERR_BREAKDOWN, "non-finite values in the right-hand side");
     launch_zero<double>(c, ntot, x);
 
-    int total = 0, outer = 0, restarts = 0;
+    int total = 0, updates = 0, restarts = 0;
     bool converged = false, nonfinite = false;
     const double tol = p.tol;
     {
@@ -474,20 +474,19 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
         if (e != DD_OK) return e;
         cpx<double>* r64 = (cpx<double>*)workspace(c, W_RES64, ntot * sizeof(cpx<double>), &e);
         if (e != DD_OK) return e;
-        // reliable-update threshold: inner_tol for DD_MIXED, 0.1 for FP64
-        const double delta = p.prec == DD_MIXED ? p.inner_tol : 0.1;
+        const double delta = p.delta > 0 ? p.delta : (p.prec == DD_MIXED ? 0.01 : 0.1);
         if (kind == DD_BICGSTAB && p.prec == DD_MIXED)
             e = bicgstab_reliable<float>(c, g, U, U32, kappa, dag, ncol, b, x, bb, p, delta, w32, x32, r64, st, partial,
-                                         dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+                                         dots, mask_dev, rel, &total, &updates, &restarts, &nonfinite);
         else if (kind == DD_BICGSTAB)
             e = bicgstab_reliable<double>(c, g, U, U, kappa, dag, ncol, b, x, bb, p, delta, w64, nullptr, r64, st,
-                                          partial, dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+                                          partial, dots, mask_dev, rel, &total, &updates, &restarts, &nonfinite);
         else if (p.prec == DD_MIXED)
             e = cgnr_reliable<float>(c, g, U, U32, kappa, dag, ncol, b, x, bb, p, delta, w32, x32, r64, st, partial,
-                                     dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+                                     dots, mask_dev, rel, &total, &updates, &restarts, &nonfinite);
         else
             e = cgnr_reliable<double>(c, g, U, U, kappa, dag, ncol, b, x, bb, p, delta, w64, nullptr, r64, st, partial,
-                                      dots, mask_dev, rel, &total, &outer, &restarts, &nonfinite);
+                                      dots, mask_dev, rel, &total, &updates, &restarts, &nonfinite);
         if (e != DD_OK) return e;
         converged = !nonfinite;
         for (int j = 0; j < ncol; j++)
@@ -496,7 +495,7 @@ dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int
     if (stats) {
         stats->nrhs = ncol;
         stats->iters = total;
-        stats->outer = outer;
+        stats->updates = updates;
         stats->restarts = restarts;
         for (int j = 0; j < DD_MAX_RHS; j++) stats->true_rel_resid[j] = j < ncol ? rel[j] : 0.0;
         stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -35,7 +35,8 @@ DD_MAX_RHS = 12
 EXPORTS = [
     "dd_create", "dd_destroy", "dd_last_error", "dd_apply_dirac", "dd_frontier_hop", "dd_block_solve",
     "dd_factorized_propagator", "dd_pion_correlator", "dd_block_solve_backward", "dd_domain_action",
-    "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing",
+    "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing_count",
+    "dd_kernel_timing",
 ]
 
 
@@ -48,16 +49,16 @@ class dd_domain(C.Structure):
 
 
 class dd_solver_params(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("prec", C.c_int), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int), ("solver", C.c_int), ("check_every", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("prec", C.c_int), ("solver", C.c_int),
+                ("delta", C.c_double), ("check_every", C.c_int)]
 
 
 class dd_solve_stats(C.Structure):
-    _fields_ = [("nrhs", C.c_int), ("iters", C.c_int), ("outer", C.c_int), ("restarts", C.c_int),
+    _fields_ = [("nrhs", C.c_int), ("iters", C.c_int), ("updates", C.c_int), ("restarts", C.c_int),
                 ("true_rel_resid", C.c_double * DD_MAX_RHS), ("ms", C.c_double)]
 
     def as_dict(self):
-        return dict(nrhs=self.nrhs, iters=self.iters, outer=self.outer, restarts=self.restarts,
+        return dict(nrhs=self.nrhs, iters=self.iters, updates=self.updates, restarts=self.restarts,
                     true_rel_resid=list(self.true_rel_resid)[: self.nrhs], ms=self.ms)
 
 
@@ -86,7 +87,9 @@ _sig = {
     "dd_block_solve_batched": ([_vp, _i, C.POINTER(dd_batch_item), C.POINTER(dd_solver_params),
                                 C.POINTER(dd_solve_stats)], _i),
     "dd_set_kernel_timing": ([_vp, _i], _i),
-    "dd_kernel_timing": ([_vp, _i, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double)], _i),
+    "dd_kernel_timing_count": ([_vp, C.POINTER(C.c_int)], _i),
+    "dd_kernel_timing": ([_vp, _i, C.c_char_p, _i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                          C.POINTER(C.c_double)], _i),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -100,10 +103,9 @@ class DDError(RuntimeError):
         self.status = status
 
 
-def solver_params(tol=1e-10, max_iter=20000, prec=DD_FP64, inner_tol=1e-5, max_outer=50, solver=DD_BICGSTAB,
-                  check_every=0):
-    return dd_solver_params(float(tol), int(max_iter), int(prec), float(inner_tol), int(max_outer), int(solver),
-                            int(check_every))
+def solver_params(tol=1e-10, max_iter=20000, prec=DD_FP64, solver=DD_CGNR, delta=0.0, check_every=0):
+    """Solver parameters; delta = 0 takes the library's reliable-update threshold."""
+    return dd_solver_params(float(tol), int(max_iter), int(prec), int(solver), float(delta), int(check_every))
 
 
 def _dom(dom):
@@ -263,11 +265,18 @@ def set_kernel_timing(ctx, enable):
     ctx._check(_lib.dd_set_kernel_timing(ctx._h, int(bool(enable))))
 
 
-def kernel_timing(ctx, kind):
-    """(ms, launches, algorithmic bytes) of the stencil launches of kind 0 (FP64) or 1 (FP32)."""
-    ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
-    ctx._check(_lib.dd_kernel_timing(ctx._h, int(kind), C.byref(ms), C.byref(n), C.byref(b)))
-    return ms.value, n.value, b.value
+def kernel_timing(ctx):
+    """{kernel instance name: (ms, launches, algorithmic bytes)} of the stencil launches
+    timed with HIP events since timing was last switched."""
+    cnt = C.c_int()
+    ctx._check(_lib.dd_kernel_timing_count(ctx._h, C.byref(cnt)))
+    out = {}
+    for i in range(cnt.value):
+        name = C.create_string_buffer(128)
+        ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
+        ctx._check(_lib.dd_kernel_timing(ctx._h, i, name, 128, C.byref(ms), C.byref(n), C.byref(b)))
+        out[name.value.decode()] = (ms.value, n.value, b.value)
+    return out
 
 
 # ------------------------------------------------------------------ layout marshalling

@@ -33,7 +33,7 @@ def test_block_solve_vs_oracle(prec, solver, T, L, bc, dom, kappa, eps):
     assert st == 0
     ctx = dd.Context(T, L, bc)
     p = dd.solver_params(tol=1e-12 if prec == "fp64" else 1e-10, max_iter=20000,
-                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, inner_tol=1e-4, solver=solver)
+                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, solver=solver)
     x, stats = dd.block_solve(ctx, dd.pack_links(U), kappa, dd.pack_field(b), dom, p)
     got = dd.unpack_field(x)
     assert max(stats["true_rel_resid"]) <= p.tol
