@@ -41,7 +41,28 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,batched,force")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (10 times), the reference that scales "
+                         "the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+
+    n = 1 << 30
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 10
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms": round(ms, 4),
+                      "GBs": round(2 * n / ms / 1e6, 1)}), flush=True)
 
 
 def log(msg):
@@ -55,7 +76,10 @@ def main():
               "lattice is one time slab; see the design notes on sharding). Run with --gpus 1.", flush=True)
         sys.exit(2)
 
-    import numpy as np
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
     import torch
 
     import paper_1612_06424_amd.dd as dd

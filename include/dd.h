@@ -220,16 +220,32 @@ typedef struct {
 } dd_batch_item;
 
 /*
- * Solve every item of an uneven batch of independent domains (prec DD_MIXED
- * or DD_FP64, BiCGStab), all domains advancing together in shared launches
- * (each launch covers every active domain), with the FP32 inner iterations
- * captured once in a HIP graph and replayed.  stats: NULL or n entries.
+ * Solve every item of an uneven batch of independent domains (each item is
+ * its own lattice with its own links, kappa, time boundary and 1..12
+ * columns: many local Dirichlet problems of the decomposition of Sec. 3
+ * solved at once).  Every column of every item is
+ * advanced together: one launch of the multi-domain stencil and of each
+ * vector kernel covers all domains still iterating, the tile shape is tuned
+ * on the batch (and cached in the context for the same batch signature), and
+ * the inner iterations are captured once into a HIP graph and replayed on a
+ * library-owned stream that is ordered after ctx's stream.  Both methods and
+ * both precisions of dd_solver_params apply; convergence is per column on the
+ * true FP64 residual.  The context's own lattice is not used.
+ * items[i].U, .b, .x: device memory of the context's device, complex128,
+ * 16-byte aligned; b is not modified.  stats: NULL or n entries (iters: the
+ * most iterations of the item's columns; updates, restarts, ms: of the whole
+ * batch).  Returns DD_ERR_NOCONV if any column missed tol (all x written).
  * Synchronises.
  */
 dd_status dd_block_solve_batched(dd_ctx* ctx, int n, const dd_batch_item* items,
                                  const dd_solver_params* params, dd_solve_stats* stats);
 
 /*
+ * Stencil launch shapes are tuned per context on first use; with the
+ * environment variable DD_TUNE_CACHE naming a file, contexts load the shapes
+ * stored there and append new ones, so that separate processes launch the
+ * same kernels.
+ *
  * Kernel timing on the context stream.  With enable != 0 every stencil
  * launch made by the library is bracketed by HIP events recorded on the
  * context stream; enabling or disabling resets the counters.  Launches are

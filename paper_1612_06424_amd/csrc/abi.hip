@@ -118,12 +118,6 @@ void timing_harvest(dd_ctx* c) {
     c->pending.clear();
 }
 
-}  // namespace dd
-
-using namespace dd;
-
-namespace {
-
 bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align) {
     if (p == nullptr || (reinterpret_cast<uintptr_t>(p) % align) != 0) return false;
     hipPointerAttribute_t a;
@@ -144,6 +138,20 @@ bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align) {
     return true;
 }
 
+dd_status check_params(dd_ctx* c, const dd_solver_params* p) {
+    if (p == nullptr) return fail(c, DD_ERR_ARG, "solver params are NULL");
+    if (!(p->tol > 0) || p->tol >= 1 || p->max_iter < 1)
+        return fail(c, DD_ERR_ARG, "need 0 < tol < 1 and max_iter >= 1");
+    if (p->prec != DD_FP64 && p->prec != DD_MIXED) return fail(c, DD_ERR_ARG, "solver prec must be DD_FP64 or DD_MIXED");
+    if (!(p->delta >= 0) || p->delta >= 1) return fail(c, DD_ERR_ARG, "solver delta must lie in [0, 1)");
+    if (p->solver != DD_BICGSTAB && p->solver != DD_CGNR) return fail(c, DD_ERR_ARG, "unknown solver kind");
+    return DD_OK;
+}
+
+}  // namespace dd
+
+using namespace dd;
+
 #define CHECK_PTR(c, p, bytes, align, name)                                                         \
     do {                                                                                             \
         if (!on_device(c, p, bytes, align))                                                          \
@@ -152,20 +160,13 @@ bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align) {
                                            "the context's device");                                 \
     } while (0)
 
+
+namespace {
+
 dd_status check_dom(dd_ctx* c, const dd_domain* dom) {
     if (dom == nullptr) return DD_OK;
     if (dom->t0 < 0 || dom->t0 >= c->lat.T || dom->nt < 1 || dom->nt >= c->lat.T)
         return fail(c, DD_ERR_ARG, "slab must satisfy 0 <= t0 < T and 1 <= nt < T");
-    return DD_OK;
-}
-
-dd_status check_params(dd_ctx* c, const dd_solver_params* p) {
-    if (p == nullptr) return fail(c, DD_ERR_ARG, "solver params are NULL");
-    if (!(p->tol > 0) || p->tol >= 1 || p->max_iter < 1)
-        return fail(c, DD_ERR_ARG, "need 0 < tol < 1 and max_iter >= 1");
-    if (p->prec != DD_FP64 && p->prec != DD_MIXED) return fail(c, DD_ERR_ARG, "solver prec must be DD_FP64 or DD_MIXED");
-    if (!(p->delta >= 0) || p->delta >= 1) return fail(c, DD_ERR_ARG, "solver delta must lie in [0, 1)");
-    if (p->solver != DD_BICGSTAB && p->solver != DD_CGNR) return fail(c, DD_ERR_ARG, "unknown solver kind");
     return DD_OK;
 }
 
@@ -196,6 +197,7 @@ dd_status dd_create(const dd_lattice* lat, void* stream, dd_ctx** out) {
         return DD_ERR_HIP;
     }
     c->ws.resize(W_NSLOTS);
+    tune_cache_load(c);
     *out = c;
     return DD_OK;
 }
@@ -210,6 +212,7 @@ void dd_destroy(dd_ctx* c) {
         (void)hipEventDestroy(t.stop);
     }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->host_state) (void)hipHostFree(c->host_state);
     if (c->host_dots) (void)hipHostFree(c->host_dots);
     delete c;
@@ -460,19 +463,11 @@ dd_status dd_domain_action(dd_ctx* c, const void* U, double kappa, const dd_doma
     }
     if (e != DD_OK) return e;
     if (S_host) {
-        const int n = 12 * g.nsite;
-        double* partial = (double*)workspace(c, W_PART, (size_t)nrhs * ((n + kBlock - 1) / kBlock) * 3 * sizeof(double), &e);
+        std::vector<double> nn;
+        e = column_norms(c, 12 * g.nsite, nrhs, (const cpx<double>*)Y, &nn);
         if (e != DD_OK) return e;
-        double* dots = (double*)workspace(c, W_DOTS, sizeof(double) * 3 * nrhs, &e);
-        if (e != DD_OK) return e;
-        launch_norm2<double>(c, n, nrhs, (const cpx<double>*)Y, partial);
-        launch_finalize(c, FIN_STORE, nrhs, (n + kBlock - 1) / kBlock, partial, nullptr, dots);
-        DD_HIP(c, hipGetLastError());
-        std::vector<double> h(3 * nrhs);
-        DD_HIP(c, hipMemcpyAsync(h.data(), dots, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, c->stream));
-        DD_HIP(c, hipStreamSynchronize(c->stream));
         double s = 0;
-        for (int j = 0; j < nrhs; j++) s += h[3 * j];
+        for (double v : nn) s += v;
         *S_host = s;
     }
     DD_HIP(c, hipStreamSynchronize(c->stream));

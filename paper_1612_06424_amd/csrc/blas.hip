@@ -1,11 +1,10 @@
-// blas.hip -- vector kernels of the Krylov solvers (fused updates with FP64
-// partial reductions), the per-column scalar updates, precision conversions and
-// the smaller pieces of the hot path: frontier hop, slab copies, point sources,
-// the pion contraction and the link force.
+// blas.hip -- the smaller kernels of the hot path: precision conversion of the
+// links, gamma_5, the frontier hop, slab copies, point sources, the pion
+// contraction and the link force.
 //
 // Reductions are deterministic: every workgroup writes its partial sums (FP64)
-// to a fixed slot and one workgroup per column adds them in a fixed order, so
-// results are bitwise reproducible run to run.
+// to a fixed slot and one workgroup adds them in a fixed order, so results are
+// bitwise reproducible run to run.
 #include <cmath>
 
 #include "dd_internal.h"
@@ -17,314 +16,8 @@ namespace {
 
 __device__ inline cpx<double> cd(double a, double b) { return {a, b}; }
 
-template <typename R>
-__device__ inline cpx<R> scal(const double re, const double im, cpx<R> a) {
-    return {R(re) * a.re - R(im) * a.im, R(re) * a.im + R(im) * a.re};
-}
-
 inline dim3 egrid(int n, int ncol) { return dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)ncol); }
 
-// p = r + beta (p - omega v)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bicg_p(int n, const cpx<R>* __restrict__ r, cpx<R>* __restrict__ p,
-                                                   const cpx<R>* __restrict__ v, const ColState* __restrict__ st) {
-    const int col = blockIdx.y;
-    if (!st[col].active) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    const ColState& s = st[col];
-    const cpx<R> t = p[k] - scal(s.omega_re, s.omega_im, v[k]);
-    p[k] = r[k] + scal(s.beta_re, s.beta_im, t);
-}
-
-// s = r - alpha v
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bicg_s(int n, const cpx<R>* __restrict__ r, const cpx<R>* __restrict__ v,
-                                                   cpx<R>* __restrict__ s_, const ColState* __restrict__ st) {
-    const int col = blockIdx.y;
-    if (!st[col].active) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    s_[k] = r[k] - scal(st[col].alpha_re, st[col].alpha_im, v[k]);
-}
-
-// x += alpha p + omega s; r = s - omega t; partials <r^, r>, |r|^2
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bicg_xr(int n, cpx<R>* __restrict__ x, cpx<R>* __restrict__ r,
-                                                    const cpx<R>* __restrict__ p, const cpx<R>* __restrict__ s_,
-                                                    const cpx<R>* __restrict__ t, const cpx<R>* __restrict__ rh,
-                                                    double* __restrict__ partial, const ColState* __restrict__ st) {
-    const int col = blockIdx.y;
-    if (!st[col].active) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double d0 = 0, d1 = 0, d2 = 0;
-    if (i < n) {
-        const size_t k = (size_t)col * n + i;
-        const ColState& s = st[col];
-        const cpx<R> sv = s_[k];
-        x[k] = x[k] + scal(s.alpha_re, s.alpha_im, p[k]) + scal(s.omega_re, s.omega_im, sv);
-        const cpx<R> rn = sv - scal(s.omega_re, s.omega_im, t[k]);
-        r[k] = rn;
-        const cpx<R> q = rh[k];
-        d0 = (double)q.re * rn.re + (double)q.im * rn.im;
-        d1 = (double)q.re * rn.im - (double)q.im * rn.re;
-        d2 = (double)rn.re * rn.re + (double)rn.im * rn.im;
-    }
-    block_sum3(d0, d1, d2, partial + ((size_t)col * gridDim.x + blockIdx.x) * 3);
-}
-
-// CGNR: x += alpha p; r -= alpha w; partial |r|^2 (alpha real)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_xr(int n, cpx<R>* __restrict__ x, cpx<R>* __restrict__ r,
-                                                  const cpx<R>* __restrict__ p, const cpx<R>* __restrict__ w,
-                                                  double* __restrict__ partial, const ColState* __restrict__ st) {
-    const int col = blockIdx.y;
-    if (!st[col].active) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double d0 = 0;
-    if (i < n) {
-        const size_t k = (size_t)col * n + i;
-        const R a = R(st[col].alpha_re);
-        x[k] = x[k] + a * p[k];
-        const cpx<R> rn = r[k] - a * w[k];
-        r[k] = rn;
-        d0 = (double)rn.re * rn.re + (double)rn.im * rn.im;
-    }
-    block_sum3(d0, 0.0, 0.0, partial + ((size_t)col * gridDim.x + blockIdx.x) * 3);
-}
-
-// CGNR: p = z + beta p (beta real)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_p(int n, cpx<R>* __restrict__ p, const cpx<R>* __restrict__ z,
-                                                 const ColState* __restrict__ st) {
-    const int col = blockIdx.y;
-    if (!st[col].active) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    p[k] = z[k] + R(st[col].beta_re) * p[k];
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_norm2(int n, const cpx<R>* __restrict__ a, double* __restrict__ partial) {
-    const int col = blockIdx.y;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double d0 = 0;
-    if (i < n) {
-        const cpx<R> v = a[(size_t)col * n + i];
-        d0 = (double)v.re * v.re + (double)v.im * v.im;
-    }
-    block_sum3(d0, 0.0, 0.0, partial + ((size_t)col * gridDim.x + blockIdx.x) * 3);
-}
-
-// One workgroup per column: fixed-order sum of the column's partials, then the
-// scalar recurrences of BiCGStab / CG for that column.
-__global__ __launch_bounds__(kBlock) void k_finalize(int fin, int nsb, const double* __restrict__ partial,
-                                                     ColState* __restrict__ st, double* __restrict__ out) {
-    const int col = blockIdx.x;
-    if (fin != FIN_STORE && !st[col].active) return;
-    double d0 = 0, d1 = 0, d2 = 0;
-    const double* p = partial + (size_t)col * nsb * 3;
-    for (int k = threadIdx.x; k < nsb; k += kBlock) {
-        d0 += p[3 * k];
-        d1 += p[3 * k + 1];
-        d2 += p[3 * k + 2];
-    }
-    __shared__ double red[3];
-    block_sum3(d0, d1, d2, red);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    d0 = red[0];
-    d1 = red[1];
-    d2 = red[2];
-    if (fin == FIN_STORE) {
-        out[col * 3 + 0] = d0;
-        out[col * 3 + 1] = d1;
-        out[col * 3 + 2] = d2;
-        return;
-    }
-    ColState& s = st[col];
-    switch (fin) {
-        case FIN_ALPHA: {  // alpha = rho / <r^, v>
-            const double den = d0 * d0 + d1 * d1;
-            if (!(den > 0) || !isfinite(den)) {
-                s.breakdown = isfinite(den) ? 1 : 2;
-                s.active = 0;
-                break;
-            }
-            s.alpha_re = (s.rho_re * d0 + s.rho_im * d1) / den;
-            s.alpha_im = (s.rho_im * d0 - s.rho_re * d1) / den;
-            break;
-        }
-        case FIN_OMEGA: {  // omega = <t, s> / <t, t>
-            if (!(d2 > 0) || !isfinite(d2)) {
-                s.breakdown = isfinite(d2) ? 1 : 2;
-                s.active = 0;
-                break;
-            }
-            s.omega_re = d0 / d2;
-            s.omega_im = d1 / d2;
-            if (s.omega_re == 0.0 && s.omega_im == 0.0) {
-                s.breakdown = 1;
-                s.active = 0;
-            }
-            break;
-        }
-        case FIN_RHO: {  // beta = (rho_new / rho) (alpha / omega), rho = rho_new
-            const double rr = d2;
-            s.rr = rr;
-            s.iters += 1;
-            if (!isfinite(rr) || !isfinite(d0) || !isfinite(d1)) {
-                s.breakdown = 2;
-                s.active = 0;
-                break;
-            }
-            if (rr <= s.stop2) {
-                s.active = 0;
-                break;
-            }
-            const double rden = s.rho_re * s.rho_re + s.rho_im * s.rho_im;
-            const double q_re = (d0 * s.rho_re + d1 * s.rho_im) / rden;  // rho_new / rho
-            const double q_im = (d1 * s.rho_re - d0 * s.rho_im) / rden;
-            const double oden = s.omega_re * s.omega_re + s.omega_im * s.omega_im;
-            const double w_re = (s.alpha_re * s.omega_re + s.alpha_im * s.omega_im) / oden;  // alpha / omega
-            const double w_im = (s.alpha_im * s.omega_re - s.alpha_re * s.omega_im) / oden;
-            s.beta_re = q_re * w_re - q_im * w_im;
-            s.beta_im = q_re * w_im + q_im * w_re;
-            s.rho_re = d0;
-            s.rho_im = d1;
-            if (d0 * d0 + d1 * d1 < 1e-24 * rr * s.rh2) {  // r^ numerically orthogonal to r
-                s.breakdown = 1;
-                s.active = 0;
-            }
-            break;
-        }
-        case FIN_CG_ALPHA: {
-            if (!(d0 > 0) || !isfinite(d0)) {
-                s.breakdown = isfinite(d0) ? 1 : 2;
-                s.active = 0;
-                break;
-            }
-            s.alpha_re = s.zz / d0;
-            s.alpha_im = 0;
-            break;
-        }
-        case FIN_CG_RR: {
-            s.rr = d0;
-            s.iters += 1;
-            if (!isfinite(d0)) {
-                s.breakdown = 2;
-                s.active = 0;
-            } else if (d0 <= s.stop2) {
-                s.active = 0;
-            }
-            break;
-        }
-        case FIN_CG_BETA: {
-            s.beta_re = d0 / s.zz;
-            s.beta_im = 0;
-            s.zz = d0;
-            break;
-        }
-        case FIN_INIT: {
-            s.rr = d0;
-            s.rh2 = d0;
-            s.rho_re = d0;
-            s.rho_im = 0;
-            s.stop2 *= d0;
-            s.alpha_re = s.omega_re = 1.0;
-            s.alpha_im = s.omega_im = 0.0;
-            s.beta_re = s.beta_im = 0.0;
-            s.iters = 0;
-            s.breakdown = 0;
-            if (!isfinite(d0)) {
-                s.breakdown = 2;
-                s.active = 0;
-            } else if (!(d0 > 0)) {
-                s.active = 0;
-            }
-            break;
-        }
-        case FIN_CG_ZZ: {
-            s.zz = d0;
-            if (!(d0 > 0) || !isfinite(d0)) {
-                s.breakdown = isfinite(d0) ? 1 : 2;
-                s.active = 0;
-            }
-            break;
-        }
-        default:
-            break;
-    }
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_copy_cols(int n, const cpx<R>* __restrict__ a, cpx<R>* __restrict__ b,
-                                                      const ColState* __restrict__ st) {
-    const int col = blockIdx.y;
-    if (st != nullptr && !st[col].active) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    b[(size_t)col * n + i] = a[(size_t)col * n + i];
-}
-
-
-// Reliable update helpers (columns selected by mask[col] != 0):
-//   x64 += xk; xk = 0        (xk in the Krylov precision)
-//   rk = (Rk) r64            (replace the recursive residual by the true one)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_fold_x(int n, cpx<double>* __restrict__ x, cpx<R>* __restrict__ xk,
-                                                   const int* __restrict__ mask) {
-    const int col = blockIdx.y;
-    if (!mask[col]) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    const cpx<R> e = xk[k];
-    const cpx<double> v = x[k];
-    x[k] = cd(v.re + (double)e.re, v.im + (double)e.im);
-    xk[k] = cpx<R>{R(0), R(0)};
-}
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_set_resid(int n, const cpx<double>* __restrict__ r64, cpx<R>* __restrict__ rk,
-                                                      const int* __restrict__ mask) {
-    const int col = blockIdx.y;
-    if (!mask[col]) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    const cpx<double> v = r64[k];
-    rk[k] = cpx<R>{(R)v.re, (R)v.im};
-}
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_restart_dirs(int n, const cpx<R>* __restrict__ r, cpx<R>* __restrict__ rh,
-                                                         cpx<R>* __restrict__ p, cpx<R>* __restrict__ v,
-                                                         const int* __restrict__ mask) {
-    const int col = blockIdx.y;
-    if (mask[col] != 2) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    rh[k] = r[k];
-    p[k] = cpx<R>{R(0), R(0)};
-    v[k] = cpx<R>{R(0), R(0)};
-}
-
-// CGNR reliable update: p += t - z; z = t (columns with mask != 0)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_shift(int n, cpx<R>* __restrict__ p, cpx<R>* __restrict__ z,
-                                                     const cpx<R>* __restrict__ t, const int* __restrict__ mask) {
-    const int col = blockIdx.y;
-    if (!mask[col]) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t k = (size_t)col * n + i;
-    const cpx<R> tv = t[k];
-    p[k] = p[k] + tv - z[k];
-    z[k] = tv;
-}
 
 __global__ __launch_bounds__(kBlock) void k_links_to_f32(size_t n, const cpx<double>* __restrict__ a,
                                                          cpx<float>* __restrict__ b) {
@@ -547,39 +240,6 @@ __global__ __launch_bounds__(kBlock) void k_link_force(Geo g, int ncol, const cp
 
 // ------------------------------------------------------------------ launchers
 
-template <typename R>
-void launch_bicg_p(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* p, const cpx<R>* v, const ColState* st) {
-    hipLaunchKernelGGL(k_bicg_p<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, r, p, v, st);
-}
-template <typename R>
-void launch_bicg_s(dd_ctx* c, int n, int ncol, const cpx<R>* r, const cpx<R>* v, cpx<R>* s, const ColState* st) {
-    hipLaunchKernelGGL(k_bicg_s<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, r, v, s, st);
-}
-template <typename R>
-void launch_bicg_xr(dd_ctx* c, int n, int ncol, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* s,
-                    const cpx<R>* t, const cpx<R>* rh, double* partial, const ColState* st) {
-    hipLaunchKernelGGL(k_bicg_xr<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, x, r, p, s, t, rh, partial, st);
-}
-template <typename R>
-void launch_cg_xr(dd_ctx* c, int n, int ncol, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* w,
-                  double* partial, const ColState* st) {
-    hipLaunchKernelGGL(k_cg_xr<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, x, r, p, w, partial, st);
-}
-template <typename R>
-void launch_cg_p(dd_ctx* c, int n, int ncol, cpx<R>* p, const cpx<R>* z, const ColState* st) {
-    hipLaunchKernelGGL(k_cg_p<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, p, z, st);
-}
-template <typename R>
-void launch_norm2(dd_ctx* c, int n, int ncol, const cpx<R>* a, double* partial) {
-    hipLaunchKernelGGL(k_norm2<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, a, partial);
-}
-void launch_finalize(dd_ctx* c, int fin, int ncol, int nsb, const double* partial, ColState* st, double* out) {
-    hipLaunchKernelGGL(k_finalize, dim3(ncol), dim3(kBlock), 0, c->stream, fin, nsb, partial, st, out);
-}
-template <typename R>
-void launch_copy_cols(dd_ctx* c, int n, int ncol, const cpx<R>* src, cpx<R>* dst, const ColState* st) {
-    hipLaunchKernelGGL(k_copy_cols<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, src, dst, st);
-}
 void launch_links_to_f32(dd_ctx* c, size_t n, const cpx<double>* src, cpx<float>* dst) {
     hipLaunchKernelGGL(k_links_to_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
                        n, src, dst);
@@ -639,45 +299,8 @@ void launch_link_force(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* X, 
 }
 
 
-template <typename R>
-void launch_fold_x(dd_ctx* c, int n, int ncol, cpx<double>* x, cpx<R>* xk, const int* mask) {
-    hipLaunchKernelGGL(k_fold_x<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, x, xk, mask);
-}
-template <typename R>
-void launch_set_resid(dd_ctx* c, int n, int ncol, const cpx<double>* r64, cpx<R>* rk, const int* mask) {
-    hipLaunchKernelGGL(k_set_resid<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, r64, rk, mask);
-}
-template <typename R>
-void launch_restart_dirs(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* rh, cpx<R>* p, cpx<R>* v,
-                         const int* mask) {
-    hipLaunchKernelGGL(k_restart_dirs<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, r, rh, p, v, mask);
-}
-template void launch_fold_x<float>(dd_ctx*, int, int, cpx<double>*, cpx<float>*, const int*);
-template void launch_set_resid<float>(dd_ctx*, int, int, const cpx<double>*, cpx<float>*, const int*);
-template void launch_set_resid<double>(dd_ctx*, int, int, const cpx<double>*, cpx<double>*, const int*);
-template void launch_restart_dirs<float>(dd_ctx*, int, int, const cpx<float>*, cpx<float>*, cpx<float>*, cpx<float>*,
-                                         const int*);
-template void launch_restart_dirs<double>(dd_ctx*, int, int, const cpx<double>*, cpx<double>*, cpx<double>*,
-                                          cpx<double>*, const int*);
-
-template <typename R>
-void launch_cg_shift(dd_ctx* c, int n, int ncol, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask) {
-    hipLaunchKernelGGL(k_cg_shift<R>, egrid(n, ncol), dim3(kBlock), 0, c->stream, n, p, z, t, mask);
-}
-template void launch_cg_shift<float>(dd_ctx*, int, int, cpx<float>*, cpx<float>*, const cpx<float>*, const int*);
-template void launch_cg_shift<double>(dd_ctx*, int, int, cpx<double>*, cpx<double>*, const cpx<double>*, const int*);
-
-#define DD_INST(R)                                                                                           \
-    template void launch_bicg_p<R>(dd_ctx*, int, int, const cpx<R>*, cpx<R>*, const cpx<R>*, const ColState*); \
-    template void launch_bicg_s<R>(dd_ctx*, int, int, const cpx<R>*, const cpx<R>*, cpx<R>*, const ColState*); \
-    template void launch_bicg_xr<R>(dd_ctx*, int, int, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*,          \
-                                    const cpx<R>*, const cpx<R>*, double*, const ColState*);                   \
-    template void launch_cg_xr<R>(dd_ctx*, int, int, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, double*,   \
-                                  const ColState*);                                                            \
-    template void launch_cg_p<R>(dd_ctx*, int, int, cpx<R>*, const cpx<R>*, const ColState*);                  \
-    template void launch_norm2<R>(dd_ctx*, int, int, const cpx<R>*, double*);                                   \
-    template void launch_copy_cols<R>(dd_ctx*, int, int, const cpx<R>*, cpx<R>*, const ColState*);             \
-    template void launch_gamma5<R>(dd_ctx*, int, int, const cpx<R>*, cpx<R>*);                                  \
+#define DD_INST(R)                                                           \
+    template void launch_gamma5<R>(dd_ctx*, int, int, const cpx<R>*, cpx<R>*); \
     template void launch_zero<R>(dd_ctx*, size_t, cpx<R>*);
 
 DD_INST(double)

@@ -132,6 +132,8 @@ struct dd_ctx {
     // autotuned stencil launch shapes, keyed by (precision, ncol, geometry)
     std::map<std::string, dd::StencilSched> sched;
     int autotune = 1;
+    // library-owned stream for work captured into HIP graphs (created on first use)
+    hipStream_t own_stream = nullptr;
     // pinned host mirrors of per-column state and of small reductions
     dd::ColState* host_state = nullptr;
     double* host_dots = nullptr;
@@ -147,7 +149,7 @@ enum Slot {
     W_B32, W_X32, W_U32, W_RES64,
     W_PART, W_STATE, W_STATE32, W_DOTS,
     W_AUX0, W_AUX1, W_AUX2, W_AUX3, W_AUX4,
-    W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
+    W_SEGS, W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
     W_NSLOTS
 };
 
@@ -162,6 +164,9 @@ void* workspace(dd_ctx* c, Slot s, size_t bytes, dd_status* st);
     } while (0)
 
 Geo make_geo(const dd_lattice& lat, const dd_domain* dom);
+// p is device memory of the context's device, aligned, with bytes available
+bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align);
+dd_status check_params(dd_ctx* c, const dd_solver_params* p);
 
 // ---------------------------------------------------------------- stencil launchers
 // Epilogues fused into the stencil (one pass over the output):
@@ -183,6 +188,9 @@ void launch_dslash(dd_ctx* c, const Geo& g, const cpx<R>* U, double kappa, int d
 // Number of partial-sum slots per column written by one stencil launch.
 StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol);
 int stencil_slots(dd_ctx* c, const Geo& g, int kind, int ncol);
+// Tuned shapes shared across processes through the file named by DD_TUNE_CACHE.
+void tune_cache_load(dd_ctx* c);
+void tune_cache_store(dd_ctx* c, const std::string& key, const StencilSched& sc);
 StencilSched default_sched(const Geo& g);
 int stencil_blocks(const Geo& g, const StencilSched& sc);
 template <typename R>
@@ -191,26 +199,48 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
                          double* partial, const ColState* st);
 inline int site_blocks(int nsite) { return (nsite + kBlock - 1) / kBlock; }
 
-// ---------------------------------------------------------------- BLAS / reductions
-template <typename R>
-void launch_bicg_p(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* p, const cpx<R>* v,
-                   const ColState* st);
-template <typename R>
-void launch_bicg_s(dd_ctx* c, int n, int ncol, const cpx<R>* r, const cpx<R>* v, cpx<R>* s,
-                   const ColState* st);
-template <typename R>
-void launch_bicg_xr(dd_ctx* c, int n, int ncol, cpx<R>* x, cpx<R>* r, const cpx<R>* p,
-                    const cpx<R>* s, const cpx<R>* t, const cpx<R>* rh, double* partial,
-                    const ColState* st);
-template <typename R>
-void launch_cg_xr(dd_ctx* c, int n, int ncol, cpx<R>* x, cpx<R>* r, const cpx<R>* p,
-                  const cpx<R>* w, double* partial, const ColState* st);
-template <typename R>
-void launch_cg_p(dd_ctx* c, int n, int ncol, cpx<R>* p, const cpx<R>* z, const ColState* st);
-template <typename R>
-void launch_norm2(dd_ctx* c, int n, int ncol, const cpx<R>* a, double* partial);
+// ---------------------------------------------------------------- solver segments
+// A solve advances many columns ("segments") together: the columns of one
+// lattice or slab, or every column of every domain of a batch.  Segments lie
+// back to back in each work vector and may differ in length.  Device tables:
+struct Segs {
+    const long long* off;  // [nseg] first element (complex) of each segment
+    const int* len;        // [nseg] elements of each segment (12 x sites)
+    const int* eb0;        // [nseg + 1] first elementwise workgroup of each segment
+    const int* eseg;       // [neb] segment of each elementwise workgroup
+    int nseg, neb;
+};
 
-// finalize kinds (one block per column reduces its partials, then updates scalars)
+// Vector kernels of the Krylov solvers over segments; reductions write one
+// partial slot per elementwise workgroup (slots of segment k: [eb0[k], eb0[k+1])).
+template <typename R>
+void launch_bicg_p(dd_ctx* c, const Segs& S, const cpx<R>* r, cpx<R>* p, const cpx<R>* v, const ColState* st);
+template <typename R>
+void launch_bicg_s(dd_ctx* c, const Segs& S, const cpx<R>* r, const cpx<R>* v, cpx<R>* s, const ColState* st);
+template <typename R>
+void launch_bicg_xr(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* s,
+                    const cpx<R>* t, const cpx<R>* rh, double* partial, const ColState* st);
+template <typename R>
+void launch_cg_xr(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* w,
+                  double* partial, const ColState* st);
+template <typename R>
+void launch_cg_p(dd_ctx* c, const Segs& S, cpx<R>* p, const cpx<R>* z, const ColState* st);
+template <typename R>
+void launch_norm2(dd_ctx* c, const Segs& S, const cpx<R>* a, double* partial);
+template <typename R>
+void launch_copy_segs(dd_ctx* c, const Segs& S, const cpx<R>* a, cpx<R>* b, const ColState* st);
+template <typename R>
+void launch_fold_x(dd_ctx* c, const Segs& S, cpx<double>* x, cpx<R>* xk, const int* mask);
+template <typename R>
+void launch_set_resid(dd_ctx* c, const Segs& S, const cpx<double>* r64, cpx<R>* rk, const int* mask);
+template <typename R>
+void launch_restart_dirs(dd_ctx* c, const Segs& S, const cpx<R>* r, cpx<R>* rh, cpx<R>* p, cpx<R>* v,
+                         const int* mask);
+template <typename R>
+void launch_cg_shift(dd_ctx* c, const Segs& S, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask);
+
+// finalize kinds (one workgroup per segment reduces its partial slots, then
+// updates that segment's scalars)
 enum Fin {
     FIN_ALPHA = 0,   // dots = <r^,v>        -> alpha = rho / <r^,v>
     FIN_OMEGA,       // dots = <t,s>, |t|^2  -> omega
@@ -218,26 +248,70 @@ enum Fin {
     FIN_CG_ALPHA,    // dots = |w|^2         -> alpha = zz / |w|^2
     FIN_CG_RR,       // dots = |r|^2         -> rr, convergence
     FIN_CG_BETA,     // dots = |z|^2         -> beta = zz_new / zz
-    FIN_CG_ZZ,       // dots = |z|^2         -> zz (start of a CG cycle)
-    FIN_INIT,        // dots = |r|^2 of a fresh residual -> rho = rr = rh2 = |r|^2,
-                     //   stop2 *= |r|^2, alpha = omega = 1, beta = 0, iters = 0
-    FIN_STORE        // dots -> out[col*3 + k] (plain reduction)
+    FIN_CG_ZZ,       // dots = |z|^2         -> zz
+    FIN_STORE        // dots -> out[seg*3 + k] (plain reduction)
 };
-void launch_finalize(dd_ctx* c, int fin, int ncol, int nsb, const double* partial, ColState* st,
+// p0: device [nseg + 1] prefix of the partial slots of each segment.
+void launch_finalize(dd_ctx* c, int fin, int nseg, const int* p0, const double* partial, ColState* st,
                      double* out);
 
-template <typename R>
-void launch_copy_cols(dd_ctx* c, int n, int ncol, const cpx<R>* src, cpx<R>* dst, const ColState* st);
+// The operator side of a solve: nseg independent systems M_k x_k = b_k.
+// apply runs the stencil of every segment in precision R with a fused
+// epilogue (dag = 1: D^+); the partial slots of segment k written by such a
+// launch are [sp0[kind][k], sp0[kind][k+1]) with kind 0 = FP64, 1 = FP32.
+struct System {
+    dd_ctx* c = nullptr;
+    int nseg = 0;
+    size_t nelem = 0;                      // complex elements of one work vector
+    Segs seg{};                            // elementwise segment tables
+    const int* sp0[2] = {nullptr, nullptr};
+    size_t nslots = 0;                     // partial slots needed by any launch
+    bool graph = false;                    // replay the inner iterations from a captured HIP graph
+    bool has32 = false;                    // FP32 stencil available (links converted)
+    virtual ~System() {}
+    virtual void apply64(int dag, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux,
+                         double* partial, const ColState* st) = 0;
+    virtual void apply32(int dag, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux,
+                         double* partial, const ColState* st) = 0;
+    void apply(int dag, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux,
+               double* partial, const ColState* st) {
+        apply64(dag, epi, in, out, aux, partial, st);
+    }
+    void apply(int dag, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux, double* partial,
+               const ColState* st) {
+        apply32(dag, epi, in, out, aux, partial, st);
+    }
+};
+
+// Host and device copies of a segment layout.  upload() places the device
+// tables in workspace slot `slot` and waits for the copy.
+struct SegLayout {
+    std::vector<long long> off;
+    std::vector<int> len;
+    std::vector<int> sp0[2];  // stencil partial prefixes per kind, filled by the caller
+    std::vector<int> eb0, eseg;
+    dd_status upload(dd_ctx* c, Slot slot, System* S);
+};
+
+// Outcome of solve_system per segment and overall.
+struct SolveResult {
+    int iters = 0;                  // lockstep iterations
+    int updates = 0;                // rounds of reliable updates
+    int restarts = 0;
+    std::vector<double> rel;        // true |b - M x| / |b| per segment
+    std::vector<int> seg_iters;     // iterations each segment was active
+};
+
+// Solve every segment of S to p.tol (true FP64 residual); b and x are work
+// vectors laid out as S.seg.  Returns DD_ERR_NOCONV / DD_ERR_BREAKDOWN with the
+// result filled.
+dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd_solver_params& p,
+                       SolveResult* res);
+
+// |a_j|^2 of the ncol columns of a (each n elements), into out; synchronises.
+dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::vector<double>* out);
+
 void launch_links_to_f32(dd_ctx* c, size_t n, const cpx<double>* src, cpx<float>* dst);
-template <typename R>
-void launch_fold_x(dd_ctx* c, int n, int ncol, cpx<double>* x, cpx<R>* xk, const int* mask);
-template <typename R>
-void launch_set_resid(dd_ctx* c, int n, int ncol, const cpx<double>* r64, cpx<R>* rk, const int* mask);
-template <typename R>
-void launch_cg_shift(dd_ctx* c, int n, int ncol, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask);
-template <typename R>
-void launch_restart_dirs(dd_ctx* c, int n, int ncol, const cpx<R>* r, cpx<R>* rh, cpx<R>* p, cpx<R>* v,
-                         const int* mask);
 template <typename R>
 void launch_gamma5(dd_ctx* c, int n, int ncol, const cpx<R>* in, cpx<R>* out);
 template <typename R>

@@ -6,8 +6,15 @@
 // slice of them touches).  The first launch for a new key times every
 // candidate on scratch buffers of the same size and keeps the fastest; later
 // launches reuse it.  Small problems use the default shape untimed.
+//
+// With the environment variable DD_TUNE_CACHE naming a file, a new context
+// loads the choices stored there and every new choice is appended to it, so
+// that separate processes (for instance the passes of a profiler) launch the
+// same shapes.
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
+#include <fstream>
 #include <string>
 
 #include "dd_internal.h"
@@ -78,6 +85,23 @@ StencilSched tune(dd_ctx* c, const Geo& g, int ncol) {
 
 }  // namespace
 
+void tune_cache_load(dd_ctx* c) {
+    const char* path = std::getenv("DD_TUNE_CACHE");
+    if (path == nullptr || *path == 0) return;
+    std::ifstream f(path);
+    std::string key;
+    StencilSched sc;
+    while (f >> key >> sc.nt >> sc.tc >> sc.remap) c->sched[key] = sc;
+}
+
+void tune_cache_store(dd_ctx* c, const std::string& key, const StencilSched& sc) {
+    c->sched[key] = sc;
+    const char* path = std::getenv("DD_TUNE_CACHE");
+    if (path == nullptr || *path == 0) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << sc.nt << " " << sc.tc << " " << sc.remap << "\n";
+}
+
 StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol) {
     const std::string k = key_of(g, kind, ncol);
     auto it = c->sched.find(k);
@@ -85,7 +109,7 @@ StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol) {
     StencilSched sc = default_sched(g);
     if (c->autotune && (size_t)g.nsite * ncol >= ((size_t)1 << 18))
         sc = kind == 0 ? tune<double>(c, g, ncol) : tune<float>(c, g, ncol);
-    c->sched[k] = sc;
+    tune_cache_store(c, k, sc);
     return sc;
 }
 
