@@ -1,0 +1,133 @@
+"""Condense rocprofv3 output of bench.py into the short text kept under profiles/.
+
+    python -m paper_1612_06424_amd.rocprof_summary DIR [--keep-raw]
+
+DIR holds one rocprofv3 output directory per pass (csv format):
+  trace/       --kernel-trace --stats of the bench
+  fetch/       --pmc FETCH_SIZE  (stencil kernels)
+  write/       --pmc WRITE_SIZE  (stencil kernels)
+  copy_fetch/  --pmc FETCH_SIZE  of bench.py --copy-calibration
+  copy_write/  --pmc WRITE_SIZE  of bench.py --copy-calibration
+and writes DIR/summary.md (per-kernel durations, HBM bytes per launch from
+the counters scaled by the copy calibration) and DIR/stencil_traffic.json,
+which bench.py reads to fill roofline.traffic while the stencil sources are
+unchanged (same kernel_source_hash).  Raw csv files are deleted unless
+--keep-raw (they are large).
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+# the sources that decide what the stencil kernels do and how they are launched
+STENCIL_SOURCES = ["csrc/dd_dslash.h", "csrc/dd_wilson.h", "csrc/dirac.hip", "csrc/batched.hip", "csrc/tune.hip",
+                   "tune_cache_mi355x.txt"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in STENCIL_SOURCES:
+        p = os.path.join(PKG, rel)
+        h.update(rel.encode())
+        if os.path.exists(p):
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(n: str) -> str:
+    m = re.search(r"(k_\w+<[^()]*>|k_\w+|__amd_\w+)", n)
+    return m.group(1) if m else n[:48]
+
+
+def _rows(pattern):
+    out = []
+    for f in glob.glob(pattern, recursive=True):
+        with open(f) as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def counters(d):
+    """{kernel: (dispatches, mean counter value per dispatch)} of one --pmc pass."""
+    agg = collections.OrderedDict()
+    for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+        k = short_name(r.get("Kernel_Name", "?"))
+        a = agg.setdefault(k, [set(), 0.0])
+        a[0].add(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        a[1] += float(r.get("Counter_Value") or 0)
+    return {k: (len(v[0]), v[1] / max(len(v[0]), 1)) for k, v in agg.items()}
+
+
+def main(argv):
+    d = argv[0]
+    keep = "--keep-raw" in argv
+    stats = _rows(os.path.join(d, "trace", "**", "*kernel_stats.csv"))
+    cf, cw = counters(os.path.join(d, "copy_fetch")), counters(os.path.join(d, "copy_write"))
+    fe, wr = counters(os.path.join(d, "fetch")), counters(os.path.join(d, "write"))
+    copy_bytes = 1 << 30
+    ck = "__amd_rocclr_copyBuffer"
+    # counters are in KiB; scale so that the plain copy of copy_bytes reads / writes copy_bytes
+    f_scale = copy_bytes / (cf[ck][1] * 1024) if ck in cf else None
+    w_scale = copy_bytes / (cw[ck][1] * 1024) if ck in cw else None
+    bench = None
+    for line in open(os.path.join(d, "trace.log")) if os.path.exists(os.path.join(d, "trace.log")) else []:
+        if line.startswith('{"metric"'):
+            bench = json.loads(line)
+    lines = ["| kernel | calls | avg us | total ms | % time |", "|---|---:|---:|---:|---:|"]
+    tot = {}
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+        k = short_name(r["Name"])
+        tot[k] = (int(r["Calls"]), float(r["AverageNs"]))
+        lines.append(f"| `{k}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.2f} |")
+    traffic = {}
+    tl = ["| kernel | launches (pmc) | FETCH B/launch | WRITE B/launch | HBM B/launch | algorithmic B/launch | "
+          "HBM / algorithmic | HIP-event avg us | rocprof avg us |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    kt = (bench or {}).get("stencil_kernels", {})
+    for k in sorted(set(fe) & set(wr)):
+        if f_scale is None or w_scale is None:
+            break
+        fb = fe[k][1] * 1024 * f_scale
+        wb = wr[k][1] * 1024 * w_scale
+        alg = ev = None
+        if k in kt and kt[k]["launches"]:
+            alg = kt[k]["GBs"] * kt[k]["ms"] * 1e6 / kt[k]["launches"]
+            ev = kt[k]["ms"] / kt[k]["launches"] * 1e3
+        traffic[k] = dict(launches=fe[k][0], fetch_bytes=round(fb), write_bytes=round(wb),
+                          hbm_bytes=round(fb + wb), algorithmic_bytes=round(alg) if alg else None)
+        tl.append(f"| `{k}` | {fe[k][0]} | {fb:.4g} | {wb:.4g} | {fb + wb:.4g} | "
+                  f"{alg:.4g} | {(fb + wb) / alg:.2f} | {ev:.1f} | {tot.get(k, (0, 0))[1] / 1e3:.1f} |"
+                  if alg else f"| `{k}` | {fe[k][0]} | {fb:.4g} | {wb:.4g} | {fb + wb:.4g} | - | - | - | - |")
+    src_hash = kernel_source_hash()
+    with open(os.path.join(d, "stencil_traffic.json"), "w") as f:
+        json.dump({"source_hash": src_hash, "fetch_scale": f_scale, "write_scale": w_scale, "kernels": traffic},
+                  f, indent=1)
+    with open(os.path.join(d, "summary.md"), "w") as f:
+        f.write(f"Stencil source hash: `{src_hash}`\n\n")
+        if f_scale:
+            f.write(f"Copy calibration (1 GiB device copy): FETCH_SIZE x {f_scale:.3f}, WRITE_SIZE x {w_scale:.3f} "
+                    "give bytes.\n\n")
+        if bench:
+            f.write("Bench line of the traced run: value %.1f GB/s, roofline %s\n\n"
+                    % (bench["value"], json.dumps(bench["roofline"])))
+        f.write("Kernel trace (top 25 by total time, warm-up and timed steps together):\n\n")
+        f.write("\n".join(lines) + "\n\nHBM traffic of the stencil kernels (counter passes):\n\n")
+        f.write("\n".join(tl) + "\n")
+    if not keep:
+        for sub in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
+            for p in glob.glob(os.path.join(d, sub, "**", "*"), recursive=True):
+                if os.path.isfile(p):
+                    os.remove(p)
+    print(open(os.path.join(d, "summary.md")).read())
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
