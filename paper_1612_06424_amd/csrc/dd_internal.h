@@ -15,6 +15,7 @@
 namespace dd {
 
 constexpr int kBlock = 256;   // threads per workgroup for site-parallel kernels
+constexpr int kElems = 4;     // elements per thread of the solver vector kernels
 constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kNumXcd = 8;    // MI355X: workgroups are dealt round-robin over 8 XCDs
 

@@ -3,8 +3,9 @@
 // A solve advances many columns ("segments") together: the columns of one
 // lattice, or every column of every domain of a batch.  Segments are laid out
 // back to back in each work vector and may differ in length; every elementwise
-// workgroup covers kBlock consecutive elements of one segment, found through a
-// workgroup -> segment table (Segs).  Columns whose ColState is inactive skip
+// workgroup covers kBlock * kElems consecutive elements of one segment (each
+// thread kElems of them, kBlock apart, so every load is coalesced), found
+// through a workgroup -> segment table (Segs).  Columns whose ColState is inactive skip
 // their work; the reliable-update helpers are selected by a per-segment mask.
 //
 // Reductions are deterministic: every workgroup writes its FP64 partial sums
@@ -26,30 +27,51 @@ __device__ inline cpx<R> scal(const double re, const double im, cpx<R> a) {
     return {R(re) * a.re - R(im) * a.im, R(re) * a.im + R(im) * a.re};
 }
 
-// This workgroup's segment, and this thread's element in it.
+// This workgroup's segment, and the first of this thread's kElems elements
+// (element j of the thread is k + j * kBlock).
 struct SegPos {
     int seg;
-    bool live;  // element inside the segment
-    size_t k;   // element index in the work vectors
+    int i0;     // offset of the first element inside the segment
+    int len;    // segment length
+    size_t k;   // index of the first element in the work vectors
+    __device__ bool live(int j) const { return i0 + j * kBlock < len; }
+    __device__ bool full() const { return i0 + (kElems - 1) * kBlock < len; }
+    __device__ size_t at(int j) const { return k + (size_t)j * kBlock; }
 };
 __device__ inline SegPos seg_pos(const Segs& S) {
     SegPos q;
     q.seg = S.eseg[blockIdx.x];
-    const int i = ((int)blockIdx.x - S.eb0[q.seg]) * kBlock + (int)threadIdx.x;
-    q.live = i < S.len[q.seg];
-    q.k = (size_t)S.off[q.seg] + (size_t)i;
+    q.i0 = ((int)blockIdx.x - S.eb0[q.seg]) * (kBlock * kElems) + (int)threadIdx.x;
+    q.len = S.len[q.seg];
+    q.k = (size_t)S.off[q.seg] + (size_t)q.i0;
     return q;
 }
+
+// Elementwise kernels read all their inputs for the kElems elements first
+// (LD), then compute and store (OP), so that every load of a thread is in
+// flight at once; a workgroup at the end of a segment takes the checked path.
+#define SEG_LOOP(LD, OP)                                          \
+    if (q.full()) {                                               \
+        _Pragma("unroll") for (int j = 0; j < kElems; j++) LD;    \
+        _Pragma("unroll") for (int j = 0; j < kElems; j++) OP;    \
+    } else {                                                      \
+        for (int j = 0; j < kElems; j++)                          \
+            if (q.live(j)) {                                      \
+                LD;                                               \
+                OP;                                               \
+            }                                                     \
+    }
 
 // p = r + beta (p - omega v)
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_bicg_p(Segs S, const cpx<R>* __restrict__ r, cpx<R>* __restrict__ p,
                                                    const cpx<R>* __restrict__ v, const ColState* __restrict__ st) {
     const SegPos q = seg_pos(S);
-    if (!st[q.seg].active || !q.live) return;
+    if (!st[q.seg].active) return;
     const ColState& s = st[q.seg];
-    const cpx<R> t = p[q.k] - scal(s.omega_re, s.omega_im, v[q.k]);
-    p[q.k] = r[q.k] + scal(s.beta_re, s.beta_im, t);
+    cpx<R> rv[kElems], pv[kElems], vv[kElems];
+    SEG_LOOP((rv[j] = r[q.at(j)], pv[j] = p[q.at(j)], vv[j] = v[q.at(j)]),
+             (p[q.at(j)] = rv[j] + scal(s.beta_re, s.beta_im, pv[j] - scal(s.omega_re, s.omega_im, vv[j]))))
 }
 
 // s = r - alpha v
@@ -57,8 +79,10 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_bicg_s(Segs S, const cpx<R>* __restrict__ r, const cpx<R>* __restrict__ v,
                                                    cpx<R>* __restrict__ s_, const ColState* __restrict__ st) {
     const SegPos q = seg_pos(S);
-    if (!st[q.seg].active || !q.live) return;
-    s_[q.k] = r[q.k] - scal(st[q.seg].alpha_re, st[q.seg].alpha_im, v[q.k]);
+    if (!st[q.seg].active) return;
+    const ColState& s = st[q.seg];
+    cpx<R> rv[kElems], vv[kElems];
+    SEG_LOOP((rv[j] = r[q.at(j)], vv[j] = v[q.at(j)]), (s_[q.at(j)] = rv[j] - scal(s.alpha_re, s.alpha_im, vv[j])))
 }
 
 // x += alpha p + omega s; r = s - omega t; partials <r^, r>, |r|^2
@@ -70,18 +94,17 @@ __global__ __launch_bounds__(kBlock) void k_bicg_xr(Segs S, cpx<R>* __restrict__
     const SegPos q = seg_pos(S);
     if (!st[q.seg].active) return;  // uniform over the workgroup
     double d0 = 0, d1 = 0, d2 = 0;
-    if (q.live) {
-        const size_t k = q.k;
-        const ColState& s = st[q.seg];
-        const cpx<R> sv = s_[k];
-        x[k] = x[k] + scal(s.alpha_re, s.alpha_im, p[k]) + scal(s.omega_re, s.omega_im, sv);
-        const cpx<R> rn = sv - scal(s.omega_re, s.omega_im, t[k]);
-        r[k] = rn;
-        const cpx<R> h = rh[k];
-        d0 = (double)h.re * rn.re + (double)h.im * rn.im;
-        d1 = (double)h.re * rn.im - (double)h.im * rn.re;
-        d2 = (double)rn.re * rn.re + (double)rn.im * rn.im;
-    }
+    const ColState& s = st[q.seg];
+    cpx<R> xv[kElems], pv[kElems], sv[kElems], tv[kElems], hv[kElems];
+    SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)], sv[j] = s_[q.at(j)], tv[j] = t[q.at(j)], hv[j] = rh[q.at(j)]),
+             ({
+                 x[q.at(j)] = xv[j] + scal(s.alpha_re, s.alpha_im, pv[j]) + scal(s.omega_re, s.omega_im, sv[j]);
+                 const cpx<R> rn = sv[j] - scal(s.omega_re, s.omega_im, tv[j]);
+                 r[q.at(j)] = rn;
+                 d0 += (double)hv[j].re * rn.re + (double)hv[j].im * rn.im;
+                 d1 += (double)hv[j].re * rn.im - (double)hv[j].im * rn.re;
+                 d2 += (double)rn.re * rn.re + (double)rn.im * rn.im;
+             }))
     block_sum3(d0, d1, d2, partial + (size_t)blockIdx.x * 3);
 }
 
@@ -93,14 +116,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_xr(Segs S, cpx<R>* __restrict__ x
     const SegPos q = seg_pos(S);
     if (!st[q.seg].active) return;
     double d0 = 0;
-    if (q.live) {
-        const size_t k = q.k;
-        const R a = R(st[q.seg].alpha_re);
-        x[k] = x[k] + a * p[k];
-        const cpx<R> rn = r[k] - a * w[k];
-        r[k] = rn;
-        d0 = (double)rn.re * rn.re + (double)rn.im * rn.im;
-    }
+    const R a = R(st[q.seg].alpha_re);
+    cpx<R> xv[kElems], pv[kElems], rv[kElems], wv[kElems];
+    SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)], rv[j] = r[q.at(j)], wv[j] = w[q.at(j)]),
+             ({
+                 x[q.at(j)] = xv[j] + a * pv[j];
+                 const cpx<R> rn = rv[j] - a * wv[j];
+                 r[q.at(j)] = rn;
+                 d0 += (double)rn.re * rn.re + (double)rn.im * rn.im;
+             }))
     block_sum3(d0, 0.0, 0.0, partial + (size_t)blockIdx.x * 3);
 }
 
@@ -109,8 +133,10 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cg_p(Segs S, cpx<R>* __restrict__ p, const cpx<R>* __restrict__ z,
                                                  const ColState* __restrict__ st) {
     const SegPos q = seg_pos(S);
-    if (!st[q.seg].active || !q.live) return;
-    p[q.k] = z[q.k] + R(st[q.seg].beta_re) * p[q.k];
+    if (!st[q.seg].active) return;
+    const R b = R(st[q.seg].beta_re);
+    cpx<R> zv[kElems], pv[kElems];
+    SEG_LOOP((zv[j] = z[q.at(j)], pv[j] = p[q.at(j)]), (p[q.at(j)] = zv[j] + b * pv[j]))
 }
 
 // partial |a|^2 of every segment
@@ -118,10 +144,8 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_norm2(Segs S, const cpx<R>* __restrict__ a, double* __restrict__ partial) {
     const SegPos q = seg_pos(S);
     double d0 = 0;
-    if (q.live) {
-        const cpx<R> v = a[q.k];
-        d0 = (double)v.re * v.re + (double)v.im * v.im;
-    }
+    cpx<R> v[kElems];
+    SEG_LOOP((v[j] = a[q.at(j)]), (d0 += (double)v[j].re * v[j].re + (double)v[j].im * v[j].im))
     block_sum3(d0, 0.0, 0.0, partial + (size_t)blockIdx.x * 3);
 }
 
@@ -130,8 +154,9 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_copy_segs(Segs S, const cpx<R>* __restrict__ a, cpx<R>* __restrict__ b,
                                                       const ColState* __restrict__ st) {
     const SegPos q = seg_pos(S);
-    if (!st[q.seg].active || !q.live) return;
-    b[q.k] = a[q.k];
+    if (!st[q.seg].active) return;
+    cpx<R> v[kElems];
+    SEG_LOOP((v[j] = a[q.at(j)]), (b[q.at(j)] = v[j]))
 }
 
 // Reliable-update helpers (segments selected by mask[seg] != 0):
@@ -141,19 +166,19 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_fold_x(Segs S, cpx<double>* __restrict__ x, cpx<R>* __restrict__ xk,
                                                    const int* __restrict__ mask) {
     const SegPos q = seg_pos(S);
-    if (!mask[q.seg] || !q.live) return;
-    const cpx<R> e = xk[q.k];
-    const cpx<double> v = x[q.k];
-    x[q.k] = cd(v.re + (double)e.re, v.im + (double)e.im);
-    xk[q.k] = cpx<R>{R(0), R(0)};
+    if (!mask[q.seg]) return;
+    cpx<R> e[kElems];
+    cpx<double> v[kElems];
+    SEG_LOOP((e[j] = xk[q.at(j)], v[j] = x[q.at(j)]),
+             (x[q.at(j)] = cd(v[j].re + (double)e[j].re, v[j].im + (double)e[j].im), xk[q.at(j)] = cpx<R>{R(0), R(0)}))
 }
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_set_resid(Segs S, const cpx<double>* __restrict__ r64,
                                                       cpx<R>* __restrict__ rk, const int* __restrict__ mask) {
     const SegPos q = seg_pos(S);
-    if (!mask[q.seg] || !q.live) return;
-    const cpx<double> v = r64[q.k];
-    rk[q.k] = cpx<R>{(R)v.re, (R)v.im};
+    if (!mask[q.seg]) return;
+    cpx<double> v[kElems];
+    SEG_LOOP((v[j] = r64[q.at(j)]), (rk[q.at(j)] = cpx<R>{(R)v[j].re, (R)v[j].im}))
 }
 // BiCGStab restart (mask == 2): fresh shadow residual r^ = r, directions cleared
 template <typename R>
@@ -161,20 +186,20 @@ __global__ __launch_bounds__(kBlock) void k_restart_dirs(Segs S, const cpx<R>* _
                                                          cpx<R>* __restrict__ p, cpx<R>* __restrict__ v,
                                                          const int* __restrict__ mask) {
     const SegPos q = seg_pos(S);
-    if (mask[q.seg] != 2 || !q.live) return;
-    rh[q.k] = r[q.k];
-    p[q.k] = cpx<R>{R(0), R(0)};
-    v[q.k] = cpx<R>{R(0), R(0)};
+    if (mask[q.seg] != 2) return;
+    cpx<R> v_[kElems];
+    SEG_LOOP((v_[j] = r[q.at(j)]),
+             (rh[q.at(j)] = v_[j], p[q.at(j)] = cpx<R>{R(0), R(0)}, v[q.at(j)] = cpx<R>{R(0), R(0)}))
 }
 // CGNR reliable update: p += t - z; z = t
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cg_shift(Segs S, cpx<R>* __restrict__ p, cpx<R>* __restrict__ z,
                                                      const cpx<R>* __restrict__ t, const int* __restrict__ mask) {
     const SegPos q = seg_pos(S);
-    if (!mask[q.seg] || !q.live) return;
-    const cpx<R> tv = t[q.k];
-    p[q.k] = p[q.k] + tv - z[q.k];
-    z[q.k] = tv;
+    if (!mask[q.seg]) return;
+    cpx<R> tv[kElems], pv[kElems], zv[kElems];
+    SEG_LOOP((tv[j] = t[q.at(j)], pv[j] = p[q.at(j)], zv[j] = z[q.at(j)]),
+             (p[q.at(j)] = pv[j] + tv[j] - zv[j], z[q.at(j)] = tv[j]))
 }
 
 // One workgroup per segment: fixed-order sum of the segment's partial slots
@@ -300,6 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int fin, const int* __restr
     }
 }
 
+
+#undef SEG_LOOP
 
 }  // namespace
 

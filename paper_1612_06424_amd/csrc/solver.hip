@@ -477,7 +477,8 @@ struct SingleSystem : System {
 dd_status SegLayout::upload(dd_ctx* c, Slot slot, System* S) {
     const int ns = (int)off.size();
     eb0.assign(ns + 1, 0);
-    for (int k = 0; k < ns; k++) eb0[k + 1] = eb0[k] + (len[k] + kBlock - 1) / kBlock;
+    const int per = kBlock * kElems;  // elements per elementwise workgroup
+    for (int k = 0; k < ns; k++) eb0[k + 1] = eb0[k] + (len[k] + per - 1) / per;
     const int neb = eb0[ns];
     eseg.resize(neb);
     for (int k = 0; k < ns; k++)
