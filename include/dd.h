@@ -76,6 +76,13 @@ typedef enum {
     DD_CGNR = 1       /* CG on D^+ D x = D^+ b (converges wherever D is invertible) */
 } dd_solver_kind;
 
+typedef enum {
+    DD_PRECOND_EO = 0,   /* even-odd: solve the even-site Schur complement m - H_eo H_oe / (4m)
+                            where the lattice is bipartite (L even; T even for a whole lattice),
+                            otherwise no preconditioning */
+    DD_PRECOND_NONE = 1  /* always solve with the full operator */
+} dd_precond;
+
 typedef struct {
     int T, L;      /* lattice extent T x L^3, L >= 2, T >= 2 */
     int time_bc;   /* -1 antiperiodic, +1 periodic, 0 Dirichlet walls at t = 0 and T-1 */
@@ -100,6 +107,7 @@ typedef struct {
     int solver;        /* dd_solver_kind */
     double delta;      /* reliable-update threshold in (0, 1); 0: 0.1 (DD_FP64), 0.01 (DD_MIXED) */
     int check_every;   /* iterations between host-side convergence reads (0: 8) */
+    int precond;       /* dd_precond (single-lattice solves; batched solves use the full operator) */
 } dd_solver_params;
 
 typedef struct {

@@ -145,6 +145,7 @@ dd_status check_params(dd_ctx* c, const dd_solver_params* p) {
     if (p->prec != DD_FP64 && p->prec != DD_MIXED) return fail(c, DD_ERR_ARG, "solver prec must be DD_FP64 or DD_MIXED");
     if (!(p->delta >= 0) || p->delta >= 1) return fail(c, DD_ERR_ARG, "solver delta must lie in [0, 1)");
     if (p->solver != DD_BICGSTAB && p->solver != DD_CGNR) return fail(c, DD_ERR_ARG, "unknown solver kind");
+    if (p->precond != DD_PRECOND_EO && p->precond != DD_PRECOND_NONE) return fail(c, DD_ERR_ARG, "unknown precond");
     return DD_OK;
 }
 

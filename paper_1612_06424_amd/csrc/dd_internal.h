@@ -150,7 +150,7 @@ enum Slot {
     W_B32, W_X32, W_U32, W_RES64,
     W_PART, W_STATE, W_STATE32, W_DOTS,
     W_AUX0, W_AUX1, W_AUX2, W_AUX3, W_AUX4,
-    W_SEGS, W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
+    W_SEGS, W_SEGN, W_EO_B, W_EO_X, W_EO_BHAT, W_EO_T64, W_EO_T32, W_EO_U64, W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
     W_NSLOTS
 };
 
@@ -269,6 +269,7 @@ struct System {
     size_t nslots = 0;                     // partial slots needed by any launch
     bool graph = false;                    // replay the inner iterations from a captured HIP graph
     bool has32 = false;                    // FP32 stencil available (links converted)
+    const double* ref_norm2 = nullptr;     // host [nseg]: |.|^2 that residuals are relative to (default |b|^2)
     virtual ~System() {}
     virtual void apply64(int dag, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux,
                          double* partial, const ColState* st) = 0;
@@ -308,6 +309,12 @@ struct SolveResult {
 // result filled.
 dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd_solver_params& p,
                        SolveResult* res);
+
+// Even-odd preconditioned solve of one lattice or slab (evenodd.hip); usable
+// when the lattice is bipartite: L even, and nt even for a whole lattice.
+bool eo_applicable(const Geo& g);
+dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
+                   cpx<double>* x, const dd_solver_params& p, dd_solve_stats* stats, int dag);
 
 // |a_j|^2 of the ncol columns of a (each n elements), into out; synchronises.
 dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::vector<double>* out);

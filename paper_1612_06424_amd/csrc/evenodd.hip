@@ -1,0 +1,282 @@
+// evenodd.hip -- even-odd preconditioned solves on one lattice or slab.
+//
+// D x = b (or D^+ x = b) is solved through the Schur complement on the even
+// sites (dd_eo.h): the source is prepared with one half hop, the reliable-
+// update Krylov solver of solver.hip runs on the half fields with
+// Dhat = m - (1/(4m)) H_eo H_oe applied as two half hops, the odd half is
+// reconstructed with one more half hop, and the answer is checked against the
+// full operator (true FP64 residual |b - D x| / |b|).  Since the full residual
+// equals the Schur residual on the even sites, the Schur solve converges on
+// |b_e' - Dhat x_e| <= tol |b| (the norm of the original source).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "dd_eo.h"
+
+namespace dd {
+
+namespace {
+
+// Workgroup -> (column fastest, block of NT half sites); partial slot of
+// (col, block) = col * nblk + block.
+template <typename R, int DAG, int EPI, int NT>
+__global__ __launch_bounds__(NT) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self, R c_hop, int p_out,
+                                               const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
+                                               cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux, int ncol,
+                                               double* __restrict__ partial, const ColState* __restrict__ st) {
+    const int lb = (int)blockIdx.x;
+    const int col = lb % ncol, hb = lb / ncol;
+    if (st != nullptr && !st[col].active) return;  // uniform over the workgroup
+    const int nblk = (int)gridDim.x / ncol;
+    const size_t off = (size_t)col * 12 * (size_t)(g.nsite >> 1);
+    const int h = hb * NT + (int)threadIdx.x;
+    eo_hop_site<R, DAG, EPI, NT>(g, U, a_self, c_hop, p_out, h, in + off, self != nullptr ? self + off : nullptr,
+                                 out + off, aux != nullptr ? aux + off : nullptr,
+                                 partial + ((size_t)col * nblk + hb) * 3);
+}
+
+// full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
+__global__ __launch_bounds__(kBlock) void k_eo_split(Geo g, int ncol, const cpx<double>* __restrict__ full,
+                                                     cpx<double>* __restrict__ ev, cpx<double>* __restrict__ od) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const size_t n = (size_t)ncol * 12 * g.nsite;
+    if (i >= n) return;
+    const int s = (int)(i % (size_t)g.nsite);
+    const size_t row = i / (size_t)g.nsite;  // col * 12 + component
+    const int tl = s / g.L3, sp = s - tl * g.L3;
+    const int par = (tl + sp % g.L + (sp / g.L) % g.L + sp / g.L2) & 1;
+    const size_t j = row * (size_t)(g.nsite >> 1) + (size_t)(s >> 1);
+    (par ? od : ev)[j] = full[i];
+}
+__global__ __launch_bounds__(kBlock) void k_eo_merge(Geo g, int ncol, const cpx<double>* __restrict__ ev,
+                                                     const cpx<double>* __restrict__ od,
+                                                     cpx<double>* __restrict__ full) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const size_t n = (size_t)ncol * 12 * g.nsite;
+    if (i >= n) return;
+    const int s = (int)(i % (size_t)g.nsite);
+    const size_t row = i / (size_t)g.nsite;
+    const int tl = s / g.L3, sp = s - tl * g.L3;
+    const int par = (tl + sp % g.L + (sp / g.L) % g.L + sp / g.L2) & 1;
+    const size_t j = row * (size_t)(g.nsite >> 1) + (size_t)(s >> 1);
+    full[i] = (par ? od : ev)[j];
+}
+
+// Ueo[mu][k][parity][nsite / 2] (precision R) from the lattice links U[mu][k][V]
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_links_eo(Geo g, const cpx<double>* __restrict__ U,
+                                                     cpx<R>* __restrict__ Ueo) {
+    const int s = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (s >= g.nsite) return;
+    const int tl = s / g.L3, sp = s - tl * g.L3;
+    const int t = g.t0 + tl;
+    const size_t sl = (size_t)(t >= g.T ? t - g.T : t) * g.L3 + sp;
+    const int par = (tl + sp % g.L + (sp / g.L) % g.L + sp / g.L2) & 1;
+    const size_t nh = (size_t)(g.nsite >> 1);
+    for (int row = 0; row < 36; row++) {
+        const cpx<double> v = U[(size_t)row * g.vlink + sl];
+        Ueo[((size_t)row * 2 + par) * nh + (size_t)(s >> 1)] = cpx<R>{(R)v.re, (R)v.im};
+    }
+}
+
+constexpr int kEoNT = 256;
+
+int eo_blocks(const Geo& g) { return ((g.nsite >> 1) + kEoNT - 1) / kEoNT; }
+
+template <typename R, int DAG>
+void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
+                   const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, double* partial,
+                   const ColState* st) {
+    const dim3 block(kEoNT);
+#define DD_EO_CASE(E)                                                                                              \
+    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, self, out, \
+                       aux, ncol, partial, st)
+    switch (epi) {
+        case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
+        case EPI_DOT_AUX: DD_EO_CASE(EPI_DOT_AUX); break;
+        case EPI_TS: DD_EO_CASE(EPI_TS); break;
+        case EPI_RESID: DD_EO_CASE(EPI_RESID); break;
+        default: DD_EO_CASE(EPI_NORM); break;
+    }
+#undef DD_EO_CASE
+}
+
+// out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns
+template <typename R>
+void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, double c_hop, int p_out, int dag,
+                   int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol,
+                   double* partial, const ColState* st) {
+    const dim3 grid((unsigned)(eo_blocks(g) * ncol));
+    hipEvent_t ev = nullptr;
+    if (c->timing) timing_begin(c, &ev);
+    if (dag)
+        launch_eo_epi<R, 1>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, partial,
+                            st);
+    else
+        launch_eo_epi<R, 0>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, partial,
+                            st);
+    if (c->timing) {
+        // per output half site: the input spinor, the output (+ self / aux when read), and the
+        // links: every link of the field is used once by one output site of a given parity
+        const double nh = (double)(g.nsite >> 1);
+        const double extra = (a_self != 0 || epi == EPI_TS ? 24.0 : 0.0) +
+                             (epi == EPI_DOT_AUX || epi == EPI_RESID ? 24.0 : 0.0);
+        const double bytes = nh * ((48.0 + extra) * ncol + 144.0) * sizeof(R);
+        const std::string name = std::string("k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+                                 std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
+                                 std::to_string(kEoNT) + ">";
+        timing_end(c, ev, name, bytes);
+    }
+}
+
+// The Schur complement of one lattice or slab: segments are the ncol even
+// half-field columns; apply = two half hops through a scratch odd half field.
+struct EOSystem : System {
+    Geo g{};
+    const cpx<double>* U64 = nullptr;  // checkerboard-ordered links of the field (Ueo)
+    const cpx<float>* U32 = nullptr;
+    double m = 0;  // 1 / (2 kappa)
+    int dag = 0;
+    int ncol = 0;
+    cpx<double>* tmp64 = nullptr;
+    cpx<float>* tmp32 = nullptr;
+    template <typename R>
+    void schur(const cpx<R>* UR, cpx<R>* tmp, int d, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux,
+               double* partial, const ColState* st) {
+        launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, partial, st);
+        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, partial, st);
+    }
+    void apply64(int d, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux, double* partial,
+                 const ColState* st) override {
+        schur<double>(U64, tmp64, d ^ dag, epi, in, out, aux, partial, st);
+    }
+    void apply32(int d, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux, double* partial,
+                 const ColState* st) override {
+        schur<float>(U32, tmp32, d ^ dag, epi, in, out, aux, partial, st);
+    }
+};
+
+}  // namespace
+
+bool eo_applicable(const Geo& g) { return g.L % 2 == 0 && (!g.whole || g.nt % 2 == 0); }
+
+dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
+                   cpx<double>* x, const dd_solver_params& p, dd_solve_stats* stats, int dag) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const size_t nh = (size_t)(g.nsite >> 1);
+    const size_t nhalf = (size_t)ncol * 12 * nh;  // elements of one half field (all columns)
+    const size_t nfull = 2 * nhalf;
+    const double m = 1.0 / (2.0 * kappa);
+    dd_status e = DD_OK;
+    // b_e | b_o, later the full residual; x_e | x_o; the prepared source; the odd scratch fields
+    cpx<double>* bb = (cpx<double>*)workspace(c, W_EO_B, nfull * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* xx = (cpx<double>*)workspace(c, W_EO_X, nfull * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* bhat = (cpx<double>*)workspace(c, W_EO_BHAT, nhalf * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    // checkerboard-ordered links of the field: FP64 always, FP32 for DD_MIXED
+    const size_t nl = (size_t)36 * g.nsite;
+    const unsigned glink = (unsigned)((g.nsite + kBlock - 1) / kBlock);
+    cpx<double>* Ueo64 = (cpx<double>*)workspace(c, W_EO_U64, nl * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    hipLaunchKernelGGL(k_links_eo<double>, dim3(glink), dim3(kBlock), 0, c->stream, g, U, Ueo64);
+    EOSystem S;
+    S.c = c;
+    S.g = g;
+    S.U64 = Ueo64;
+    S.m = m;
+    S.dag = dag;
+    S.ncol = ncol;
+    S.nelem = nhalf;
+    S.tmp64 = (cpx<double>*)workspace(c, W_EO_T64, nhalf * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    if (p.prec == DD_MIXED) {
+        cpx<float>* U32 = (cpx<float>*)workspace(c, W_U32, nl * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+        hipLaunchKernelGGL(k_links_eo<float>, dim3(glink), dim3(kBlock), 0, c->stream, g, U, U32);
+        S.U32 = U32;
+        S.tmp32 = (cpx<float>*)workspace(c, W_EO_T32, nhalf * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+        S.has32 = true;
+    }
+    SegLayout lay;
+    const int n = (int)(12 * nh);
+    const int nblk = eo_blocks(g);
+    for (int k = 0; k < ncol; k++) {
+        lay.off.push_back((long long)k * n);
+        lay.len.push_back(n);
+    }
+    for (int kind = 0; kind < 2; kind++) {
+        lay.sp0[kind].resize(ncol + 1);
+        for (int k = 0; k <= ncol; k++) lay.sp0[kind][k] = k * nblk;
+    }
+    e = lay.upload(c, W_SEGS, &S);
+    if (e != DD_OK) return e;
+    // the partial slots of the source preparation and reconstruction use the same layout
+    S.nslots = std::max(S.nslots, (size_t)ncol * nblk);
+
+    // |b|^2 per column: the reference of every relative residual
+    std::vector<double> bnorm;
+    e = column_norms(c, (int)(12 * g.nsite), ncol, b, &bnorm);
+    if (e != DD_OK) return e;
+    for (double v : bnorm)
+        if (!std::isfinite(v)) return fail(c, DD_ERR_BREAKDOWN, "non-finite values in the right-hand side");
+    S.ref_norm2 = bnorm.data();
+
+    const unsigned gsplit = (unsigned)((nfull + kBlock - 1) / kBlock);
+    cpx<double>*b_e = bb, *b_o = bb + nhalf, *x_e = xx, *x_o = xx + nhalf;
+    hipLaunchKernelGGL(k_eo_split, dim3(gsplit), dim3(kBlock), 0, c->stream, g, ncol, b, b_e, b_o);
+    double* partial = (double*)workspace(c, W_PART, S.nslots * 3 * sizeof(double), &e);
+    if (e != DD_OK) return e;
+    // b_e' = b_e + (1/(2m)) H_eo b_o
+    launch_eo_hop<double>(c, g, Ueo64, 1.0, 0.5 / m, 0, dag, EPI_STORE, b_o, b_e, bhat, nullptr, ncol, partial,
+                          nullptr);
+
+    SolveResult res;
+    dd_status st = solve_system(S, bhat, x_e, p, &res);
+    if (st != DD_OK && st != DD_ERR_NOCONV && st != DD_ERR_BREAKDOWN) return st;
+
+    // x_o = (b_o + 1/2 H_oe x_e) / m, then the full answer and its true residual
+    launch_eo_hop<double>(c, g, Ueo64, 1.0 / m, 0.5 / m, 1, dag, EPI_STORE, x_e, b_o, x_o, nullptr, ncol, partial,
+                          nullptr);
+    hipLaunchKernelGGL(k_eo_merge, dim3(gsplit), dim3(kBlock), 0, c->stream, g, ncol, x_e, x_o, x);
+    cpx<double>* r = bb;  // b_e | b_o are no longer needed
+    const size_t rslots = std::max(S.nslots, (size_t)ncol * stencil_slots(c, g, 0, ncol));
+    partial = (double*)workspace(c, W_PART, rslots * 3 * sizeof(double), &e);
+    if (e != DD_OK) return e;
+    launch_dslash<double>(c, g, U, kappa, dag, EPI_RESID, x, r, b, ncol, partial, nullptr);
+    DD_HIP(c, hipGetLastError());
+    std::vector<double> rr;
+    e = column_norms(c, (int)(12 * g.nsite), ncol, r, &rr);
+    if (e != DD_OK) return e;
+    bool converged = st == DD_OK, nonfinite = st == DD_ERR_BREAKDOWN;
+    std::vector<double> rel(ncol, 0.0);
+    for (int j = 0; j < ncol; j++) {
+        if (!std::isfinite(rr[j])) nonfinite = true;
+        rel[j] = bnorm[j] > 0 ? std::sqrt(rr[j] / bnorm[j]) : 0.0;
+        if (!(rel[j] <= p.tol)) converged = false;
+    }
+    if (stats) {
+        stats->nrhs = ncol;
+        stats->iters = res.iters;
+        stats->updates = res.updates;
+        stats->restarts = res.restarts;
+        for (int j = 0; j < DD_MAX_RHS; j++) stats->true_rel_resid[j] = j < ncol ? rel[j] : 0.0;
+        stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (nonfinite) return fail(c, DD_ERR_BREAKDOWN, "non-finite values in the Krylov iteration");
+    if (!converged) {
+        double worst = 0;
+        for (double v : rel) worst = std::max(worst, v);
+        return fail(c, DD_ERR_NOCONV,
+                    "even-odd solver stopped after " + std::to_string(res.iters) +
+                        " iterations with relative residual " + std::to_string(worst) + " > tol " +
+                        std::to_string(p.tol));
+    }
+    return DD_OK;
+}
+
+}  // namespace dd

@@ -541,6 +541,11 @@ dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd
     for (int j = 0; j < ns; j++) bb[j] = c->host_dots[3 * j];
     for (int j = 0; j < ns; j++)
         if (!std::isfinite(bb[j])) return fail(c, DD_ERR_BREAKDOWN, "non-finite values in the right-hand side");
+    // relative residuals refer to |b|^2, or to the norm the System names (the
+    // original source of a preconditioned system); a zero source stays done
+    if (S.ref_norm2 != nullptr)
+        for (int j = 0; j < ns; j++)
+            if (bb[j] > 0) bb[j] = S.ref_norm2[j];
 
     const bool mixed = p.prec == DD_MIXED;
     if (mixed && !S.has32) return fail(c, DD_ERR_ARG, "DD_MIXED needs FP32 links");
@@ -607,7 +612,7 @@ dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::ve
     }
     lay.sp0[0].assign(ncol + 1, 0);
     lay.sp0[1].assign(ncol + 1, 0);
-    dd_status e = lay.upload(c, W_SEGS, &S);
+    dd_status e = lay.upload(c, W_SEGN, &S);  // own slot: a System's tables may be live in W_SEGS
     if (e != DD_OK) return e;
     e = ensure_host(c, ncol);
     if (e != DD_OK) return e;
@@ -625,6 +630,7 @@ dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::ve
 // Solve M x = b on one lattice or slab for ncol columns (M = D, or D^+ for dag).
 dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
                 cpx<double>* x, const dd_solver_params& p, dd_solve_stats* stats, int dag) {
+    if (p.precond == DD_PRECOND_EO && eo_applicable(g)) return solve_eo(c, U, kappa, g, ncol, b, x, p, stats, dag);
     const auto t_start = std::chrono::steady_clock::now();
     SingleSystem S;
     S.c = c;

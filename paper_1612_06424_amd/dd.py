@@ -30,6 +30,7 @@ _lib = C.CDLL(LIB_PATH)
 DD_OK, DD_ERR_ARG, DD_ERR_HIP, DD_ERR_NOMEM, DD_ERR_NOCONV, DD_ERR_BREAKDOWN, DD_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 DD_FP64, DD_FP32, DD_MIXED = 0, 1, 2
 DD_BICGSTAB, DD_CGNR = 0, 1
+DD_PRECOND_EO, DD_PRECOND_NONE = 0, 1
 DD_MAX_RHS = 12
 
 EXPORTS = [
@@ -50,7 +51,7 @@ class dd_domain(C.Structure):
 
 class dd_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("prec", C.c_int), ("solver", C.c_int),
-                ("delta", C.c_double), ("check_every", C.c_int)]
+                ("delta", C.c_double), ("check_every", C.c_int), ("precond", C.c_int)]
 
 
 class dd_solve_stats(C.Structure):
@@ -103,9 +104,12 @@ class DDError(RuntimeError):
         self.status = status
 
 
-def solver_params(tol=1e-10, max_iter=20000, prec=DD_FP64, solver=DD_CGNR, delta=0.0, check_every=0):
-    """Solver parameters; delta = 0 takes the library's reliable-update threshold."""
-    return dd_solver_params(float(tol), int(max_iter), int(prec), int(solver), float(delta), int(check_every))
+def solver_params(tol=1e-10, max_iter=20000, prec=DD_FP64, solver=DD_CGNR, delta=0.0, check_every=0,
+                  precond=None):
+    """Solver parameters; delta = 0 takes the library's reliable-update threshold; precond
+    defaults to even-odd (used where the lattice allows it)."""
+    return dd_solver_params(float(tol), int(max_iter), int(prec), int(solver), float(delta), int(check_every),
+                            DD_PRECOND_EO if precond is None else int(precond))
 
 
 def _dom(dom):

@@ -164,3 +164,60 @@ def test_error_paths():
     assert e.value.status == dd.DD_ERR_ARG
     with pytest.raises(ValueError):
         dd.apply_dirac(ctx, Ud, 0.13, b.cpu())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("T,L,bc,dom", [
+    (16, 4, -1, None),      # whole lattice, T and L even: even-odd applies
+    (12, 6, -1, (9, 5)),    # odd-length slab across the time wrap
+    (8, 4, 0, None),        # Dirichlet time walls
+])
+def test_even_odd_matches_full_operator(prec, solver, T, L, bc, dom):
+    """The even-odd preconditioned solve and the plain one both reach the oracle's
+    solution (and so each other)."""
+    dd = lib()
+    step(f"even-odd {prec} solver={solver} T={T} L={L} bc={bc} dom={dom}")
+    kappa = 0.13
+    U = random_links(T, L, 0.3, 2500 + T)
+    nsite = (T if dom is None else dom[1]) * L ** 3
+    b = gaussian_field(nsite, 4, 2501)
+    ref, _, _, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=1e-13, method=1)
+    assert st == 0
+    ctx = dd.Context(T, L, bc)
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    bar = 1e-10 if prec == "fp64" else 1e-6
+    got = {}
+    for pc in (dd.DD_PRECOND_EO, dd.DD_PRECOND_NONE):
+        p = dd.solver_params(tol=tol, prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, solver=solver, precond=pc)
+        x, stats = dd.block_solve(ctx, dd.pack_links(U), kappa, dd.pack_field(b), dom, p)
+        assert max(stats["true_rel_resid"]) <= tol
+        got[pc] = dd.unpack_field(x)
+        assert relerr(got[pc], ref) < bar
+    assert relerr(got[dd.DD_PRECOND_EO], got[dd.DD_PRECOND_NONE]) < 2 * bar
+
+
+def test_even_odd_adjoint_and_fallback():
+    """D^+ solves go through the even-odd path too; an odd time extent on a whole
+    lattice (not bipartite) falls back to the full operator and still converges."""
+    dd = lib()
+    step("even-odd adjoint + odd-T fallback")
+    T, L, bc, kappa = 8, 4, -1, 0.13
+    U = random_links(T, L, 0.3, 2600)
+    b = gaussian_field(T * L ** 3, 2, 2601)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U)
+    p = dd.solver_params(tol=1e-12)
+    x, _ = dd.block_solve(ctx, Ud, kappa, dd.pack_field(b), None, p)
+    g = gaussian_field(T * L ** 3, 2, 2602)
+    gb, _, _ = dd.block_solve_backward(ctx, Ud, kappa, x, dd.pack_field(g), None, p)
+    lam = dd.unpack_field(gb)
+    assert relerr(O.gamma5(O.apply_dirac(U, kappa, T, L, bc, O.gamma5(lam))), g) < 1e-11
+    T2 = 7
+    U2 = random_links(T2, L, 0.3, 2603)
+    b2 = gaussian_field(T2 * L ** 3, 2, 2604)
+    ctx2 = dd.Context(T2, L, bc)
+    x2, st2 = dd.block_solve(ctx2, dd.pack_links(U2), kappa, dd.pack_field(b2), None, p)
+    assert max(st2["true_rel_resid"]) <= 1e-12
+    ref, _, _, _ = O.solve(U2, kappa, T2, L, bc, b2, tol=1e-13, method=1)
+    assert relerr(dd.unpack_field(x2), ref) < 1e-10
