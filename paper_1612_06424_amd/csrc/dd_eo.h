@@ -16,6 +16,7 @@
 // is dropped, so no link outside the field is needed.  One thread computes
 // one output half site:
 //     out = a_self * self + c_hop * (H in)_site      (in: the other parity)
+// (SELF = false: no self term, the pure hop).
 // with the fused epilogues of the full stencil (dd_dslash.h).
 #pragma once
 
@@ -24,7 +25,7 @@
 
 namespace dd {
 
-template <typename R, int DAG, int EPI, int NT>
+template <typename R, int DAG, int EPI, int NT, bool SELF>
 __device__ __forceinline__ void eo_hop_site(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
                                             int p_out, int h, const cpx<R>* __restrict__ in,
                                             const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
@@ -82,7 +83,7 @@ __device__ __forceinline__ void eo_hop_site(const Geo& g, const cpx<R>* __restri
         bhop<R, 3, BW, true>(a, rf, cs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1, R(1));
 
         const rsrc_t ro = make_rsrc(out, 12u * cs);
-        const bool has_self = a_self != R(0) || EPI == EPI_TS;
+        constexpr bool has_self = SELF || EPI == EPI_TS;
         const rsrc_t rs = make_rsrc(self != nullptr ? self : in, 12u * cs);
         const rsrc_t rx = make_rsrc(aux != nullptr ? aux : in, 12u * cs);
         const uint32_t vo = (uint32_t)h * CB;

@@ -16,6 +16,25 @@ namespace dd {
 
 constexpr int kBlock = 256;   // threads per workgroup for site-parallel kernels
 constexpr int kElems = 4;     // elements per thread of the solver vector kernels
+
+// Minimum resident waves per SIMD asked of the stencil kernels (bounds their
+// register use): [0] FP64, [1] FP32, for the time-sweep and the half-hop kernels.
+#ifndef DD_SWEEP_WAVES64
+#define DD_SWEEP_WAVES64 1
+#endif
+#ifndef DD_SWEEP_WAVES32
+#define DD_SWEEP_WAVES32 1
+#endif
+#ifndef DD_EO_WAVES64
+#define DD_EO_WAVES64 1
+#endif
+#ifndef DD_EO_WAVES32
+#define DD_EO_WAVES32 1
+#endif
+template <typename R>
+constexpr int sweep_waves() { return sizeof(R) == 8 ? DD_SWEEP_WAVES64 : DD_SWEEP_WAVES32; }
+template <typename R>
+constexpr int eo_waves() { return sizeof(R) == 8 ? DD_EO_WAVES64 : DD_EO_WAVES32; }
 constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kNumXcd = 8;    // MI355X: workgroups are dealt round-robin over 8 XCDs
 

@@ -13,7 +13,7 @@ namespace {
 // Workgroup index -> (column fastest, spatial block, time chunk), optionally
 // remapped so that each XCD takes a contiguous range of workgroups.
 template <typename R, int DAG, int EPI, int NT>
-__global__ __launch_bounds__(NT) void k_dslash(Geo g, const cpx<R>* __restrict__ U, R mass,
+__global__ __launch_bounds__(NT, sweep_waves<R>()) void k_dslash(Geo g, const cpx<R>* __restrict__ U, R mass,
                                                const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                const cpx<R>* __restrict__ aux, int ncol, int tc_len,
                                                int remap, double* __restrict__ partial,

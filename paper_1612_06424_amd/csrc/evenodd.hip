@@ -21,8 +21,8 @@ namespace {
 
 // Workgroup -> (column fastest, block of NT half sites); partial slot of
 // (col, block) = col * nblk + block.
-template <typename R, int DAG, int EPI, int NT>
-__global__ __launch_bounds__(NT) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self, R c_hop, int p_out,
+template <typename R, int DAG, int EPI, int NT, bool SELF>
+__global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self, R c_hop, int p_out,
                                                const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
                                                cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux, int ncol,
                                                double* __restrict__ partial, const ColState* __restrict__ st) {
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(NT) void k_eo_hop(Geo g, const cpx<R>* __restrict__
     const int nblk = (int)gridDim.x / ncol;
     const size_t off = (size_t)col * 12 * (size_t)(g.nsite >> 1);
     const int h = hb * NT + (int)threadIdx.x;
-    eo_hop_site<R, DAG, EPI, NT>(g, U, a_self, c_hop, p_out, h, in + off, self != nullptr ? self + off : nullptr,
+    eo_hop_site<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, h, in + off, self != nullptr ? self + off : nullptr,
                                  out + off, aux != nullptr ? aux + off : nullptr,
                                  partial + ((size_t)col * nblk + hb) * 3);
 }
@@ -85,13 +85,13 @@ constexpr int kEoNT = 256;
 
 int eo_blocks(const Geo& g) { return ((g.nsite >> 1) + kEoNT - 1) / kEoNT; }
 
-template <typename R, int DAG>
+template <typename R, int DAG, bool SELF>
 void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
                    const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, double* partial,
                    const ColState* st) {
     const dim3 block(kEoNT);
 #define DD_EO_CASE(E)                                                                                              \
-    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, self, out, \
+    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, self, out, \
                        aux, ncol, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
@@ -111,12 +111,17 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, doub
     const dim3 grid((unsigned)(eo_blocks(g) * ncol));
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
-    if (dag)
-        launch_eo_epi<R, 1>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, partial,
-                            st);
-    else
-        launch_eo_epi<R, 0>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, partial,
-                            st);
+#define DD_EO_LAUNCH(D, SF) \
+    launch_eo_epi<R, D, SF>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, partial, st)
+    const bool sf = self != nullptr && a_self != 0;
+    if (dag) {
+        if (sf) DD_EO_LAUNCH(1, true);
+        else DD_EO_LAUNCH(1, false);
+    } else {
+        if (sf) DD_EO_LAUNCH(0, true);
+        else DD_EO_LAUNCH(0, false);
+    }
+#undef DD_EO_LAUNCH
     if (c->timing) {
         // per output half site: the input spinor, the output (+ self / aux when read), and the
         // links: every link of the field is used once by one output site of a given parity
