@@ -10,11 +10,18 @@
 // time-chunk length) is tuned on the batch itself before the solve, and the
 // inner Krylov iterations are captured once into a HIP graph and replayed on
 // a library-owned stream.
+//
+// When every domain is bipartite (and even-odd preconditioning is asked for)
+// the batch solves the even-site Schur complements of all domains together
+// (dd_eo.h), with a multi-domain half-hop kernel; the source preparation, the
+// reconstruction of the odd sites and the final check on the full operator run
+// domain by domain.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
 
 #include "dd_dslash.h"
+#include "dd_eo.h"
 
 namespace dd {
 
@@ -58,6 +65,64 @@ __global__ __launch_bounds__(NT) void k_bdslash(const BDom* __restrict__ doms, i
     double* slot = partial + ((size_t)d.slot0 + (size_t)col * d.nsb * d.nchunk + (size_t)tc * d.nsb + sb) * 3;
     dslash_tile<R, DAG, EPI, NT>(g, (const cpx<R>*)d.U, R(d.mass), in + off, out + off,
                                  aux != nullptr ? aux + off : nullptr, sb, tc, d.tc, slot);
+}
+
+// One domain of an even-odd batch in one precision.
+struct BEODom {
+    Geo g;
+    const void* Ueo;   // its checkerboard-ordered links, cpx<R>
+    double mass;       // 1 / (2 kappa)
+    long long hoff;    // element offset of its column 0 in the half-field work vectors
+    int ncol, seg0, blk0;
+    int nblk;          // workgroups per column
+    int slot0;         // its first partial slot
+    int pad;
+};
+static_assert(sizeof(BEODom) % 8 == 0, "descriptor layout must be the same on host and device");
+
+constexpr int kBeoNT = 256;
+
+// SCHUR = false: out = H_oe in (odd sites); SCHUR = true: out = m self - H_eo in / (4m) (even sites)
+template <typename R, int DAG, int EPI, bool SCHUR>
+__global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ doms, int ndom,
+                                                   const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
+                                                   cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
+                                                   double* __restrict__ partial, const ColState* __restrict__ st) {
+    const int bid = (int)blockIdx.x;
+    int lo = 0, hi = ndom - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (doms[mid].blk0 <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const BEODom& d = doms[lo];
+    const int lb = bid - d.blk0;
+    const int col = lb % d.ncol, hb = lb / d.ncol;
+    if (st != nullptr && !st[d.seg0 + col].active) return;  // uniform over the workgroup
+    const Geo g = d.g;
+    const size_t off = (size_t)d.hoff + (size_t)col * 12 * (size_t)(g.nsite >> 1);
+    const R a_self = SCHUR ? R(d.mass) : R(0);
+    const R c_hop = SCHUR ? R(-0.25 / d.mass) : R(1);
+    eo_hop_site<R, DAG, EPI, kBeoNT, SCHUR>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1,
+                                            hb * kBeoNT + (int)threadIdx.x, in + off, self != nullptr ? self + off : nullptr,
+                                            out + off, aux != nullptr ? aux + off : nullptr,
+                                            partial + ((size_t)d.slot0 + (size_t)col * d.nblk + hb) * 3);
+}
+
+template <typename R, int DAG, bool SCHUR>
+void launch_beo(hipStream_t s, int epi, unsigned nblk, const BEODom* doms, int ndom, const cpx<R>* in,
+                const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, double* partial, const ColState* st) {
+    const dim3 grid(nblk), block(kBeoNT);
+#define DD_BEO_CASE(E) \
+    hipLaunchKernelGGL((k_beo_hop<R, DAG, E, SCHUR>), grid, block, 0, s, doms, ndom, in, self, out, aux, partial, st)
+    switch (epi) {
+        case EPI_STORE: DD_BEO_CASE(EPI_STORE); break;
+        case EPI_DOT_AUX: DD_BEO_CASE(EPI_DOT_AUX); break;
+        case EPI_TS: DD_BEO_CASE(EPI_TS); break;
+        case EPI_RESID: DD_BEO_CASE(EPI_RESID); break;
+        default: DD_BEO_CASE(EPI_NORM); break;
+    }
+#undef DD_BEO_CASE
 }
 
 template <typename R, int DAG, int NT>
@@ -191,6 +256,57 @@ struct BatchSystem : System {
     }
 };
 
+// The even-site Schur complements of every domain of a batch: segments are
+// the even half-field columns, apply = two multi-domain half hops through an
+// odd half-field scratch vector.
+struct BatchEOSystem : System {
+    const BEODom* doms[2] = {nullptr, nullptr};  // kind 0: FP64 links, 1: FP32 links
+    std::vector<BEODom> host;                    // FP64 descriptors (sizes, for timing)
+    int ndom = 0;
+    unsigned nblk = 0;
+    cpx<double>* tmp64 = nullptr;
+    cpx<float>* tmp32 = nullptr;
+
+    template <typename R>
+    void schur(const BEODom* dv, cpx<R>* tmp, int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux,
+               double* partial, const ColState* st) {
+        for (int half = 0; half < 2; half++) {
+            const int e = half ? epi : EPI_STORE;
+            hipEvent_t ev = nullptr;
+            if (c->timing) timing_begin(c, &ev);
+            if (half == 0) {
+                if (dag) launch_beo<R, 1, false>(c->stream, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, partial, st);
+                else launch_beo<R, 0, false>(c->stream, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, partial, st);
+            } else {
+                if (dag) launch_beo<R, 1, true>(c->stream, e, nblk, dv, ndom, tmp, in, out, aux, partial, st);
+                else launch_beo<R, 0, true>(c->stream, e, nblk, dv, ndom, tmp, in, out, aux, partial, st);
+            }
+            if (c->timing) {
+                // per output half site: input, output (+ self, + aux) spinors; every link of a domain once
+                double sc = 0, s = 0;
+                for (const BEODom& d : host) {
+                    sc += (double)(d.g.nsite >> 1) * d.ncol;
+                    s += (double)(d.g.nsite >> 1);
+                }
+                const double extra = (half ? 24.0 : 0.0) + (e == EPI_DOT_AUX || e == EPI_RESID ? 24.0 : 0.0);
+                const double bytes = ((48.0 + extra) * sc + 144.0 * s) * sizeof(R);
+                const std::string name = std::string("k_beo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+                                         std::to_string(dag ? 1 : 0) + ", " + std::to_string(e) + ", " +
+                                         (half ? "true" : "false") + ">";
+                timing_end(c, ev, name, bytes);
+            }
+        }
+    }
+    void apply64(int dag, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux, double* partial,
+                 const ColState* st) override {
+        schur<double>(doms[0], tmp64, dag, epi, in, out, aux, partial, st);
+    }
+    void apply32(int dag, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux, double* partial,
+                 const ColState* st) override {
+        schur<float>(doms[1], tmp32, dag, epi, in, out, aux, partial, st);
+    }
+};
+
 // Pick the tile shape of one precision by timing the stencil on the batch
 // itself (out-of-place on two work vectors whose contents do not matter).
 // The choice is cached in the context per batch signature (precision and
@@ -287,6 +403,152 @@ class OwnStream {
     hipStream_t caller_;
 };
 
+// The even-odd batch: every domain bipartite.  b is in bcat (full layout,
+// offsets its[i].voff); the answer goes to xcat.
+dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solver_params& p, const cpx<double>* bcat,
+                         cpx<double>* xcat, SolveResult* res, std::vector<double>* rel) {
+    const int n = (int)its.size();
+    dd_status e = DD_OK;
+    std::vector<long long> hoff(n), eoff(n);
+    long long nhalf = 0, nl = 0;
+    for (int i = 0; i < n; i++) {
+        hoff[i] = nhalf;
+        eoff[i] = nl;
+        nhalf += (long long)its[i].ncol * 12 * (its[i].g.nsite >> 1);
+        nl += (long long)36 * its[i].g.nsite;
+    }
+    const bool mixed = p.prec == DD_MIXED;
+    cpx<double>* U64 = (cpx<double>*)workspace(c, W_EO_U64, (size_t)nl * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<float>* U32 = nullptr;
+    if (mixed) {
+        U32 = (cpx<float>*)workspace(c, W_U32, (size_t)nl * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+    }
+    cpx<double>* bb = (cpx<double>*)workspace(c, W_EO_B, 2 * (size_t)nhalf * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* xx = (cpx<double>*)workspace(c, W_EO_X, 2 * (size_t)nhalf * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* bhat = (cpx<double>*)workspace(c, W_EO_BHAT, (size_t)nhalf * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>*b_e = bb, *b_o = bb + nhalf, *x_e = xx, *x_o = xx + nhalf;
+    for (int i = 0; i < n; i++) {
+        const Item& it = its[i];
+        const double m = 1.0 / (2.0 * it.kappa);
+        launch_links_eo<double>(c, it.g, it.U64, U64 + eoff[i]);
+        if (mixed) launch_links_eo<float>(c, it.g, it.U64, U32 + eoff[i]);
+        launch_eo_split(c, it.g, it.ncol, bcat + it.voff, b_e + hoff[i], b_o + hoff[i]);
+        // b_e' = b_e + (1/(2m)) H_eo b_o
+        launch_eo_hop64(c, it.g, U64 + eoff[i], 1.0, 0.5 / m, 0, 0, b_o + hoff[i], b_e + hoff[i], bhat + hoff[i],
+                        it.ncol);
+    }
+    DD_HIP(c, hipGetLastError());
+
+    BatchEOSystem S;
+    S.c = c;
+    S.ndom = n;
+    S.nelem = (size_t)nhalf;
+    S.graph = true;
+    S.has32 = mixed;
+    S.tmp64 = (cpx<double>*)workspace(c, W_EO_T64, (size_t)nhalf * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    if (mixed) {
+        S.tmp32 = (cpx<float>*)workspace(c, W_EO_T32, (size_t)nhalf * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+    }
+    SegLayout lay;
+    std::vector<BEODom> d32;
+    int blk = 0, slot = 0, seg = 0;
+    for (int i = 0; i < n; i++) {
+        const Item& it = its[i];
+        BEODom d;
+        std::memset(&d, 0, sizeof(d));
+        d.g = it.g;
+        d.Ueo = U64 + eoff[i];
+        d.mass = 1.0 / (2.0 * it.kappa);
+        d.hoff = hoff[i];
+        d.ncol = it.ncol;
+        d.seg0 = seg;
+        d.blk0 = blk;
+        d.nblk = ((it.g.nsite >> 1) + kBeoNT - 1) / kBeoNT;
+        d.slot0 = slot;
+        S.host.push_back(d);
+        d.Ueo = mixed ? (const void*)(U32 + eoff[i]) : nullptr;
+        d32.push_back(d);
+        const int hlen = 12 * (it.g.nsite >> 1);
+        for (int j = 0; j < it.ncol; j++) {
+            lay.off.push_back(hoff[i] + (long long)j * hlen);
+            lay.len.push_back(hlen);
+            lay.sp0[0].push_back(slot + j * d.nblk);
+        }
+        blk += d.nblk * it.ncol;
+        slot += d.nblk * it.ncol;
+        seg += it.ncol;
+    }
+    lay.sp0[0].push_back(slot);
+    lay.sp0[1] = lay.sp0[0];
+    S.nblk = (unsigned)blk;
+    for (int kind = 0; kind < (mixed ? 2 : 1); kind++) {
+        const std::vector<BEODom>& h = kind == 0 ? S.host : d32;
+        BEODom* dev = (BEODom*)workspace(c, kind == 0 ? W_BATCH0 : W_BATCH4, sizeof(BEODom) * n, &e);
+        if (e != DD_OK) return e;
+        DD_HIP(c, hipMemcpyAsync(dev, h.data(), sizeof(BEODom) * n, hipMemcpyHostToDevice, c->stream));
+        S.doms[kind] = dev;
+    }
+    DD_HIP(c, hipStreamSynchronize(c->stream));  // the descriptors are pageable host memory
+    e = lay.upload(c, W_SEGS, &S);
+    if (e != DD_OK) return e;
+
+    // relative residuals refer to the original sources
+    std::vector<long long> foff;
+    std::vector<int> flen;
+    for (const Item& it : its)
+        for (int j = 0; j < it.ncol; j++) {
+            foff.push_back(it.voff + (long long)j * 12 * it.g.nsite);
+            flen.push_back(12 * it.g.nsite);
+        }
+    std::vector<double> bnorm;
+    e = segment_norms(c, foff, flen, bcat, &bnorm);
+    if (e != DD_OK) return e;
+    S.ref_norm2 = bnorm.data();
+
+    const dd_status st = solve_system(S, bhat, x_e, p, res);
+    if (st != DD_OK && st != DD_ERR_NOCONV && st != DD_ERR_BREAKDOWN) return st;
+
+    // odd sites, the full answer, and its true residual domain by domain
+    cpx<double>* r = bb;  // b_e | b_o are no longer needed (2 nhalf = the full size)
+    size_t pslots = 0;
+    for (const Item& it : its) pslots = std::max(pslots, (size_t)it.ncol * stencil_slots(c, it.g, 0, it.ncol));
+    double* partial = (double*)workspace(c, W_PART, std::max(pslots, S.nslots) * 3 * sizeof(double), &e);
+    if (e != DD_OK) return e;
+    for (int i = 0; i < n; i++) {
+        const Item& it = its[i];
+        const double m = 1.0 / (2.0 * it.kappa);
+        launch_eo_hop64(c, it.g, U64 + eoff[i], 1.0 / m, 0.5 / m, 1, 0, x_e + hoff[i], b_o + hoff[i], x_o + hoff[i],
+                        it.ncol);
+        launch_eo_merge(c, it.g, it.ncol, x_e + hoff[i], x_o + hoff[i], xcat + it.voff);
+    }
+    for (int i = 0; i < n; i++) {
+        const Item& it = its[i];
+        launch_dslash<double>(c, it.g, it.U64, it.kappa, 0, EPI_RESID, xcat + it.voff, r + it.voff, bcat + it.voff,
+                              it.ncol, partial, nullptr);
+    }
+    DD_HIP(c, hipGetLastError());
+    std::vector<double> rr;
+    e = segment_norms(c, foff, flen, r, &rr);
+    if (e != DD_OK) return e;
+    rel->assign(rr.size(), 0.0);
+    bool ok = true, nonfinite = st == DD_ERR_BREAKDOWN;
+    for (size_t k = 0; k < rr.size(); k++) {
+        if (!std::isfinite(rr[k])) nonfinite = true;
+        (*rel)[k] = bnorm[k] > 0 ? std::sqrt(rr[k] / bnorm[k]) : 0.0;
+        if (!((*rel)[k] <= p.tol)) ok = false;
+    }
+    if (nonfinite) return fail(c, DD_ERR_BREAKDOWN, "non-finite values in the Krylov iteration");
+    if (!ok) return fail(c, DD_ERR_NOCONV, "batched even-odd solve missed tol on some column");
+    return DD_OK;
+}
+
 }  // namespace
 
 }  // namespace dd
@@ -341,15 +603,49 @@ extern "C" dd_status dd_block_solve_batched(dd_ctx* c, int n, const dd_batch_ite
     e = own.enter();
     if (e != DD_OK) return e;
 
+    cpx<double>* bcat = (cpx<double>*)workspace(c, W_BATCH1, nelem * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* xcat = (cpx<double>*)workspace(c, W_BATCH2, nelem * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    for (int i = 0; i < n; i++)
+        DD_HIP(c, hipMemcpyAsync(bcat + its[i].voff, items[i].b, (size_t)its[i].ncol * 12 * its[i].g.nsite * 16,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    bool eo = p->precond == DD_PRECOND_EO;
+    for (const Item& it : its) eo = eo && eo_applicable(it.g);
+    if (eo) {
+        SolveResult res;
+        std::vector<double> rel;
+        const dd_status st = solve_batch_eo(c, its, *p, bcat, xcat, &res, &rel);
+        if (st != DD_OK && st != DD_ERR_NOCONV && st != DD_ERR_BREAKDOWN) return st;
+        for (int i = 0; i < n; i++)
+            DD_HIP(c, hipMemcpyAsync(items[i].x, xcat + its[i].voff, (size_t)its[i].ncol * 12 * its[i].g.nsite * 16,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        DD_HIP(c, hipStreamSynchronize(c->stream));
+        if (stats) {
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            int seg = 0;
+            for (int i = 0; i < n; i++) {
+                dd_solve_stats& s = stats[i];
+                std::memset(&s, 0, sizeof(s));
+                s.nrhs = its[i].ncol;
+                s.updates = res.updates;
+                s.restarts = res.restarts;
+                s.ms = ms;
+                for (int j = 0; j < its[i].ncol; j++, seg++) {
+                    s.iters = std::max(s.iters, seg < (int)res.seg_iters.size() ? res.seg_iters[seg] : 0);
+                    s.true_rel_resid[j] = seg < (int)rel.size() ? rel[seg] : 0.0;
+                }
+            }
+        }
+        return st;
+    }
+
     BatchSystem S;
     S.c = c;
     S.ndom = n;
     S.nelem = nelem;
     S.graph = true;
-    cpx<double>* bcat = (cpx<double>*)workspace(c, W_BATCH1, nelem * sizeof(cpx<double>), &e);
-    if (e != DD_OK) return e;
-    cpx<double>* xcat = (cpx<double>*)workspace(c, W_BATCH2, nelem * sizeof(cpx<double>), &e);
-    if (e != DD_OK) return e;
     cpx<float>* U32 = nullptr;
     if (p->prec == DD_MIXED) {
         U32 = (cpx<float>*)workspace(c, W_BATCH3, (size_t)uoff * sizeof(cpx<float>), &e);
@@ -357,9 +653,6 @@ extern "C" dd_status dd_block_solve_batched(dd_ctx* c, int n, const dd_batch_ite
         for (int i = 0; i < n; i++) launch_links_to_f32(c, (size_t)36 * its[i].g.vlink, its[i].U64, U32 + its[i].uoff);
         S.has32 = true;
     }
-    for (int i = 0; i < n; i++)
-        DD_HIP(c, hipMemcpyAsync(bcat + its[i].voff, items[i].b, (size_t)its[i].ncol * 12 * its[i].g.nsite * 16,
-                                 hipMemcpyDeviceToDevice, c->stream));
 
     // tile shapes, tuned on the batch (FP64 always: residuals; FP32 for mixed)
     {

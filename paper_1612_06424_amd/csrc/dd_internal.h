@@ -332,9 +332,22 @@ dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd
 // Even-odd preconditioned solve of one lattice or slab (evenodd.hip); usable
 // when the lattice is bipartite: L even, and nt even for a whole lattice.
 bool eo_applicable(const Geo& g);
+// checkerboard-ordered links of the field g (Ueo[mu][k][parity][nsite/2]) from U[mu][k][V]
+template <typename R>
+void launch_links_eo(dd_ctx* c, const Geo& g, const cpx<double>* U, cpx<R>* Ueo);
+// full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite/2]
+void launch_eo_split(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* full, cpx<double>* ev, cpx<double>* od);
+void launch_eo_merge(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* ev, const cpx<double>* od,
+                     cpx<double>* full);
+// out = a_self * self + c_hop * H_{p_out, 1 - p_out} in (FP64, no epilogue); self may be NULL
+void launch_eo_hop64(dd_ctx* c, const Geo& g, const cpx<double>* Ueo, double a_self, double c_hop, int p_out, int dag,
+                     const cpx<double>* in, const cpx<double>* self, cpx<double>* out, int ncol);
 dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
                    cpx<double>* x, const dd_solver_params& p, dd_solve_stats* stats, int dag);
 
+// |a_k|^2 of the segments [off[k], off[k] + len[k]) of a, into out; synchronises.
+dd_status segment_norms(dd_ctx* c, const std::vector<long long>& off, const std::vector<int>& len,
+                        const cpx<double>* a, std::vector<double>* out);
 // |a_j|^2 of the ncol columns of a (each n elements), into out; synchronises.
 dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::vector<double>* out);
 

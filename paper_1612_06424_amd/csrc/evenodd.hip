@@ -165,7 +165,34 @@ struct EOSystem : System {
 
 }  // namespace
 
-bool eo_applicable(const Geo& g) { return g.L % 2 == 0 && (!g.whole || g.nt % 2 == 0); }
+// A hop that wraps around the time edge of a whole lattice joins sites of the
+// same parity when nt is odd, unless time_bc = 0 drops it.
+bool eo_applicable(const Geo& g) { return g.L % 2 == 0 && (!g.whole || g.nt % 2 == 0 || g.bc == 0); }
+
+template <typename R>
+void launch_links_eo(dd_ctx* c, const Geo& g, const cpx<double>* U, cpx<R>* Ueo) {
+    hipLaunchKernelGGL(k_links_eo<R>, dim3((unsigned)((g.nsite + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, g,
+                       U, Ueo);
+}
+template void launch_links_eo<double>(dd_ctx*, const Geo&, const cpx<double>*, cpx<double>*);
+template void launch_links_eo<float>(dd_ctx*, const Geo&, const cpx<double>*, cpx<float>*);
+
+void launch_eo_split(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* full, cpx<double>* ev, cpx<double>* od) {
+    const size_t n = (size_t)ncol * 12 * g.nsite;
+    hipLaunchKernelGGL(k_eo_split, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, g, ncol,
+                       full, ev, od);
+}
+void launch_eo_merge(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* ev, const cpx<double>* od,
+                     cpx<double>* full) {
+    const size_t n = (size_t)ncol * 12 * g.nsite;
+    hipLaunchKernelGGL(k_eo_merge, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, g, ncol,
+                       ev, od, full);
+}
+void launch_eo_hop64(dd_ctx* c, const Geo& g, const cpx<double>* Ueo, double a_self, double c_hop, int p_out, int dag,
+                     const cpx<double>* in, const cpx<double>* self, cpx<double>* out, int ncol) {
+    launch_eo_hop<double>(c, g, Ueo, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol, nullptr,
+                          nullptr);
+}
 
 dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
                    cpx<double>* x, const dd_solver_params& p, dd_solve_stats* stats, int dag) {

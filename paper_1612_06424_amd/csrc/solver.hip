@@ -596,7 +596,8 @@ dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd
     return DD_OK;
 }
 
-dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::vector<double>* out) {
+dd_status segment_norms(dd_ctx* c, const std::vector<long long>& off, const std::vector<int>& len,
+                        const cpx<double>* a, std::vector<double>* out) {
     struct NoStencil : System {
         void apply64(int, int, const cpx<double>*, cpx<double>*, const cpx<double>*, double*,
                      const ColState*) override {}
@@ -604,27 +605,32 @@ dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::ve
                      const ColState*) override {}
     } S;
     S.c = c;
-    S.nelem = (size_t)n * ncol;
+    const int ns = (int)off.size();
     SegLayout lay;
-    for (int k = 0; k < ncol; k++) {
-        lay.off.push_back((long long)k * n);
-        lay.len.push_back(n);
-    }
-    lay.sp0[0].assign(ncol + 1, 0);
-    lay.sp0[1].assign(ncol + 1, 0);
+    lay.off = off;
+    lay.len = len;
+    lay.sp0[0].assign(ns + 1, 0);
+    lay.sp0[1].assign(ns + 1, 0);
     dd_status e = lay.upload(c, W_SEGN, &S);  // own slot: a System's tables may be live in W_SEGS
     if (e != DD_OK) return e;
-    e = ensure_host(c, ncol);
+    e = ensure_host(c, ns);
     if (e != DD_OK) return e;
     double* partial = (double*)workspace(c, W_PART, S.nslots * 3 * sizeof(double), &e);
     if (e != DD_OK) return e;
-    double* dots = (double*)workspace(c, W_DOTS, sizeof(double) * 3 * ncol, &e);
+    double* dots = (double*)workspace(c, W_DOTS, sizeof(double) * 3 * ns, &e);
     if (e != DD_OK) return e;
     e = norms_to_host<double>(S, a, partial, dots);
     if (e != DD_OK) return e;
-    out->resize(ncol);
-    for (int k = 0; k < ncol; k++) (*out)[k] = c->host_dots[3 * k];
+    out->resize(ns);
+    for (int k = 0; k < ns; k++) (*out)[k] = c->host_dots[3 * k];
     return DD_OK;
+}
+
+dd_status column_norms(dd_ctx* c, int n, int ncol, const cpx<double>* a, std::vector<double>* out) {
+    std::vector<long long> off(ncol);
+    std::vector<int> len(ncol, n);
+    for (int k = 0; k < ncol; k++) off[k] = (long long)k * n;
+    return segment_norms(c, off, len, a, out);
 }
 
 // Solve M x = b on one lattice or slab for ncol columns (M = D, or D^+ for dag).

@@ -4,7 +4,7 @@
 
 DIR holds one rocprofv3 output directory per pass (csv format):
   trace/       --kernel-trace --stats of the bench
-  fetch/       --pmc FETCH_SIZE  (stencil kernels)
+  fetch/       --pmc FETCH_SIZE  (stencil kernels: dslash and half-hop instances)
   write/       --pmc WRITE_SIZE  (stencil kernels)
   copy_fetch/  --pmc FETCH_SIZE  of bench.py --copy-calibration
   copy_write/  --pmc WRITE_SIZE  of bench.py --copy-calibration
@@ -27,8 +27,8 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 # the sources that decide what the stencil kernels do and how they are launched
-STENCIL_SOURCES = ["csrc/dd_dslash.h", "csrc/dd_wilson.h", "csrc/dirac.hip", "csrc/batched.hip", "csrc/tune.hip",
-                   "tune_cache_mi355x.txt"]
+STENCIL_SOURCES = ["csrc/dd_dslash.h", "csrc/dd_eo.h", "csrc/dd_wilson.h", "csrc/dd_internal.h", "csrc/dirac.hip",
+                   "csrc/evenodd.hip", "csrc/batched.hip", "csrc/tune.hip", "tune_cache_mi355x.txt"]
 
 
 def kernel_source_hash() -> str:

@@ -26,11 +26,20 @@ SMALL_BATCH = [
     (10, 5, 0, 0.132, 5, 0.25),
     (8, 6, 1, 0.12, 2, 0.3),
 ]
+# every domain bipartite (even L; even T or Dirichlet time walls): the batch takes
+# the even-odd path unless the parameters ask for the full operator
+EO_BATCH = [
+    (8, 4, 0, 0.125, 3, 0.3),
+    (4, 6, 0, 0.13, 12, 0.3),
+    (6, 4, -1, 0.128, 1, 0.3),
+    (9, 4, 0, 0.132, 5, 0.25),
+    (8, 6, 1, 0.12, 2, 0.3),
+]
 
 
-def _items(dd, seed):
+def _items(dd, seed, batch=SMALL_BATCH):
     items, refs = [], []
-    for i, (T, L, bc, kappa, ncol, eps) in enumerate(SMALL_BATCH):
+    for i, (T, L, bc, kappa, ncol, eps) in enumerate(batch):
         U = random_links(T, L, eps, seed + i)
         b = gaussian_field(T * L ** 3, ncol, seed + 100 + i)
         items.append(dict(T=T, L=L, time_bc=bc, U=dd.pack_links(U), kappa=kappa, b=dd.pack_field(b),
@@ -39,16 +48,18 @@ def _items(dd, seed):
     return items, refs
 
 
+@pytest.mark.parametrize("batch,precond", [("uneven", 0), ("bipartite", 0), ("bipartite", 1)])
 @pytest.mark.parametrize("prec,solver", [("fp64", 1), ("mixed", 1), ("fp64", 0), ("mixed", 0)])
-def test_batched_vs_oracle(prec, solver):
+def test_batched_vs_oracle(prec, solver, batch, precond):
     dd = lib()
-    step(f"batched small {prec} solver={solver}")
-    items, refs = _items(dd, 3000)
+    step(f"batched {batch} precond={precond} {prec} solver={solver}")
+    shapes = SMALL_BATCH if batch == "uneven" else EO_BATCH
+    items, refs = _items(dd, 3000, shapes)
     ctx = dd.Context(8, 4, 0)
     p = dd.solver_params(tol=1e-12 if prec == "fp64" else 1e-10, max_iter=20000,
-                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, solver=solver)
+                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, solver=solver, precond=precond)
     stats = dd.block_solve_batched(ctx, items, p)
-    for it, (U, b), st, (T, L, bc, kappa, ncol, _) in zip(items, refs, stats, SMALL_BATCH):
+    for it, (U, b), st, (T, L, bc, kappa, ncol, _) in zip(items, refs, stats, shapes):
         assert st["nrhs"] == ncol
         assert max(st["true_rel_resid"][:ncol]) <= p.tol
         ref, _, _, ost = O.solve(U, kappa, T, L, bc, b, tol=1e-13, method=1)
@@ -58,12 +69,14 @@ def test_batched_vs_oracle(prec, solver):
         assert relerr(O.apply_dirac(U, kappa, T, L, bc, got), b) <= 2 * p.tol
 
 
-def test_batched_repeatable_and_matches_single():
+@pytest.mark.parametrize("batch", ["uneven", "bipartite"])
+def test_batched_repeatable_and_matches_single(batch):
     """Two batched solves give bitwise the same answer (graph replays are
     deterministic), and each domain agrees with its own single-domain solve."""
     dd = lib()
-    step("batched repeat + single")
-    items, refs = _items(dd, 3100)
+    step(f"batched repeat + single ({batch})")
+    shapes = SMALL_BATCH if batch == "uneven" else EO_BATCH
+    items, refs = _items(dd, 3100, shapes)
     ctx = dd.Context(8, 4, 0)
     p = dd.solver_params(tol=1e-12, prec=dd.DD_MIXED)
     dd.block_solve_batched(ctx, items, p)
@@ -71,7 +84,7 @@ def test_batched_repeatable_and_matches_single():
     dd.block_solve_batched(ctx, items, p)
     for a, it in zip(first, items):
         assert torch.equal(a, it["x"])
-    for it, (T, L, bc, kappa, ncol, _) in zip(items, SMALL_BATCH):
+    for it, (T, L, bc, kappa, ncol, _) in zip(items, shapes):
         sctx = dd.Context(T, L, bc)
         x, _ = dd.block_solve(sctx, it["U"], kappa, it["b"], None, p)
         assert relerr(dd.unpack_field(x), dd.unpack_field(it["x"])) < 1e-9
