@@ -131,7 +131,7 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, doub
         const double bytes = nh * ((48.0 + extra) * ncol + 144.0) * sizeof(R);
         const std::string name = std::string("k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
-                                 std::to_string(kEoNT) + ">";
+                                 std::to_string(kEoNT) + (sf ? ", true>" : ", false>");
         timing_end(c, ev, name, bytes);
     }
 }
