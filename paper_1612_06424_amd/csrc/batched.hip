@@ -74,8 +74,10 @@ struct BEODom {
     double mass;       // 1 / (2 kappa)
     long long hoff;    // element offset of its column 0 in the half-field work vectors
     int ncol, seg0, blk0;
-    int nblk;          // workgroups per column
+    int nblk;          // workgroups per column: ntile x chunks
     int slot0;         // its first partial slot
+    int ntile;         // tiles of kBeoNT pairs per slice
+    int tc;            // slices per chunk
     int pad;
 };
 static_assert(sizeof(BEODom) % 8 == 0, "descriptor layout must be the same on host and device");
@@ -97,16 +99,16 @@ __global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ d
     }
     const BEODom& d = doms[lo];
     const int lb = bid - d.blk0;
-    const int col = lb % d.ncol, hb = lb / d.ncol;
+    const int col = lb % d.ncol, blk = lb / d.ncol;
     if (st != nullptr && !st[d.seg0 + col].active) return;  // uniform over the workgroup
     const Geo g = d.g;
     const size_t off = (size_t)d.hoff + (size_t)col * 12 * (size_t)(g.nsite >> 1);
     const R a_self = SCHUR ? R(d.mass) : R(0);
     const R c_hop = SCHUR ? R(-0.25 / d.mass) : R(1);
-    eo_hop_site<R, DAG, EPI, kBeoNT, SCHUR>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1,
-                                            hb * kBeoNT + (int)threadIdx.x, in + off, self != nullptr ? self + off : nullptr,
-                                            out + off, aux != nullptr ? aux + off : nullptr,
-                                            partial + ((size_t)d.slot0 + (size_t)col * d.nblk + hb) * 3);
+    eo_sweep_tile<R, DAG, EPI, kBeoNT, SCHUR>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1, in + off,
+                                              self != nullptr ? self + off : nullptr, out + off,
+                                              aux != nullptr ? aux + off : nullptr, blk % d.ntile, blk / d.ntile, d.tc,
+                                              partial + ((size_t)d.slot0 + (size_t)col * d.nblk + blk) * 3);
 }
 
 template <typename R, int DAG, bool SCHUR>
@@ -263,13 +265,15 @@ struct BatchEOSystem : System {
     const BEODom* doms[2] = {nullptr, nullptr};  // kind 0: FP64 links, 1: FP32 links
     std::vector<BEODom> host;                    // FP64 descriptors (sizes, for timing)
     int ndom = 0;
-    unsigned nblk = 0;
+    unsigned nblk = 0;                 // workgroups of a launch while tuning
+    unsigned nblk64 = 0, nblk32 = 0;   // workgroups of a launch per precision
     cpx<double>* tmp64 = nullptr;
     cpx<float>* tmp32 = nullptr;
 
     template <typename R>
     void schur(const BEODom* dv, cpx<R>* tmp, int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux,
                double* partial, const ColState* st) {
+        const unsigned nblk = this->nblk != 0 ? this->nblk : (sizeof(R) == 8 ? nblk64 : nblk32);
         for (int half = 0; half < 2; half++) {
             const int e = half ? epi : EPI_STORE;
             hipEvent_t ev = nullptr;
@@ -456,46 +460,117 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
         S.tmp32 = (cpx<float>*)workspace(c, W_EO_T32, (size_t)nhalf * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
     }
+    // descriptors for a chunk length tc of the half-hop sweep, precision kind
+    auto build = [&](int tc, int kind, std::vector<BEODom>* h, std::vector<int>* sp0) {
+        h->clear();
+        sp0->clear();
+        int blk = 0, slot = 0, seg = 0;
+        for (int i = 0; i < n; i++) {
+            const Item& it = its[i];
+            BEODom d;
+            std::memset(&d, 0, sizeof(d));
+            d.g = it.g;
+            d.Ueo = kind == 0 ? (const void*)(U64 + eoff[i]) : (const void*)(U32 + eoff[i]);
+            d.mass = 1.0 / (2.0 * it.kappa);
+            d.hoff = hoff[i];
+            d.ncol = it.ncol;
+            d.seg0 = seg;
+            d.blk0 = blk;
+            d.ntile = ((it.g.L3 >> 1) + kBeoNT - 1) / kBeoNT;
+            d.tc = std::min(tc, it.g.nt);
+            d.nblk = d.ntile * ((it.g.nt + d.tc - 1) / d.tc);
+            d.slot0 = slot;
+            h->push_back(d);
+            for (int j = 0; j < it.ncol; j++) sp0->push_back(slot + j * d.nblk);
+            blk += d.nblk * it.ncol;
+            slot += d.nblk * it.ncol;
+            seg += it.ncol;
+        }
+        sp0->push_back(slot);
+        return blk;
+    };
+    auto upload = [&](int kind, const std::vector<BEODom>& h) -> dd_status {
+        dd_status ee = DD_OK;
+        BEODom* dev = (BEODom*)workspace(c, kind == 0 ? W_BATCH0 : W_BATCH4, sizeof(BEODom) * n, &ee);
+        if (ee != DD_OK) return ee;
+        DD_HIP(c, hipMemcpyAsync(dev, h.data(), sizeof(BEODom) * n, hipMemcpyHostToDevice, c->stream));
+        DD_HIP(c, hipStreamSynchronize(c->stream));  // h is pageable host memory
+        S.doms[kind] = dev;
+        return DD_OK;
+    };
+    // chunk length per precision: timed on the batch's Schur operator at first use (cached
+    // per batch signature), on work vectors whose contents do not matter
+    std::string sig;
+    for (const Item& it : its)
+        sig += ":" + std::to_string(it.g.T) + "x" + std::to_string(it.g.L) + "x" + std::to_string(it.ncol) + "b" +
+               std::to_string(it.g.bc);
     SegLayout lay;
-    std::vector<BEODom> d32;
-    int blk = 0, slot = 0, seg = 0;
-    for (int i = 0; i < n; i++) {
-        const Item& it = its[i];
-        BEODom d;
-        std::memset(&d, 0, sizeof(d));
-        d.g = it.g;
-        d.Ueo = U64 + eoff[i];
-        d.mass = 1.0 / (2.0 * it.kappa);
-        d.hoff = hoff[i];
-        d.ncol = it.ncol;
-        d.seg0 = seg;
-        d.blk0 = blk;
-        d.nblk = ((it.g.nsite >> 1) + kBeoNT - 1) / kBeoNT;
-        d.slot0 = slot;
-        S.host.push_back(d);
-        d.Ueo = mixed ? (const void*)(U32 + eoff[i]) : nullptr;
-        d32.push_back(d);
+    std::vector<BEODom> hk;
+    for (int kind = 0; kind < (mixed ? 2 : 1); kind++) {
+        const std::string key = "beo:" + std::to_string(kind) + sig;
+        int tc = 4;
+        const auto hit = c->sched.find(key);
+        if (hit != c->sched.end()) {
+            tc = hit->second.tc;
+        } else {
+            hipEvent_t ea, eb;
+            DD_HIP(c, hipEventCreate(&ea));
+            DD_HIP(c, hipEventCreate(&eb));
+            const int saved = c->timing;
+            c->timing = 0;
+            float best = 1e30f;
+            std::vector<int> sp;
+            for (int t : {1, 2, 4, 8}) {
+                S.nblk = (unsigned)build(t, kind, &hk, &sp);
+                S.host = hk;
+                e = upload(kind, hk);
+                if (e != DD_OK) break;
+                auto run = [&]() {
+                    if (kind == 0) S.schur<double>(S.doms[0], S.tmp64, 0, EPI_STORE, bhat, x_e, nullptr, nullptr, nullptr);
+                    else S.schur<float>(S.doms[1], S.tmp32, 0, EPI_STORE, (const cpx<float>*)x_o, (cpx<float>*)x_e,
+                                        nullptr, nullptr, nullptr);
+                };
+                run();
+                run();
+                (void)hipEventRecord(ea, c->stream);
+                for (int r = 0; r < 3; r++) run();
+                (void)hipEventRecord(eb, c->stream);
+                (void)hipEventSynchronize(eb);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, ea, eb);
+                if (ms < best) {
+                    best = ms;
+                    tc = t;
+                }
+            }
+            c->timing = saved;
+            S.nblk = 0;  // launches size themselves from nblk64 / nblk32 again
+            (void)hipEventDestroy(ea);
+            (void)hipEventDestroy(eb);
+            if (e != DD_OK) return e;
+            StencilSched keep;
+            keep.nt = kBeoNT;
+            keep.tc = tc;
+            tune_cache_store(c, key, keep);
+        }
+        const unsigned nb = (unsigned)build(tc, kind, &hk, &lay.sp0[kind]);
+        if (kind == 0) {
+            S.nblk64 = nb;
+            S.host = hk;
+        } else {
+            S.nblk32 = nb;
+        }
+        e = upload(kind, hk);
+        if (e != DD_OK) return e;
+    }
+    if (!mixed) lay.sp0[1] = lay.sp0[0];
+    for (const Item& it : its) {
         const int hlen = 12 * (it.g.nsite >> 1);
         for (int j = 0; j < it.ncol; j++) {
-            lay.off.push_back(hoff[i] + (long long)j * hlen);
+            lay.off.push_back(hoff[&it - &its[0]] + (long long)j * hlen);
             lay.len.push_back(hlen);
-            lay.sp0[0].push_back(slot + j * d.nblk);
         }
-        blk += d.nblk * it.ncol;
-        slot += d.nblk * it.ncol;
-        seg += it.ncol;
     }
-    lay.sp0[0].push_back(slot);
-    lay.sp0[1] = lay.sp0[0];
-    S.nblk = (unsigned)blk;
-    for (int kind = 0; kind < (mixed ? 2 : 1); kind++) {
-        const std::vector<BEODom>& h = kind == 0 ? S.host : d32;
-        BEODom* dev = (BEODom*)workspace(c, kind == 0 ? W_BATCH0 : W_BATCH4, sizeof(BEODom) * n, &e);
-        if (e != DD_OK) return e;
-        DD_HIP(c, hipMemcpyAsync(dev, h.data(), sizeof(BEODom) * n, hipMemcpyHostToDevice, c->stream));
-        S.doms[kind] = dev;
-    }
-    DD_HIP(c, hipStreamSynchronize(c->stream));  // the descriptors are pageable host memory
     e = lay.upload(c, W_SEGS, &S);
     if (e != DD_OK) return e;
 

@@ -19,22 +19,24 @@ namespace dd {
 
 namespace {
 
-// Workgroup -> (column fastest, block of NT half sites); partial slot of
-// (col, block) = col * nblk + block.
+// Workgroup -> (column fastest, tile of NT pairs of a slice, chunk of tc_len
+// slices); partial slot of (col, block) = col * nblk + block.
 template <typename R, int DAG, int EPI, int NT, bool SELF>
-__global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self, R c_hop, int p_out,
-                                               const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
-                                               cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux, int ncol,
-                                               double* __restrict__ partial, const ColState* __restrict__ st) {
+__global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self,
+                                                             R c_hop, int p_out, const cpx<R>* __restrict__ in,
+                                                             const cpx<R>* __restrict__ self,
+                                                             cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
+                                                             int ncol, int tc_len, double* __restrict__ partial,
+                                                             const ColState* __restrict__ st) {
     const int lb = (int)blockIdx.x;
-    const int col = lb % ncol, hb = lb / ncol;
+    const int col = lb % ncol, blk = lb / ncol;
     if (st != nullptr && !st[col].active) return;  // uniform over the workgroup
     const int nblk = (int)gridDim.x / ncol;
+    const int ntile = ((g.L3 >> 1) + NT - 1) / NT;
     const size_t off = (size_t)col * 12 * (size_t)(g.nsite >> 1);
-    const int h = hb * NT + (int)threadIdx.x;
-    eo_hop_site<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, h, in + off, self != nullptr ? self + off : nullptr,
-                                 out + off, aux != nullptr ? aux + off : nullptr,
-                                 partial + ((size_t)col * nblk + hb) * 3);
+    eo_sweep_tile<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, in + off, self != nullptr ? self + off : nullptr,
+                                         out + off, aux != nullptr ? aux + off : nullptr, blk % ntile, blk / ntile,
+                                         tc_len, partial + ((size_t)col * nblk + blk) * 3);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -83,16 +85,17 @@ __global__ __launch_bounds__(kBlock) void k_links_eo(Geo g, const cpx<double>* _
 
 constexpr int kEoNT = 256;
 
-int eo_blocks(const Geo& g) { return ((g.nsite >> 1) + kEoNT - 1) / kEoNT; }
+// workgroups per column: tiles of kEoNT pairs per slice x chunks of tc slices
+int eo_blocks(const Geo& g, int tc) { return (((g.L3 >> 1) + kEoNT - 1) / kEoNT) * ((g.nt + tc - 1) / tc); }
 
 template <typename R, int DAG, bool SELF>
 void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
-                   const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, double* partial,
-                   const ColState* st) {
+                   const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
+                   double* partial, const ColState* st) {
     const dim3 block(kEoNT);
 #define DD_EO_CASE(E)                                                                                              \
-    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, self, out, \
-                       aux, ncol, partial, st)
+    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, self, \
+                       out, aux, ncol, tc, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_EO_CASE(EPI_DOT_AUX); break;
@@ -103,16 +106,18 @@ void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>
 #undef DD_EO_CASE
 }
 
-// out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns
+// out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
+// time chunks of tc slices
 template <typename R>
 void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, double c_hop, int p_out, int dag,
-                   int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol,
+                   int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
                    double* partial, const ColState* st) {
-    const dim3 grid((unsigned)(eo_blocks(g) * ncol));
+    const dim3 grid((unsigned)(eo_blocks(g, tc) * ncol));
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_EO_LAUNCH(D, SF) \
-    launch_eo_epi<R, D, SF>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, partial, st)
+    launch_eo_epi<R, D, SF>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, tc, \
+                            partial, st)
     const bool sf = self != nullptr && a_self != 0;
     if (dag) {
         if (sf) DD_EO_LAUNCH(1, true);
@@ -147,21 +152,67 @@ struct EOSystem : System {
     int ncol = 0;
     cpx<double>* tmp64 = nullptr;
     cpx<float>* tmp32 = nullptr;
+    int tc[2] = {8, 8};  // chunk length of the half-hop sweep per kind (0: FP64, 1: FP32)
     template <typename R>
-    void schur(const cpx<R>* UR, cpx<R>* tmp, int d, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux,
-               double* partial, const ColState* st) {
-        launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, partial, st);
-        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, partial, st);
+    void schur(const cpx<R>* UR, cpx<R>* tmp, int t, int d, int epi, const cpx<R>* in, cpx<R>* out,
+               const cpx<R>* aux, double* partial, const ColState* st) {
+        launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, t, partial, st);
+        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, t, partial, st);
     }
     void apply64(int d, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux, double* partial,
                  const ColState* st) override {
-        schur<double>(U64, tmp64, d ^ dag, epi, in, out, aux, partial, st);
+        schur<double>(U64, tmp64, tc[0], d ^ dag, epi, in, out, aux, partial, st);
     }
     void apply32(int d, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux, double* partial,
                  const ColState* st) override {
-        schur<float>(U32, tmp32, d ^ dag, epi, in, out, aux, partial, st);
+        schur<float>(U32, tmp32, tc[1], d ^ dag, epi, in, out, aux, partial, st);
     }
 };
+
+// Chunk length of the half-hop sweep for one precision: timed on the Schur
+// operator of this geometry and column count at first use (candidates 1, 2,
+// 4, 8 slices), cached in the context like the stencil shapes; small fields
+// take 4 untimed.
+template <typename R>
+int eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, const cpx<R>* in, cpx<R>* out) {
+    const Geo& g = S.g;
+    const std::string key = std::string("eo:") + (sizeof(R) == 8 ? "0" : "1") + ":" + std::to_string(S.ncol) + ":" +
+                            std::to_string(g.L) + ":" + std::to_string(g.T) + ":" + std::to_string(g.nt) + ":" +
+                            std::to_string(g.whole);
+    const auto hit = c->sched.find(key);
+    if (hit != c->sched.end()) return hit->second.tc;
+    StencilSched best;
+    best.nt = kEoNT;
+    best.tc = std::min(4, g.nt);
+    if ((size_t)g.nsite * S.ncol >= ((size_t)1 << 18)) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+            const int saved = c->timing;
+            c->timing = 0;
+            float best_ms = 1e30f;
+            for (int t : {1, 2, 4, 8}) {
+                if (t > g.nt) continue;
+                for (int w = 0; w < 2; w++) S.schur<R>(UR, tmp, t, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                (void)hipEventRecord(a, c->stream);
+                for (int r = 0; r < 3; r++) S.schur<R>(UR, tmp, t, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                (void)hipEventRecord(b, c->stream);
+                (void)hipEventSynchronize(b);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.tc = t;
+                }
+            }
+            c->timing = saved;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+        (void)hipGetLastError();
+    }
+    tune_cache_store(c, key, best);
+    return best.tc;
+}
 
 }  // namespace
 
@@ -190,8 +241,8 @@ void launch_eo_merge(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* ev, c
 }
 void launch_eo_hop64(dd_ctx* c, const Geo& g, const cpx<double>* Ueo, double a_self, double c_hop, int p_out, int dag,
                      const cpx<double>* in, const cpx<double>* self, cpx<double>* out, int ncol) {
-    launch_eo_hop<double>(c, g, Ueo, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol, nullptr,
-                          nullptr);
+    launch_eo_hop<double>(c, g, Ueo, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol,
+                          std::min(4, g.nt), nullptr, nullptr);
 }
 
 dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
@@ -234,21 +285,30 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
         if (e != DD_OK) return e;
         S.has32 = true;
     }
+    // chunk lengths (tuned on two half-field work vectors whose contents do not matter)
+    S.tc[0] = eo_tune<double>(c, S, Ueo64, S.tmp64, bhat, xx);
+    if (S.has32) {
+        cpx<float>* a32 = (cpx<float>*)workspace(c, W_R32, nhalf * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+        cpx<float>* b32 = (cpx<float>*)workspace(c, W_RH32, nhalf * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+        S.tc[1] = eo_tune<float>(c, S, S.U32, S.tmp32, a32, b32);
+    }
     SegLayout lay;
     const int n = (int)(12 * nh);
-    const int nblk = eo_blocks(g);
     for (int k = 0; k < ncol; k++) {
         lay.off.push_back((long long)k * n);
         lay.len.push_back(n);
     }
     for (int kind = 0; kind < 2; kind++) {
+        const int nblk = eo_blocks(g, S.tc[kind]);
         lay.sp0[kind].resize(ncol + 1);
         for (int k = 0; k <= ncol; k++) lay.sp0[kind][k] = k * nblk;
     }
     e = lay.upload(c, W_SEGS, &S);
     if (e != DD_OK) return e;
-    // the partial slots of the source preparation and reconstruction use the same layout
-    S.nslots = std::max(S.nslots, (size_t)ncol * nblk);
+    // the partial slots of the source preparation and reconstruction (chunks of min(4, nt))
+    S.nslots = std::max(S.nslots, (size_t)ncol * eo_blocks(g, std::min(4, g.nt)));
 
     // |b|^2 per column: the reference of every relative residual
     std::vector<double> bnorm;
@@ -264,16 +324,14 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
     double* partial = (double*)workspace(c, W_PART, S.nslots * 3 * sizeof(double), &e);
     if (e != DD_OK) return e;
     // b_e' = b_e + (1/(2m)) H_eo b_o
-    launch_eo_hop<double>(c, g, Ueo64, 1.0, 0.5 / m, 0, dag, EPI_STORE, b_o, b_e, bhat, nullptr, ncol, partial,
-                          nullptr);
+    launch_eo_hop64(c, g, Ueo64, 1.0, 0.5 / m, 0, dag, b_o, b_e, bhat, ncol);
 
     SolveResult res;
     dd_status st = solve_system(S, bhat, x_e, p, &res);
     if (st != DD_OK && st != DD_ERR_NOCONV && st != DD_ERR_BREAKDOWN) return st;
 
     // x_o = (b_o + 1/2 H_oe x_e) / m, then the full answer and its true residual
-    launch_eo_hop<double>(c, g, Ueo64, 1.0 / m, 0.5 / m, 1, dag, EPI_STORE, x_e, b_o, x_o, nullptr, ncol, partial,
-                          nullptr);
+    launch_eo_hop64(c, g, Ueo64, 1.0 / m, 0.5 / m, 1, dag, x_e, b_o, x_o, ncol);
     hipLaunchKernelGGL(k_eo_merge, dim3(gsplit), dim3(kBlock), 0, c->stream, g, ncol, x_e, x_o, x);
     cpx<double>* r = bb;  // b_e | b_o are no longer needed
     const size_t rslots = std::max(S.nslots, (size_t)ncol * stencil_slots(c, g, 0, ncol));
