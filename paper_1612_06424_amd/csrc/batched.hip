@@ -74,7 +74,7 @@ struct BEODom {
     double mass;       // 1 / (2 kappa)
     long long hoff;    // element offset of its column 0 in the half-field work vectors
     int ncol, seg0, blk0;
-    int nblk;          // workgroups per column: ntile x chunks
+    int nblk;          // workgroups per column (group): ntile x chunks
     int slot0;         // its first partial slot
     int ntile;         // tiles of kBeoNT pairs per slice
     int tc;            // slices per chunk
@@ -84,13 +84,15 @@ static_assert(sizeof(BEODom) % 8 == 0, "descriptor layout must be the same on ho
 
 constexpr int kBeoNT = 256;
 
-// SCHUR = false: out = H_oe in (odd sites); SCHUR = true: out = m self - H_eo in / (4m) (even sites)
-template <typename R, int DAG, int EPI, bool SCHUR>
+// SCHUR = false: out = H_oe in (odd sites); SCHUR = true: out = m self - H_eo in / (4m) (even sites).
+// A workgroup serves KC columns of its domain (every domain's ncol is a multiple of KC).
+template <typename R, int DAG, int EPI, bool SCHUR, int KC>
 __global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ doms, int ndom,
                                                    const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
                                                    cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
-                                                   double* __restrict__ partial, const ColState* __restrict__ st) {
-    const int bid = (int)blockIdx.x;
+                                                   int remap, double* __restrict__ partial,
+                                                   const ColState* __restrict__ st) {
+    const int bid = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     int lo = 0, hi = ndom - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -99,24 +101,38 @@ __global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ d
     }
     const BEODom& d = doms[lo];
     const int lb = bid - d.blk0;
-    const int col = lb % d.ncol, blk = lb / d.ncol;
-    if (st != nullptr && !st[d.seg0 + col].active) return;  // uniform over the workgroup
+    const int ngrp = d.ncol / KC;
+    const int col0 = (lb % ngrp) * KC, blk = lb / ngrp;
+    unsigned live = 0;  // active columns of the group; the workgroup runs while one is
+#pragma unroll
+    for (int k = 0; k < KC; k++)
+        if (st == nullptr || st[d.seg0 + col0 + k].active) live |= 1u << k;
+    if (live == 0) return;  // uniform over the workgroup
     const Geo g = d.g;
-    const size_t off = (size_t)d.hoff + (size_t)col * 12 * (size_t)(g.nsite >> 1);
+    const size_t off = (size_t)d.hoff + (size_t)col0 * 12 * (size_t)(g.nsite >> 1);
     const R a_self = SCHUR ? R(d.mass) : R(0);
     const R c_hop = SCHUR ? R(-0.25 / d.mass) : R(1);
-    eo_sweep_tile<R, DAG, EPI, kBeoNT, SCHUR>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1, in + off,
-                                              self != nullptr ? self + off : nullptr, out + off,
-                                              aux != nullptr ? aux + off : nullptr, blk % d.ntile, blk / d.ntile, d.tc,
-                                              partial + ((size_t)d.slot0 + (size_t)col * d.nblk + blk) * 3);
+    double* slot = partial + ((size_t)d.slot0 + (size_t)col0 * d.nblk + blk) * 3;
+    if constexpr (KC == 1)
+        eo_sweep_tile<R, DAG, EPI, kBeoNT, SCHUR>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1, in + off,
+                                                  self != nullptr ? self + off : nullptr, out + off,
+                                                  aux != nullptr ? aux + off : nullptr, blk % d.ntile, blk / d.ntile,
+                                                  d.tc, slot);
+    else
+        eo_sweep_cols<R, DAG, EPI, kBeoNT, SCHUR, KC>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1,
+                                                      in + off, self != nullptr ? self + off : nullptr, out + off,
+                                                      aux != nullptr ? aux + off : nullptr, live, blk % d.ntile,
+                                                      blk / d.ntile, d.tc, slot, (size_t)d.nblk);
 }
 
-template <typename R, int DAG, bool SCHUR>
-void launch_beo(hipStream_t s, int epi, unsigned nblk, const BEODom* doms, int ndom, const cpx<R>* in,
-                const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, double* partial, const ColState* st) {
+template <typename R, int DAG, bool SCHUR, int KC>
+void launch_beo_epi(hipStream_t s, int epi, unsigned nblk, const BEODom* doms, int ndom, const cpx<R>* in,
+                    const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int remap, double* partial,
+                    const ColState* st) {
     const dim3 grid(nblk), block(kBeoNT);
-#define DD_BEO_CASE(E) \
-    hipLaunchKernelGGL((k_beo_hop<R, DAG, E, SCHUR>), grid, block, 0, s, doms, ndom, in, self, out, aux, partial, st)
+#define DD_BEO_CASE(E)                                                                                             \
+    hipLaunchKernelGGL((k_beo_hop<R, DAG, E, SCHUR, KC>), grid, block, 0, s, doms, ndom, in, self, out, aux, remap, \
+                       partial, st)
     switch (epi) {
         case EPI_STORE: DD_BEO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_BEO_CASE(EPI_DOT_AUX); break;
@@ -125,6 +141,23 @@ void launch_beo(hipStream_t s, int epi, unsigned nblk, const BEODom* doms, int n
         default: DD_BEO_CASE(EPI_NORM); break;
     }
 #undef DD_BEO_CASE
+}
+
+// kc columns per workgroup: 1 in FP64, 1, 2 or 4 in FP32 (as for the single-system half hop)
+template <typename R, int DAG, bool SCHUR>
+void launch_beo(hipStream_t s, int kc, int epi, unsigned nblk, const BEODom* doms, int ndom, const cpx<R>* in,
+                const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int remap, double* partial, const ColState* st) {
+    if constexpr (sizeof(R) == 4) {
+        if (kc == 4) {
+            launch_beo_epi<R, DAG, SCHUR, 4>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st);
+            return;
+        }
+        if (kc == 2) {
+            launch_beo_epi<R, DAG, SCHUR, 2>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st);
+            return;
+        }
+    }
+    launch_beo_epi<R, DAG, SCHUR, 1>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st);
 }
 
 template <typename R, int DAG, int NT>
@@ -267,6 +300,8 @@ struct BatchEOSystem : System {
     int ndom = 0;
     unsigned nblk = 0;                 // workgroups of a launch while tuning
     unsigned nblk64 = 0, nblk32 = 0;   // workgroups of a launch per precision
+    int remap[2] = {0, 0};             // XCD-contiguous workgroup ranges per precision
+    int kc[2] = {1, 1};                // columns per workgroup per precision
     cpx<double>* tmp64 = nullptr;
     cpx<float>* tmp32 = nullptr;
 
@@ -274,16 +309,20 @@ struct BatchEOSystem : System {
     void schur(const BEODom* dv, cpx<R>* tmp, int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux,
                double* partial, const ColState* st) {
         const unsigned nblk = this->nblk != 0 ? this->nblk : (sizeof(R) == 8 ? nblk64 : nblk32);
+        const int rm = remap[sizeof(R) == 8 ? 0 : 1];
+        const int k = kc[sizeof(R) == 8 ? 0 : 1];
         for (int half = 0; half < 2; half++) {
             const int e = half ? epi : EPI_STORE;
             hipEvent_t ev = nullptr;
             if (c->timing) timing_begin(c, &ev);
             if (half == 0) {
-                if (dag) launch_beo<R, 1, false>(c->stream, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, partial, st);
-                else launch_beo<R, 0, false>(c->stream, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, partial, st);
+                if (dag)
+                    launch_beo<R, 1, false>(c->stream, k, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, rm, partial, st);
+                else
+                    launch_beo<R, 0, false>(c->stream, k, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, rm, partial, st);
             } else {
-                if (dag) launch_beo<R, 1, true>(c->stream, e, nblk, dv, ndom, tmp, in, out, aux, partial, st);
-                else launch_beo<R, 0, true>(c->stream, e, nblk, dv, ndom, tmp, in, out, aux, partial, st);
+                if (dag) launch_beo<R, 1, true>(c->stream, k, e, nblk, dv, ndom, tmp, in, out, aux, rm, partial, st);
+                else launch_beo<R, 0, true>(c->stream, k, e, nblk, dv, ndom, tmp, in, out, aux, rm, partial, st);
             }
             if (c->timing) {
                 // per output half site: input, output (+ self, + aux) spinors; every link of a domain once
@@ -296,7 +335,7 @@ struct BatchEOSystem : System {
                 const double bytes = ((48.0 + extra) * sc + 144.0 * s) * sizeof(R);
                 const std::string name = std::string("k_beo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                          std::to_string(dag ? 1 : 0) + ", " + std::to_string(e) + ", " +
-                                         (half ? "true" : "false") + ">";
+                                         (half ? "true, " : "false, ") + std::to_string(k) + ">";
                 timing_end(c, ev, name, bytes);
             }
         }
@@ -461,7 +500,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
         if (e != DD_OK) return e;
     }
     // descriptors for a chunk length tc of the half-hop sweep, precision kind
-    auto build = [&](int tc, int kind, std::vector<BEODom>* h, std::vector<int>* sp0) {
+    auto build = [&](int tc, int kc, int kind, std::vector<BEODom>* h, std::vector<int>* sp0) {
         h->clear();
         sp0->clear();
         int blk = 0, slot = 0, seg = 0;
@@ -482,7 +521,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             d.slot0 = slot;
             h->push_back(d);
             for (int j = 0; j < it.ncol; j++) sp0->push_back(slot + j * d.nblk);
-            blk += d.nblk * it.ncol;
+            blk += d.nblk * it.ncol / kc;
             slot += d.nblk * it.ncol;
             seg += it.ncol;
         }
@@ -498,8 +537,8 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
         S.doms[kind] = dev;
         return DD_OK;
     };
-    // chunk length per precision: timed on the batch's Schur operator at first use (cached
-    // per batch signature), on work vectors whose contents do not matter
+    // chunk length and XCD remap per precision: timed on the batch's Schur operator at first
+    // use (cached per batch signature), on work vectors whose contents do not matter
     std::string sig;
     for (const Item& it : its)
         sig += ":" + std::to_string(it.g.T) + "x" + std::to_string(it.g.L) + "x" + std::to_string(it.ncol) + "b" +
@@ -508,10 +547,20 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
     std::vector<BEODom> hk;
     for (int kind = 0; kind < (mixed ? 2 : 1); kind++) {
         const std::string key = "beo:" + std::to_string(kind) + sig;
-        int tc = 4;
+        int tc = 4, rmap = 0, kcb = 1;
+        // columns per workgroup: FP32 may share link loads between 2 or 4 columns of a domain
+        auto kc_ok = [&](int kc) {
+            if (kc == 1) return true;
+            if (kind == 0 || (kc != 2 && kc != 4)) return false;
+            for (const Item& it : its)
+                if (it.ncol % kc != 0) return false;
+            return true;
+        };
         const auto hit = c->sched.find(key);
-        if (hit != c->sched.end()) {
+        if (hit != c->sched.end() && kc_ok(hit->second.kc)) {
             tc = hit->second.tc;
+            rmap = hit->second.remap;
+            kcb = hit->second.kc;
         } else {
             hipEvent_t ea, eb;
             DD_HIP(c, hipEventCreate(&ea));
@@ -520,28 +569,38 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             c->timing = 0;
             float best = 1e30f;
             std::vector<int> sp;
+            auto run = [&]() {
+                if (kind == 0) S.schur<double>(S.doms[0], S.tmp64, 0, EPI_STORE, bhat, x_e, nullptr, nullptr, nullptr);
+                else S.schur<float>(S.doms[1], S.tmp32, 0, EPI_STORE, (const cpx<float>*)x_o, (cpx<float>*)x_e,
+                                    nullptr, nullptr, nullptr);
+            };
             for (int t : {1, 2, 4, 8}) {
-                S.nblk = (unsigned)build(t, kind, &hk, &sp);
-                S.host = hk;
-                e = upload(kind, hk);
-                if (e != DD_OK) break;
-                auto run = [&]() {
-                    if (kind == 0) S.schur<double>(S.doms[0], S.tmp64, 0, EPI_STORE, bhat, x_e, nullptr, nullptr, nullptr);
-                    else S.schur<float>(S.doms[1], S.tmp32, 0, EPI_STORE, (const cpx<float>*)x_o, (cpx<float>*)x_e,
-                                        nullptr, nullptr, nullptr);
-                };
-                run();
-                run();
-                (void)hipEventRecord(ea, c->stream);
-                for (int r = 0; r < 3; r++) run();
-                (void)hipEventRecord(eb, c->stream);
-                (void)hipEventSynchronize(eb);
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, ea, eb);
-                if (ms < best) {
-                    best = ms;
-                    tc = t;
+                for (int kc : {1, 2, 4}) {
+                    if (!kc_ok(kc)) continue;
+                    S.kc[kind] = kc;
+                    S.nblk = (unsigned)build(t, kc, kind, &hk, &sp);
+                    S.host = hk;
+                    e = upload(kind, hk);
+                    if (e != DD_OK) break;
+                    for (int rm = 0; rm < 2; rm++) {
+                        S.remap[kind] = rm;
+                        run();
+                        run();
+                        (void)hipEventRecord(ea, c->stream);
+                        for (int r = 0; r < 3; r++) run();
+                        (void)hipEventRecord(eb, c->stream);
+                        (void)hipEventSynchronize(eb);
+                        float ms = 0;
+                        (void)hipEventElapsedTime(&ms, ea, eb);
+                        if (ms < best) {
+                            best = ms;
+                            tc = t;
+                            rmap = rm;
+                            kcb = kc;
+                        }
+                    }
                 }
+                if (e != DD_OK) break;
             }
             c->timing = saved;
             S.nblk = 0;  // launches size themselves from nblk64 / nblk32 again
@@ -551,9 +610,13 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             StencilSched keep;
             keep.nt = kBeoNT;
             keep.tc = tc;
+            keep.remap = rmap;
+            keep.kc = kcb;
             tune_cache_store(c, key, keep);
         }
-        const unsigned nb = (unsigned)build(tc, kind, &hk, &lay.sp0[kind]);
+        S.remap[kind] = rmap;
+        S.kc[kind] = kcb;
+        const unsigned nb = (unsigned)build(tc, kcb, kind, &hk, &lay.sp0[kind]);
         if (kind == 0) {
             S.nblk64 = nb;
             S.host = hk;

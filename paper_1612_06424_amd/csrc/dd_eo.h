@@ -13,11 +13,10 @@
 // opposite parity).  Links are reordered the same way, local to the field:
 // Ueo[mu][k][parity][nsite / 2] holds U_mu(x)_k of the field site x, so every
 // link load of a wavefront reads consecutive elements.  A hop leaving a slab
-// is dropped, so no link outside the field is needed.  One thread computes
-// one output half site:
+// is dropped, so no link outside the field is needed.  The kernels compute
 //     out = a_self * self + c_hop * (H in)_site      (in: the other parity)
-// (SELF = false: no self term, the pure hop).
-// with the fused epilogues of the full stencil (dd_dslash.h).
+// (SELF = false: no self term, the pure hop) with the fused epilogues of the
+// full stencil (dd_dslash.h).
 #pragma once
 
 #include "dd_internal.h"
@@ -25,90 +24,64 @@
 
 namespace dd {
 
-template <typename R, int DAG, int EPI, int NT, bool SELF>
-__device__ __forceinline__ void eo_hop_site(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
-                                            int p_out, int h, const cpx<R>* __restrict__ in,
-                                            const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
-                                            const cpx<R>* __restrict__ aux, double* __restrict__ slot) {
-    const int L = g.L, L2 = g.L2, L3 = g.L3;
-    const int nh = g.nsite >> 1;
-    constexpr uint32_t CB = sizeof(cpx<R>);
-    const uint32_t cs = (uint32_t)nh * CB;       // component stride of a half field (bytes)
-    const uint32_t ls = 2u * (uint32_t)nh * CB;  // link-row stride of Ueo (bytes)
-    const uint32_t ubytes = 17u * (uint32_t)nh * CB;  // rows 0..8 of one (mu, parity)
-    constexpr int FW = DAG ? +1 : -1;            // forward hop projector (1 + FW gamma)
-    constexpr int BW = -FW;
-    double d0 = 0, d1 = 0, d2 = 0;
-    if (h < nh) {
-        const int Lh = L >> 1, L3h = L3 >> 1;
-        const int tl = h / L3h;
-        const int rem = h - tl * L3h;
-        const int xh = rem % Lh, yz = rem / Lh;
-        const int y = yz % L, z = yz / L;
-        const int x = 2 * xh + ((p_out + tl + y + z) & 1);
-        const int sp = yz * L + x;
-        const int s = tl * L3 + sp;
-        const int t = g.t0 + tl;
-        const int tg = t >= g.T ? t - g.T : t;
-        const rsrc_t rf = make_rsrc(in, 12u * cs);
-        // forward links at this site (parity p_out), backward ones at the neighbour (1 - p_out)
-        rsrc_t uf[4], ub[4];
+// Spinor of site nb in column k of a group of columns stored back to back
+// (column stride fs bytes, component stride cs bytes).
+template <typename R>
+__device__ __forceinline__ void bload_spinor_col(rsrc_t f, uint32_t cs, uint32_t col_off, int nb,
+                                                 cpx<R> (&p)[12]) {
+    const uint32_t vo = (uint32_t)nb * (uint32_t)sizeof(cpx<R>);
 #pragma unroll
-        for (int mu = 0; mu < 4; mu++) {
-            uf[mu] = make_rsrc(Ueo + (size_t)(mu * 18 + p_out) * nh, ubytes);
-            ub[mu] = make_rsrc(Ueo + (size_t)(mu * 18 + 1 - p_out) * nh, ubytes);
-        }
-        const int dxp = (x == L - 1) ? -(L - 1) : 1, dxm = (x == 0) ? (L - 1) : -1;
-        const int dyp = (y == L - 1) ? -(L - 1) * L : L, dym = (y == 0) ? (L - 1) * L : -L;
-        const int dzp = (z == L - 1) ? -(L - 1) * L2 : L2, dzm = (z == 0) ? (L - 1) * L2 : -L2;
-        cpx<R> a[12];
-#pragma unroll
-        for (int c = 0; c < 12; c++) a[c] = mk<R>(0, 0);
-        // time: forward to tl + 1 (link at this site), backward from tl - 1 (link there)
-        const bool endt = (tl == g.nt - 1), begt = (tl == 0);
-        if (!endt || g.whole) {
-            const R ph = (tg == g.T - 1) ? R(g.bc) : R(1);
-            if (ph != R(0)) bhop<R, 0, FW, false>(a, rf, cs, (endt ? sp : s + L3) >> 1, uf[0], ls, h, ph);
-        }
-        if (!begt || g.whole) {
-            const R ph = (tg == 0) ? R(g.bc) : R(1);
-            const int nb = (begt ? (g.nt - 1) * L3 + sp : s - L3) >> 1;
-            if (ph != R(0)) bhop<R, 0, BW, true>(a, rf, cs, nb, ub[0], ls, nb, ph);
-        }
-        bhop<R, 1, FW, false>(a, rf, cs, (s + dxp) >> 1, uf[1], ls, h, R(1));
-        bhop<R, 1, BW, true>(a, rf, cs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1, R(1));
-        bhop<R, 2, FW, false>(a, rf, cs, (s + dyp) >> 1, uf[2], ls, h, R(1));
-        bhop<R, 2, BW, true>(a, rf, cs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1, R(1));
-        bhop<R, 3, FW, false>(a, rf, cs, (s + dzp) >> 1, uf[3], ls, h, R(1));
-        bhop<R, 3, BW, true>(a, rf, cs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1, R(1));
+    for (int c = 0; c < 12; c++) p[c] = bload<R>(f, vo, col_off + (uint32_t)c * cs);
+}
 
-        const rsrc_t ro = make_rsrc(out, 12u * cs);
-        constexpr bool has_self = SELF || EPI == EPI_TS;
-        const rsrc_t rs = make_rsrc(self != nullptr ? self : in, 12u * cs);
-        const rsrc_t rx = make_rsrc(aux != nullptr ? aux : in, 12u * cs);
-        const uint32_t vo = (uint32_t)h * CB;
+// The nine entries of the link at half-site index sl of one (mu, parity) block.
+template <typename R>
+__device__ __forceinline__ void bload_link(rsrc_t u, uint32_t ls, int sl, cpx<R> (&w)[9]) {
+    const uint32_t vo = (uint32_t)sl * (uint32_t)sizeof(cpx<R>);
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            const uint32_t so = (uint32_t)c * cs;
-            const cpx<R> pc = has_self ? bload<R>(rs, vo, so) : mk<R>(0, 0);
-            cpx<R> r = mk<R>(a_self * pc.re + c_hop * a[c].re, a_self * pc.im + c_hop * a[c].im);
-            cpx<R> q = mk<R>(0, 0);
-            if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
-            if (EPI == EPI_RESID) r = q - r;
-            bstore<R>(ro, vo, so, r);
-            if (EPI == EPI_DOT_AUX) {
-                d0 += (double)q.re * r.re + (double)q.im * r.im;
-                d1 += (double)q.re * r.im - (double)q.im * r.re;
-            } else if (EPI == EPI_TS) {
-                d0 += (double)r.re * pc.re + (double)r.im * pc.im;
-                d1 += (double)r.re * pc.im - (double)r.im * pc.re;
-                d2 += (double)r.re * r.re + (double)r.im * r.im;
-            } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
-                d0 += (double)r.re * r.re + (double)r.im * r.im;
-            }
-        }
+    for (int k = 0; k < 9; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
+}
+
+// One spatial hop for KC columns: the link is loaded once and transports the
+// projected neighbour of every column.
+template <typename R, int MU, int SGN, bool BWD, int KC>
+__device__ __forceinline__ void bhop_cols(cpx<R> (&a)[KC][12], rsrc_t f, uint32_t cs, uint32_t fs, int nb, rsrc_t u,
+                                          uint32_t ls, int sl) {
+    cpx<R> w[9];
+    bload_link<R>(u, ls, sl, w);
+#pragma unroll
+    for (int k = 0; k < KC; k++) {
+        cpx<R> p[12];
+        bload_spinor_col<R>(f, cs, (uint32_t)k * fs, nb, p);
+        cpx<R> h[6];
+        project<R, MU, SGN>(p, h);
+        cpx<R> t[6];
+        transport<R, BWD>(w, h, R(1), t);
+        accum<R, MU, SGN>(a[k], t);
     }
-    if (EPI != EPI_STORE) block_sum3<NT>(d0, d1, d2, slot);
+}
+
+// Workgroup sums of three partial values per column; column k's sums go to
+// slot + 3 k col_stride.
+template <int NT, int KC>
+__device__ __forceinline__ void block_sum_cols(double (&d)[KC][3], double* __restrict__ slot, size_t col_stride) {
+    __shared__ double sh[NT / kWave][KC * 3];
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < KC; k++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double v = wave_sum(d[k][j]);
+            if (l == 0) sh[w][k * 3 + j] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < KC * 3) {
+        double s = 0;
+#pragma unroll
+        for (int q = 0; q < NT / kWave; q++) s += sh[q][threadIdx.x];
+        const int k = threadIdx.x / 3, j = threadIdx.x % 3;
+        slot[(size_t)k * col_stride * 3 + j] = s;
+    }
 }
 
 // Time-sweep form of the half hop.  A thread owns one pair (xh, y, z) of
@@ -259,6 +232,176 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
         }
     }
     if (EPI != EPI_STORE) block_sum3<NT>(d0, d1, d2, slot);
+}
+
+
+// The same sweep for KC > 1 columns stored back to back from in / self / out
+// / aux (12 nsite/2 entries each): every link is loaded once for all of them;
+// the sums of column k go to slot + 3 k slot_col.  Column k's output is
+// written only if bit k of live is set (a stopped column keeps its vectors):
+// its stores go through a buffer resource of size 0 otherwise, which drops
+// them without a branch.
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC>
+__device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
+                                              int p_out, const cpx<R>* __restrict__ in,
+                                              const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
+                                              const cpx<R>* __restrict__ aux, unsigned live, int tile, int chunk,
+                                              int tc_len, double* __restrict__ slot, size_t slot_col) {
+    const int L = g.L, L2 = g.L2, L3 = g.L3;
+    const int nh = g.nsite >> 1;
+    const int Lh = L >> 1, L3h = L3 >> 1;
+    constexpr uint32_t CB = sizeof(cpx<R>);
+    const uint32_t cs = (uint32_t)nh * CB;
+    const uint32_t fs = 12u * cs;  // column stride (bytes)
+    const uint32_t ls = 2u * (uint32_t)nh * CB;
+    const uint32_t ubytes = 17u * (uint32_t)nh * CB;
+    constexpr int FW = DAG ? +1 : -1;
+    constexpr int BW = -FW;
+    constexpr bool has_self = SELF || EPI == EPI_TS;
+    double d[KC][3];
+#pragma unroll
+    for (int k = 0; k < KC; k++) d[k][0] = d[k][1] = d[k][2] = 0;
+    const int pr = tile * NT + (int)threadIdx.x;  // pair index within a slice
+    if (pr < L3h) {
+        const int xh = pr % Lh, yz = pr / Lh;
+        const int y = yz % L, z = yz / L;
+        const int nt = g.nt;
+        const int tb = chunk * tc_len;
+        const int te = min(nt, tb + tc_len);
+        auto tglob = [&](int tl) {
+            const int t = g.t0 + tl;
+            return t >= g.T ? t - g.T : t;
+        };
+        auto xof = [&](int tl) { return 2 * xh + ((p_out + tl + y + z) & 1); };
+        const rsrc_t rf = make_rsrc(in, (uint32_t)KC * fs);
+        rsrc_t ro[KC];
+#pragma unroll
+        for (int k = 0; k < KC; k++) ro[k] = make_rsrc(out + (size_t)k * 12 * nh, ((live >> k) & 1u) ? fs : 0u);
+        const rsrc_t rs = make_rsrc(self != nullptr ? self : in, (uint32_t)KC * fs);
+        const rsrc_t rx = make_rsrc(aux != nullptr ? aux : in, (uint32_t)KC * fs);
+        rsrc_t uf[4], ub[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            uf[mu] = make_rsrc(Ueo + (size_t)(mu * 18 + p_out) * nh, ubytes);
+            ub[mu] = make_rsrc(Ueo + (size_t)(mu * 18 + 1 - p_out) * nh, ubytes);
+        }
+        const int dyp = (y == L - 1) ? -(L - 1) * L : L, dym = (y == 0) ? (L - 1) * L : -L;
+        const int dzp = (z == L - 1) ? -(L - 1) * L2 : L2, dzm = (z == 0) ? (L - 1) * L2 : -L2;
+        // projected backward neighbours for the first two slices of the chunk:
+        // slot cA serves slice tl, cB slice tl + 1
+        cpx<R> cA[KC][6], cB[KC][6];
+#pragma unroll
+        for (int k = 0; k < KC; k++)
+#pragma unroll
+            for (int j = 0; j < 6; j++) cA[k][j] = cB[k][j] = mk<R>(0, 0);
+        auto load_bw = [&](int tl, cpx<R> (&h)[KC][6]) {
+            // P psi_in(x(tl), tl - 1), or 0 where there is no backward time hop
+            if (tl < nt && (tl > 0 || g.whole)) {
+                const int tm = tl > 0 ? tl - 1 : nt - 1;
+#pragma unroll
+                for (int k = 0; k < KC; k++) {
+                    cpx<R> p[12];
+                    bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, (tm * L3 + yz * L + xof(tl)) >> 1, p);
+                    project<R, 0, BW>(p, h[k]);
+                }
+            }
+        };
+        if (tb < te) load_bw(tb, cA);
+        if (tb + 1 < te) load_bw(tb + 1, cB);
+#pragma unroll 1
+        for (int tl = tb; tl < te; tl++) {
+            const int x = xof(tl);
+            const int sp = yz * L + x;
+            const int s = tl * L3 + sp;
+            const int h = s >> 1;
+            const int tg = tglob(tl);
+            cpx<R> a[KC][12];
+#pragma unroll
+            for (int k = 0; k < KC; k++)
+#pragma unroll
+                for (int c = 0; c < 12; c++) a[k][c] = mk<R>(0, 0);
+            // backward time hop from the carried half spinors, link U_0(x, tl - 1) on the input parity
+            if (tl > 0 || g.whole) {
+                const R ph = (tg == 0) ? R(g.bc) : R(1);
+                if (ph != R(0)) {
+                    cpx<R> w[9];
+                    bload_link<R>(ub[0], ls, ((tl > 0 ? tl - 1 : nt - 1) * L3 + sp) >> 1, w);
+#pragma unroll
+                    for (int k = 0; k < KC; k++) {
+                        cpx<R> t[6];
+                        transport<R, true>(w, cA[k], ph, t);
+                        accum<R, 0, BW>(a[k], t);
+                    }
+                }
+            }
+            // forward time hop; the loaded spinors are also the backward neighbours of slice tl + 2
+            cpx<R> nb2[KC][6];
+#pragma unroll
+            for (int k = 0; k < KC; k++)
+#pragma unroll
+                for (int j = 0; j < 6; j++) nb2[k][j] = mk<R>(0, 0);
+            const bool endt = (tl == nt - 1);
+            if (!endt || g.whole) {
+                const R ph = (tg == g.T - 1) ? R(g.bc) : R(1);
+                cpx<R> w[9];
+#pragma unroll
+                for (int k = 0; k < KC; k++) {
+                    cpx<R> p[12];
+                    bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, (endt ? sp : s + L3) >> 1, p);
+                    if (k == 0 && ph != R(0)) bload_link<R>(uf[0], ls, h, w);
+                    if (ph != R(0)) {
+                        cpx<R> hf[6];
+                        project<R, 0, FW>(p, hf);
+                        cpx<R> t[6];
+                        transport<R, false>(w, hf, ph, t);
+                        accum<R, 0, FW>(a[k], t);
+                    }
+                    if (!endt) project<R, 0, BW>(p, nb2[k]);
+                }
+            }
+            const int dxp = (x == L - 1) ? -(L - 1) : 1, dxm = (x == 0) ? (L - 1) : -1;
+            bhop_cols<R, 1, FW, false, KC>(a, rf, cs, fs, (s + dxp) >> 1, uf[1], ls, h);
+            bhop_cols<R, 1, BW, true, KC>(a, rf, cs, fs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1);
+            bhop_cols<R, 2, FW, false, KC>(a, rf, cs, fs, (s + dyp) >> 1, uf[2], ls, h);
+            bhop_cols<R, 2, BW, true, KC>(a, rf, cs, fs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1);
+            bhop_cols<R, 3, FW, false, KC>(a, rf, cs, fs, (s + dzp) >> 1, uf[3], ls, h);
+            bhop_cols<R, 3, BW, true, KC>(a, rf, cs, fs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1);
+
+            const uint32_t vo = (uint32_t)h * CB;
+#pragma unroll
+            for (int k = 0; k < KC; k++) {
+#pragma unroll
+                for (int c = 0; c < 12; c++) {
+                    const uint32_t so = (uint32_t)k * fs + (uint32_t)c * cs;
+                    const cpx<R> pc = has_self ? bload<R>(rs, vo, so) : mk<R>(0, 0);
+                    cpx<R> r = mk<R>(a_self * pc.re + c_hop * a[k][c].re, a_self * pc.im + c_hop * a[k][c].im);
+                    cpx<R> q = mk<R>(0, 0);
+                    if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
+                    if (EPI == EPI_RESID) r = q - r;
+                    bstore<R>(ro[k], vo, (uint32_t)c * cs, r);
+                    if (EPI == EPI_DOT_AUX) {
+                        d[k][0] += (double)q.re * r.re + (double)q.im * r.im;
+                        d[k][1] += (double)q.re * r.im - (double)q.im * r.re;
+                    } else if (EPI == EPI_TS) {
+                        d[k][0] += (double)r.re * pc.re + (double)r.im * pc.im;
+                        d[k][1] += (double)r.re * pc.im - (double)r.im * pc.re;
+                        d[k][2] += (double)r.re * r.re + (double)r.im * r.im;
+                    } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
+                        d[k][0] += (double)r.re * r.re + (double)r.im * r.im;
+                    }
+                }
+            }
+            // slice tl + 1 uses cB; slice tl + 2 the half spinors just loaded
+#pragma unroll
+            for (int k = 0; k < KC; k++)
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    cA[k][j] = cB[k][j];
+                    cB[k][j] = nb2[k][j];
+                }
+        }
+    }
+    if (EPI != EPI_STORE) block_sum_cols<NT, KC>(d, slot, slot_col);
 }
 
 }  // namespace dd

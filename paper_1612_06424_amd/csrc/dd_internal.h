@@ -120,6 +120,7 @@ struct StencilSched {
     int nt = 128;
     int tc = 8;
     int remap = 0;
+    int kc = 1;  // columns per thread (even-odd half hop)
 };
 
 struct TimedLaunch {

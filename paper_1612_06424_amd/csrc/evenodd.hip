@@ -19,24 +19,39 @@ namespace dd {
 
 namespace {
 
-// Workgroup -> (column fastest, tile of NT pairs of a slice, chunk of tc_len
-// slices); partial slot of (col, block) = col * nblk + block.
-template <typename R, int DAG, int EPI, int NT, bool SELF>
+// Workgroup -> (group of KC columns fastest, tile of NT pairs of a slice, chunk
+// of tc_len slices); partial slot of (col, block) = col * nblk + block.  ncol is
+// a multiple of KC.
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC>
 __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self,
                                                              R c_hop, int p_out, const cpx<R>* __restrict__ in,
                                                              const cpx<R>* __restrict__ self,
                                                              cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
-                                                             int ncol, int tc_len, double* __restrict__ partial,
+                                                             int ncol, int tc_len, int remap,
+                                                             double* __restrict__ partial,
                                                              const ColState* __restrict__ st) {
-    const int lb = (int)blockIdx.x;
-    const int col = lb % ncol, blk = lb / ncol;
-    if (st != nullptr && !st[col].active) return;  // uniform over the workgroup
-    const int nblk = (int)gridDim.x / ncol;
+    const int lb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int ngrp = ncol / KC;
+    const int col0 = (lb % ngrp) * KC, blk = lb / ngrp;
+    unsigned live = 0;  // active columns of the group; the workgroup runs while one is
+#pragma unroll
+    for (int k = 0; k < KC; k++)
+        if (st == nullptr || st[col0 + k].active) live |= 1u << k;
+    if (live == 0) return;  // uniform over the workgroup
+    const int nblk = (int)gridDim.x / ngrp;
     const int ntile = ((g.L3 >> 1) + NT - 1) / NT;
-    const size_t off = (size_t)col * 12 * (size_t)(g.nsite >> 1);
-    eo_sweep_tile<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, in + off, self != nullptr ? self + off : nullptr,
-                                         out + off, aux != nullptr ? aux + off : nullptr, blk % ntile, blk / ntile,
-                                         tc_len, partial + ((size_t)col * nblk + blk) * 3);
+    const size_t off = (size_t)col0 * 12 * (size_t)(g.nsite >> 1);
+    double* slot = partial + ((size_t)col0 * nblk + blk) * 3;
+    if constexpr (KC == 1)
+        eo_sweep_tile<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, in + off,
+                                             self != nullptr ? self + off : nullptr, out + off,
+                                             aux != nullptr ? aux + off : nullptr, blk % ntile, blk / ntile, tc_len,
+                                             slot);
+    else
+        eo_sweep_cols<R, DAG, EPI, NT, SELF, KC>(g, U, a_self, c_hop, p_out, in + off,
+                                                 self != nullptr ? self + off : nullptr, out + off,
+                                                 aux != nullptr ? aux + off : nullptr, live, blk % ntile, blk / ntile,
+                                                 tc_len, slot, (size_t)nblk);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -88,14 +103,14 @@ constexpr int kEoNT = 256;
 // workgroups per column: tiles of kEoNT pairs per slice x chunks of tc slices
 int eo_blocks(const Geo& g, int tc) { return (((g.L3 >> 1) + kEoNT - 1) / kEoNT) * ((g.nt + tc - 1) / tc); }
 
-template <typename R, int DAG, bool SELF>
+template <typename R, int DAG, bool SELF, int KC>
 void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
                    const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                   double* partial, const ColState* st) {
+                   int remap, double* partial, const ColState* st) {
     const dim3 block(kEoNT);
-#define DD_EO_CASE(E)                                                                                              \
-    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, self, \
-                       out, aux, ncol, tc, partial, st)
+#define DD_EO_CASE(E)                                                                                            \
+    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF, KC>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, \
+                       self, out, aux, ncol, tc, remap, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_EO_CASE(EPI_DOT_AUX); break;
@@ -106,18 +121,49 @@ void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>
 #undef DD_EO_CASE
 }
 
+// Columns per thread of the half-hop sweep that a launch may use: FP32 shares
+// each link load between up to 4 columns; FP64 already needs the whole
+// register file for one.
+template <typename R>
+bool eo_kc_ok(int kc, int ncol) {
+    if (sizeof(R) == 8) return kc == 1;
+    return (kc == 1 || kc == 2 || kc == 4) && ncol % kc == 0;
+}
+
+template <typename R, int D, bool SF>
+void launch_eo_kc(hipStream_t s, int kc, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop,
+                  int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
+                  int remap, double* partial, const ColState* st) {
+    if constexpr (sizeof(R) == 4) {
+        if (kc == 4) {
+            launch_eo_epi<R, D, SF, 4>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap,
+                                       partial, st);
+            return;
+        }
+        if (kc == 2) {
+            launch_eo_epi<R, D, SF, 2>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap,
+                                       partial, st);
+            return;
+        }
+    }
+    launch_eo_epi<R, D, SF, 1>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, partial,
+                               st);
+}
+
 // out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
-// time chunks of tc slices
+// time chunks of tc slices, kc columns per thread (eo_kc_ok), workgroups
+// optionally in XCD-contiguous ranges
 template <typename R>
 void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, double c_hop, int p_out, int dag,
                    int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                   double* partial, const ColState* st) {
-    const dim3 grid((unsigned)(eo_blocks(g, tc) * ncol));
+                   int kc, int remap, double* partial, const ColState* st) {
+    if (!eo_kc_ok<R>(kc, ncol)) kc = 1;
+    const dim3 grid((unsigned)(eo_blocks(g, tc) * (ncol / kc)));
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
-#define DD_EO_LAUNCH(D, SF) \
-    launch_eo_epi<R, D, SF>(c->stream, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, tc, \
-                            partial, st)
+#define DD_EO_LAUNCH(D, SF)                                                                                           \
+    launch_eo_kc<R, D, SF>(c->stream, kc, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, tc, \
+                           remap, partial, st)
     const bool sf = self != nullptr && a_self != 0;
     if (dag) {
         if (sf) DD_EO_LAUNCH(1, true);
@@ -136,7 +182,7 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, doub
         const double bytes = nh * ((48.0 + extra) * ncol + 144.0) * sizeof(R);
         const std::string name = std::string("k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
-                                 std::to_string(kEoNT) + (sf ? ", true>" : ", false>");
+                                 std::to_string(kEoNT) + (sf ? ", true, " : ", false, ") + std::to_string(kc) + ">";
         timing_end(c, ev, name, bytes);
     }
 }
@@ -152,58 +198,72 @@ struct EOSystem : System {
     int ncol = 0;
     cpx<double>* tmp64 = nullptr;
     cpx<float>* tmp32 = nullptr;
-    int tc[2] = {8, 8};  // chunk length of the half-hop sweep per kind (0: FP64, 1: FP32)
+    // launch shape of the half-hop sweep per kind (0: FP64, 1: FP32): chunk length, XCD remap,
+    // columns per thread
+    StencilSched sh[2];
     template <typename R>
-    void schur(const cpx<R>* UR, cpx<R>* tmp, int t, int d, int epi, const cpx<R>* in, cpx<R>* out,
+    void schur(const cpx<R>* UR, cpx<R>* tmp, const StencilSched& sc, int d, int epi, const cpx<R>* in, cpx<R>* out,
                const cpx<R>* aux, double* partial, const ColState* st) {
-        launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, t, partial, st);
-        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, t, partial, st);
+        launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, sc.tc, sc.kc, sc.remap,
+                         partial, st);
+        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, sc.tc, sc.kc, sc.remap, partial,
+                         st);
     }
     void apply64(int d, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux, double* partial,
                  const ColState* st) override {
-        schur<double>(U64, tmp64, tc[0], d ^ dag, epi, in, out, aux, partial, st);
+        schur<double>(U64, tmp64, sh[0], d ^ dag, epi, in, out, aux, partial, st);
     }
     void apply32(int d, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux, double* partial,
                  const ColState* st) override {
-        schur<float>(U32, tmp32, tc[1], d ^ dag, epi, in, out, aux, partial, st);
+        schur<float>(U32, tmp32, sh[1], d ^ dag, epi, in, out, aux, partial, st);
     }
 };
 
-// Chunk length of the half-hop sweep for one precision: timed on the Schur
-// operator of this geometry and column count at first use (candidates 1, 2,
-// 4, 8 slices), cached in the context like the stencil shapes; small fields
-// take 4 untimed.
+// Launch shape of the half-hop sweep for one precision: timed on the Schur
+// operator of this geometry and column count at first use (chunks of 1, 2,
+// 4, 8 slices, workgroups in hardware order or XCD-contiguous ranges, 1, 2 or
+// 4 columns per thread where allowed), cached in the context like the stencil
+// shapes; small fields take 4 slices, no remap, one column, untimed.
 template <typename R>
-int eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, const cpx<R>* in, cpx<R>* out) {
+StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, const cpx<R>* in, cpx<R>* out) {
     const Geo& g = S.g;
     const std::string key = std::string("eo:") + (sizeof(R) == 8 ? "0" : "1") + ":" + std::to_string(S.ncol) + ":" +
                             std::to_string(g.L) + ":" + std::to_string(g.T) + ":" + std::to_string(g.nt) + ":" +
                             std::to_string(g.whole);
     const auto hit = c->sched.find(key);
-    if (hit != c->sched.end()) return hit->second.tc;
+    if (hit != c->sched.end()) return hit->second;
     StencilSched best;
     best.nt = kEoNT;
     best.tc = std::min(4, g.nt);
+    best.kc = 1;
     if ((size_t)g.nsite * S.ncol >= ((size_t)1 << 18)) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
             const int saved = c->timing;
             c->timing = 0;
             float best_ms = 1e30f;
-            for (int t : {1, 2, 4, 8}) {
-                if (t > g.nt) continue;
-                for (int w = 0; w < 2; w++) S.schur<R>(UR, tmp, t, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
-                (void)hipEventRecord(a, c->stream);
-                for (int r = 0; r < 3; r++) S.schur<R>(UR, tmp, t, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
-                (void)hipEventRecord(b, c->stream);
-                (void)hipEventSynchronize(b);
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, a, b);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best.tc = t;
-                }
-            }
+            for (int t : {1, 2, 4, 8})
+                for (int rm = 0; rm < 2; rm++)
+                    for (int kc : {1, 2, 4}) {
+                        if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol)) continue;
+                        StencilSched sc = best;
+                        sc.tc = t;
+                        sc.remap = rm;
+                        sc.kc = kc;
+                        for (int w = 0; w < 2; w++)
+                            S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                        (void)hipEventRecord(a, c->stream);
+                        for (int r = 0; r < 3; r++)
+                            S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                        (void)hipEventRecord(b, c->stream);
+                        (void)hipEventSynchronize(b);
+                        float ms = 0;
+                        (void)hipEventElapsedTime(&ms, a, b);
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = sc;
+                        }
+                    }
             c->timing = saved;
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
@@ -211,7 +271,7 @@ int eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, const cpx<R>*
         (void)hipGetLastError();
     }
     tune_cache_store(c, key, best);
-    return best.tc;
+    return best;
 }
 
 }  // namespace
@@ -242,7 +302,7 @@ void launch_eo_merge(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* ev, c
 void launch_eo_hop64(dd_ctx* c, const Geo& g, const cpx<double>* Ueo, double a_self, double c_hop, int p_out, int dag,
                      const cpx<double>* in, const cpx<double>* self, cpx<double>* out, int ncol) {
     launch_eo_hop<double>(c, g, Ueo, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol,
-                          std::min(4, g.nt), nullptr, nullptr);
+                          std::min(4, g.nt), 1, 0, nullptr, nullptr);
 }
 
 dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,
@@ -285,14 +345,14 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
         if (e != DD_OK) return e;
         S.has32 = true;
     }
-    // chunk lengths (tuned on two half-field work vectors whose contents do not matter)
-    S.tc[0] = eo_tune<double>(c, S, Ueo64, S.tmp64, bhat, xx);
+    // launch shapes (tuned on two half-field work vectors whose contents do not matter)
+    S.sh[0] = eo_tune<double>(c, S, Ueo64, S.tmp64, bhat, xx);
     if (S.has32) {
         cpx<float>* a32 = (cpx<float>*)workspace(c, W_R32, nhalf * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
         cpx<float>* b32 = (cpx<float>*)workspace(c, W_RH32, nhalf * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
-        S.tc[1] = eo_tune<float>(c, S, S.U32, S.tmp32, a32, b32);
+        S.sh[1] = eo_tune<float>(c, S, S.U32, S.tmp32, a32, b32);
     }
     SegLayout lay;
     const int n = (int)(12 * nh);
@@ -301,7 +361,7 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
         lay.len.push_back(n);
     }
     for (int kind = 0; kind < 2; kind++) {
-        const int nblk = eo_blocks(g, S.tc[kind]);
+        const int nblk = eo_blocks(g, S.sh[kind].tc);
         lay.sp0[kind].resize(ncol + 1);
         for (int k = 0; k <= ncol; k++) lay.sp0[kind][k] = k * nblk;
     }

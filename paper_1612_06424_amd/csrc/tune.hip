@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
+#include <sstream>
 #include <string>
 
 #include "dd_internal.h"
@@ -89,9 +90,16 @@ void tune_cache_load(dd_ctx* c) {
     const char* path = std::getenv("DD_TUNE_CACHE");
     if (path == nullptr || *path == 0) return;
     std::ifstream f(path);
-    std::string key;
-    StencilSched sc;
-    while (f >> key >> sc.nt >> sc.tc >> sc.remap) c->sched[key] = sc;
+    std::string line;
+    while (std::getline(f, line)) {
+        // key nt tc remap [kc]
+        std::istringstream in(line);
+        std::string key;
+        StencilSched sc;
+        if (!(in >> key >> sc.nt >> sc.tc >> sc.remap)) continue;
+        if (!(in >> sc.kc)) sc.kc = 1;
+        c->sched[key] = sc;
+    }
 }
 
 void tune_cache_store(dd_ctx* c, const std::string& key, const StencilSched& sc) {
@@ -99,7 +107,7 @@ void tune_cache_store(dd_ctx* c, const std::string& key, const StencilSched& sc)
     const char* path = std::getenv("DD_TUNE_CACHE");
     if (path == nullptr || *path == 0) return;
     std::ofstream f(path, std::ios::app);
-    f << key << " " << sc.nt << " " << sc.tc << " " << sc.remap << "\n";
+    f << key << " " << sc.nt << " " << sc.tc << " " << sc.remap << " " << sc.kc << "\n";
 }
 
 StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol) {

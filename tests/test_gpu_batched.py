@@ -37,6 +37,16 @@ EO_BATCH = [
 ]
 
 
+# bipartite domains whose column counts are all multiples of 4, so that the FP32
+# half hop may serve 1, 2 or 4 columns per workgroup
+KC_BATCH = [
+    (8, 4, 0, 0.125, 4, 0.3),
+    (4, 6, 0, 0.13, 12, 0.3),
+    (6, 4, -1, 0.128, 4, 0.3),
+    (8, 6, 1, 0.12, 8, 0.3),
+]
+
+
 def _items(dd, seed, batch=SMALL_BATCH):
     items, refs = [], []
     for i, (T, L, bc, kappa, ncol, eps) in enumerate(batch):
@@ -88,6 +98,37 @@ def test_batched_repeatable_and_matches_single(batch):
         sctx = dd.Context(T, L, bc)
         x, _ = dd.block_solve(sctx, it["U"], kappa, it["b"], None, p)
         assert relerr(dd.unpack_field(x), dd.unpack_field(it["x"])) < 1e-9
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_batched_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
+    """The XCD remap of the batched half hop gives bitwise the same mixed
+    solution; columns per workgroup and the chunk length change the rounding
+    only (agreement to 1e-8, iteration counts within a few).  Columns of a
+    domain stop at different iterations, so stopped and running columns share
+    workgroups."""
+    dd = lib()
+    step(f"batched launch shapes solver={solver}")
+    items, refs = _items(dd, 3200, KC_BATCH)
+    sig = "".join(f":{T}x{L}x{ncol}b{bc}" for (T, L, bc, _, ncol, _) in KC_BATCH)
+    p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
+    results, its = [], []
+    for tc, remap, kc in [(2, 0, 1), (2, 1, 1), (2, 0, 2), (2, 1, 4), (4, 1, 2)]:
+        path = tmp_path / f"shapes_{tc}_{remap}_{kc}.txt"
+        path.write_text(f"beo:0{sig} 256 {tc} {remap} 1\nbeo:1{sig} 256 {tc} {remap} {kc}\n")
+        monkeypatch.setenv("DD_TUNE_CACHE", str(path))
+        ctx = dd.Context(8, 4, 0)
+        stats = dd.block_solve_batched(ctx, items, p)
+        for st, (_, _, _, _, ncol, _) in zip(stats, KC_BATCH):
+            assert max(st["true_rel_resid"][:ncol]) <= p.tol
+        results.append([it["x"].clone() for it in items])
+        its.append([st["iters"] for st in stats])
+    for a, b in zip(results[1], results[0]):
+        assert torch.equal(a, b)
+    for r, it in zip(results[2:], its[2:]):
+        for a, b in zip(r, results[0]):
+            assert relerr(dd.unpack_field(a), dd.unpack_field(b)) < 1e-8
+        assert max(abs(i - j) for i, j in zip(it, its[0])) <= 4
 
 
 def test_batched_96_domains_full_size():

@@ -197,6 +197,45 @@ def test_even_odd_matches_full_operator(prec, solver, T, L, bc, dom):
     assert relerr(got[dd.DD_PRECOND_EO], got[dd.DD_PRECOND_NONE]) < 2 * bar
 
 
+@pytest.mark.parametrize("solver", [0, 1])
+def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
+    """The XCD remap of the half hop only moves work between workgroups: mixed
+    solves give bitwise the same solution.  Columns per thread (the kernel is
+    compiled once per count, and the compiler may contract multiply-adds
+    differently in each) and the chunk length (it regroups the partial sums)
+    change the rounding only: the solutions agree to 1e-8 with the same
+    iteration counts within a few.  Gaussian and point sources stop at
+    different iterations, so stopped columns share workgroups with running
+    ones, whose launches must leave the stopped columns' vectors as they were
+    (otherwise the reliable updates lose the search directions)."""
+    dd = lib()
+    step(f"even-odd launch shapes solver={solver}")
+    T, L, bc, dom, kappa = 16, 8, -1, (4, 8), 0.13
+    U = random_links(T, L, 0.3, 2700)
+    nsite = dom[1] * L ** 3
+    b = gaussian_field(nsite, 12, 2701)
+    b[6:] = 0
+    for j in range(6, 12):
+        b[j, (j * 977) % nsite, j] = 1.0
+    Ud, bd = dd.pack_links(U), dd.pack_field(b)
+    p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
+    tail = f"12:{L}:{T}:{dom[1]}:0"
+    xs, its = [], []
+    for tc, remap, kc in [(2, 0, 1), (2, 1, 1), (2, 0, 2), (2, 1, 4), (4, 1, 2)]:
+        path = tmp_path / f"shapes_{tc}_{remap}_{kc}.txt"
+        path.write_text(f"eo:0:{tail} 256 {tc} {remap} 1\neo:1:{tail} 256 {tc} {remap} {kc}\n")
+        monkeypatch.setenv("DD_TUNE_CACHE", str(path))
+        ctx = dd.Context(T, L, bc)
+        x, stats = dd.block_solve(ctx, Ud, kappa, bd, dom, p)
+        assert max(stats["true_rel_resid"]) <= p.tol
+        xs.append(x)
+        its.append(stats["iters"])
+    assert torch.equal(xs[1], xs[0])
+    for x, it in zip(xs[2:], its[2:]):
+        assert relerr(dd.unpack_field(x), dd.unpack_field(xs[0])) < 1e-8
+        assert abs(it - its[0]) <= 4
+
+
 def test_even_odd_adjoint_and_fallback():
     """D^+ solves go through the even-odd path too; an odd time extent on a whole
     lattice (not bipartite) falls back to the full operator and still converges."""
