@@ -78,7 +78,7 @@ struct BEODom {
     int slot0;         // its first partial slot
     int ntile;         // tiles of kBeoNT pairs per slice
     int tc;            // slices per chunk
-    int pad;
+    int blocked;       // brick tiles (pair_site)
 };
 static_assert(sizeof(BEODom) % 8 == 0, "descriptor layout must be the same on host and device");
 
@@ -117,12 +117,12 @@ __global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ d
         eo_sweep_tile<R, DAG, EPI, kBeoNT, SCHUR>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1, in + off,
                                                   self != nullptr ? self + off : nullptr, out + off,
                                                   aux != nullptr ? aux + off : nullptr, blk % d.ntile, blk / d.ntile,
-                                                  d.tc, slot);
+                                                  d.tc, d.blocked, slot);
     else
         eo_sweep_cols<R, DAG, EPI, kBeoNT, SCHUR, KC>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1,
                                                       in + off, self != nullptr ? self + off : nullptr, out + off,
                                                       aux != nullptr ? aux + off : nullptr, live, blk % d.ntile,
-                                                      blk / d.ntile, d.tc, slot, (size_t)d.nblk);
+                                                      blk / d.ntile, d.tc, d.blocked, slot, (size_t)d.nblk);
 }
 
 template <typename R, int DAG, bool SCHUR, int KC>
@@ -500,7 +500,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
         if (e != DD_OK) return e;
     }
     // descriptors for a chunk length tc of the half-hop sweep, precision kind
-    auto build = [&](int tc, int kc, int kind, std::vector<BEODom>* h, std::vector<int>* sp0) {
+    auto build = [&](int tc, int kc, int blocked, int kind, std::vector<BEODom>* h, std::vector<int>* sp0) {
         h->clear();
         sp0->clear();
         int blk = 0, slot = 0, seg = 0;
@@ -518,6 +518,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             d.ntile = ((it.g.L3 >> 1) + kBeoNT - 1) / kBeoNT;
             d.tc = std::min(tc, it.g.nt);
             d.nblk = d.ntile * ((it.g.nt + d.tc - 1) / d.tc);
+            d.blocked = blocked && it.g.L % 4 == 0;
             d.slot0 = slot;
             h->push_back(d);
             for (int j = 0; j < it.ncol; j++) sp0->push_back(slot + j * d.nblk);
@@ -537,8 +538,9 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
         S.doms[kind] = dev;
         return DD_OK;
     };
-    // chunk length and XCD remap per precision: timed on the batch's Schur operator at first
-    // use (cached per batch signature), on work vectors whose contents do not matter
+    // chunk length, columns per workgroup, tile shape and XCD remap per precision: timed on
+    // the batch's Schur operator at first use (cached per batch signature), on work vectors
+    // whose contents do not matter
     std::string sig;
     for (const Item& it : its)
         sig += ":" + std::to_string(it.g.T) + "x" + std::to_string(it.g.L) + "x" + std::to_string(it.ncol) + "b" +
@@ -547,7 +549,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
     std::vector<BEODom> hk;
     for (int kind = 0; kind < (mixed ? 2 : 1); kind++) {
         const std::string key = "beo:" + std::to_string(kind) + sig;
-        int tc = 4, rmap = 0, kcb = 1;
+        int tc = 4, rmap = 0, kcb = 1, blk = 0;
         // columns per workgroup: FP32 may share link loads between 2 or 4 columns of a domain
         auto kc_ok = [&](int kc) {
             if (kc == 1) return true;
@@ -561,6 +563,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             tc = hit->second.tc;
             rmap = hit->second.remap;
             kcb = hit->second.kc;
+            blk = hit->second.blocked;
         } else {
             hipEvent_t ea, eb;
             DD_HIP(c, hipEventCreate(&ea));
@@ -574,31 +577,37 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
                 else S.schur<float>(S.doms[1], S.tmp32, 0, EPI_STORE, (const cpx<float>*)x_o, (cpx<float>*)x_e,
                                     nullptr, nullptr, nullptr);
             };
+            bool any4 = false;  // some domain can take brick tiles
+            for (const Item& it : its) any4 = any4 || it.g.L % 4 == 0;
             for (int t : {1, 2, 4, 8}) {
                 for (int kc : {1, 2, 4}) {
-                    if (!kc_ok(kc)) continue;
-                    S.kc[kind] = kc;
-                    S.nblk = (unsigned)build(t, kc, kind, &hk, &sp);
-                    S.host = hk;
-                    e = upload(kind, hk);
-                    if (e != DD_OK) break;
-                    for (int rm = 0; rm < 2; rm++) {
-                        S.remap[kind] = rm;
-                        run();
-                        run();
-                        (void)hipEventRecord(ea, c->stream);
-                        for (int r = 0; r < 3; r++) run();
-                        (void)hipEventRecord(eb, c->stream);
-                        (void)hipEventSynchronize(eb);
-                        float ms = 0;
-                        (void)hipEventElapsedTime(&ms, ea, eb);
-                        if (ms < best) {
-                            best = ms;
-                            tc = t;
-                            rmap = rm;
-                            kcb = kc;
+                    for (int bl = 0; bl < (any4 ? 2 : 1); bl++) {
+                        if (!kc_ok(kc)) continue;
+                        S.kc[kind] = kc;
+                        S.nblk = (unsigned)build(t, kc, bl, kind, &hk, &sp);
+                        S.host = hk;
+                        e = upload(kind, hk);
+                        if (e != DD_OK) break;
+                        for (int rm = 0; rm < 2; rm++) {
+                            S.remap[kind] = rm;
+                            run();
+                            run();
+                            (void)hipEventRecord(ea, c->stream);
+                            for (int r = 0; r < 3; r++) run();
+                            (void)hipEventRecord(eb, c->stream);
+                            (void)hipEventSynchronize(eb);
+                            float ms = 0;
+                            (void)hipEventElapsedTime(&ms, ea, eb);
+                            if (ms < best) {
+                                best = ms;
+                                tc = t;
+                                rmap = rm;
+                                kcb = kc;
+                                blk = bl;
+                            }
                         }
                     }
+                    if (e != DD_OK) break;
                 }
                 if (e != DD_OK) break;
             }
@@ -612,11 +621,12 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             keep.tc = tc;
             keep.remap = rmap;
             keep.kc = kcb;
+            keep.blocked = blk;
             tune_cache_store(c, key, keep);
         }
         S.remap[kind] = rmap;
         S.kc[kind] = kcb;
-        const unsigned nb = (unsigned)build(tc, kcb, kind, &hk, &lay.sp0[kind]);
+        const unsigned nb = (unsigned)build(tc, kcb, blk, kind, &hk, &lay.sp0[kind]);
         if (kind == 0) {
             S.nblk64 = nb;
             S.host = hk;

@@ -84,19 +84,40 @@ __device__ __forceinline__ void block_sum_cols(double (&d)[KC][3], double* __res
     }
 }
 
+// Pair index pr of a slice -> (xh, y, z).  Rows: NT consecutive pairs fill
+// whole x rows of one z plane after another.  Blocked (L a multiple of 4): the
+// (y, z) plane is cut into 4 x 4 blocks of full x rows, so a tile of NT pairs is
+// a compact brick and its y and z neighbours mostly lie inside it; a wavefront
+// still reads 4 consecutive rows (contiguous memory).
+__device__ __forceinline__ void pair_site(int pr, int Lh, int L, int blocked, int& xh, int& y, int& z) {
+    if (blocked) {
+        const int per = Lh * 16;
+        const int b = pr / per, r = pr - b * per;
+        const int q = r / Lh, nby = L >> 2;
+        xh = r - q * Lh;
+        y = (b % nby) * 4 + (q & 3);
+        z = (b / nby) * 4 + (q >> 2);
+    } else {
+        const int yz = pr / Lh;
+        xh = pr - yz * Lh;
+        y = yz % L;
+        z = yz / L;
+    }
+}
+
 // Time-sweep form of the half hop.  A thread owns one pair (xh, y, z) of
 // every slice and walks a chunk of tc_len slices; at slice t its output site is
 // x = 2 xh + b(t), with b alternating from slice to slice.  The forward time
 // neighbour loaded at slice t, (x(t), t + 1), is the backward time neighbour of
 // the output at slice t + 2 (same x), so its projected half spinor is carried
 // two steps and every input site of the chunk is loaded once in time
-// direction.  tile: NT consecutive pair indices of a slice.
+// direction.  tile: NT consecutive pair indices of a slice (pair_site).
 template <typename R, int DAG, int EPI, int NT, bool SELF>
 __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
                                               int p_out, const cpx<R>* __restrict__ in,
                                               const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
                                               const cpx<R>* __restrict__ aux, int tile, int chunk, int tc_len,
-                                              double* __restrict__ slot) {
+                                              int blocked, double* __restrict__ slot) {
     const int L = g.L, L2 = g.L2, L3 = g.L3;
     const int nh = g.nsite >> 1;
     const int Lh = L >> 1, L3h = L3 >> 1;
@@ -110,8 +131,9 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
     double d0 = 0, d1 = 0, d2 = 0;
     const int pr = tile * NT + (int)threadIdx.x;  // pair index within a slice
     if (pr < L3h) {
-        const int xh = pr % Lh, yz = pr / Lh;
-        const int y = yz % L, z = yz / L;
+        int xh, y, z;
+        pair_site(pr, Lh, L, blocked, xh, y, z);
+        const int yz = z * L + y;
         const int nt = g.nt;
         const int tb = chunk * tc_len;
         const int te = min(nt, tb + tc_len);
@@ -246,7 +268,7 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
                                               int p_out, const cpx<R>* __restrict__ in,
                                               const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
                                               const cpx<R>* __restrict__ aux, unsigned live, int tile, int chunk,
-                                              int tc_len, double* __restrict__ slot, size_t slot_col) {
+                                              int tc_len, int blocked, double* __restrict__ slot, size_t slot_col) {
     const int L = g.L, L2 = g.L2, L3 = g.L3;
     const int nh = g.nsite >> 1;
     const int Lh = L >> 1, L3h = L3 >> 1;
@@ -263,8 +285,9 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
     for (int k = 0; k < KC; k++) d[k][0] = d[k][1] = d[k][2] = 0;
     const int pr = tile * NT + (int)threadIdx.x;  // pair index within a slice
     if (pr < L3h) {
-        const int xh = pr % Lh, yz = pr / Lh;
-        const int y = yz % L, z = yz / L;
+        int xh, y, z;
+        pair_site(pr, Lh, L, blocked, xh, y, z);
+        const int yz = z * L + y;
         const int nt = g.nt;
         const int tb = chunk * tc_len;
         const int te = min(nt, tb + tc_len);

@@ -120,7 +120,8 @@ struct StencilSched {
     int nt = 128;
     int tc = 8;
     int remap = 0;
-    int kc = 1;  // columns per thread (even-odd half hop)
+    int kc = 1;       // columns per thread (even-odd half hop)
+    int blocked = 0;  // tiles as 4 x 4 (y, z) bricks of x rows (even-odd half hop)
 };
 
 struct TimedLaunch {

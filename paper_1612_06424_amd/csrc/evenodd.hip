@@ -27,7 +27,7 @@ __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R
                                                              R c_hop, int p_out, const cpx<R>* __restrict__ in,
                                                              const cpx<R>* __restrict__ self,
                                                              cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
-                                                             int ncol, int tc_len, int remap,
+                                                             int ncol, int tc_len, int remap, int blocked,
                                                              double* __restrict__ partial,
                                                              const ColState* __restrict__ st) {
     const int lb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -46,12 +46,12 @@ __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R
         eo_sweep_tile<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, in + off,
                                              self != nullptr ? self + off : nullptr, out + off,
                                              aux != nullptr ? aux + off : nullptr, blk % ntile, blk / ntile, tc_len,
-                                             slot);
+                                             blocked, slot);
     else
         eo_sweep_cols<R, DAG, EPI, NT, SELF, KC>(g, U, a_self, c_hop, p_out, in + off,
                                                  self != nullptr ? self + off : nullptr, out + off,
                                                  aux != nullptr ? aux + off : nullptr, live, blk % ntile, blk / ntile,
-                                                 tc_len, slot, (size_t)nblk);
+                                                 tc_len, blocked, slot, (size_t)nblk);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -106,11 +106,11 @@ int eo_blocks(const Geo& g, int tc) { return (((g.L3 >> 1) + kEoNT - 1) / kEoNT)
 template <typename R, int DAG, bool SELF, int KC>
 void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
                    const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                   int remap, double* partial, const ColState* st) {
+                   int remap, int blocked, double* partial, const ColState* st) {
     const dim3 block(kEoNT);
 #define DD_EO_CASE(E)                                                                                            \
     hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF, KC>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, \
-                       self, out, aux, ncol, tc, remap, partial, st)
+                       self, out, aux, ncol, tc, remap, blocked, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_EO_CASE(EPI_DOT_AUX); break;
@@ -133,37 +133,38 @@ bool eo_kc_ok(int kc, int ncol) {
 template <typename R, int D, bool SF>
 void launch_eo_kc(hipStream_t s, int kc, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop,
                   int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                  int remap, double* partial, const ColState* st) {
+                  int remap, int blocked, double* partial, const ColState* st) {
     if constexpr (sizeof(R) == 4) {
         if (kc == 4) {
             launch_eo_epi<R, D, SF, 4>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap,
-                                       partial, st);
+                                       blocked, partial, st);
             return;
         }
         if (kc == 2) {
             launch_eo_epi<R, D, SF, 2>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap,
-                                       partial, st);
+                                       blocked, partial, st);
             return;
         }
     }
-    launch_eo_epi<R, D, SF, 1>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, partial,
-                               st);
+    launch_eo_epi<R, D, SF, 1>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, blocked,
+                               partial, st);
 }
 
 // out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
 // time chunks of tc slices, kc columns per thread (eo_kc_ok), workgroups
-// optionally in XCD-contiguous ranges
+// optionally in XCD-contiguous ranges, tiles as rows or bricks (pair_site)
 template <typename R>
 void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, double c_hop, int p_out, int dag,
                    int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                   int kc, int remap, double* partial, const ColState* st) {
+                   int kc, int remap, int blocked, double* partial, const ColState* st) {
     if (!eo_kc_ok<R>(kc, ncol)) kc = 1;
+    if (g.L % 4 != 0) blocked = 0;
     const dim3 grid((unsigned)(eo_blocks(g, tc) * (ncol / kc)));
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_EO_LAUNCH(D, SF)                                                                                           \
     launch_eo_kc<R, D, SF>(c->stream, kc, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, tc, \
-                           remap, partial, st)
+                           remap, blocked, partial, st)
     const bool sf = self != nullptr && a_self != 0;
     if (dag) {
         if (sf) DD_EO_LAUNCH(1, true);
@@ -199,15 +200,15 @@ struct EOSystem : System {
     cpx<double>* tmp64 = nullptr;
     cpx<float>* tmp32 = nullptr;
     // launch shape of the half-hop sweep per kind (0: FP64, 1: FP32): chunk length, XCD remap,
-    // columns per thread
+    // columns per thread, tile shape
     StencilSched sh[2];
     template <typename R>
     void schur(const cpx<R>* UR, cpx<R>* tmp, const StencilSched& sc, int d, int epi, const cpx<R>* in, cpx<R>* out,
                const cpx<R>* aux, double* partial, const ColState* st) {
         launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, sc.tc, sc.kc, sc.remap,
-                         partial, st);
-        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, sc.tc, sc.kc, sc.remap, partial,
-                         st);
+                         sc.blocked, partial, st);
+        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, sc.tc, sc.kc, sc.remap,
+                         sc.blocked, partial, st);
     }
     void apply64(int d, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux, double* partial,
                  const ColState* st) override {
@@ -222,8 +223,9 @@ struct EOSystem : System {
 // Launch shape of the half-hop sweep for one precision: timed on the Schur
 // operator of this geometry and column count at first use (chunks of 1, 2,
 // 4, 8 slices, workgroups in hardware order or XCD-contiguous ranges, 1, 2 or
-// 4 columns per thread where allowed), cached in the context like the stencil
-// shapes; small fields take 4 slices, no remap, one column, untimed.
+// 4 columns per thread where allowed, row or brick tiles), cached in the
+// context like the stencil shapes; small fields take 4 slices, no remap, one
+// column, row tiles, untimed.
 template <typename R>
 StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, const cpx<R>* in, cpx<R>* out) {
     const Geo& g = S.g;
@@ -244,26 +246,28 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, cons
             float best_ms = 1e30f;
             for (int t : {1, 2, 4, 8})
                 for (int rm = 0; rm < 2; rm++)
-                    for (int kc : {1, 2, 4}) {
-                        if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol)) continue;
-                        StencilSched sc = best;
-                        sc.tc = t;
-                        sc.remap = rm;
-                        sc.kc = kc;
-                        for (int w = 0; w < 2; w++)
-                            S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
-                        (void)hipEventRecord(a, c->stream);
-                        for (int r = 0; r < 3; r++)
-                            S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
-                        (void)hipEventRecord(b, c->stream);
-                        (void)hipEventSynchronize(b);
-                        float ms = 0;
-                        (void)hipEventElapsedTime(&ms, a, b);
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            best = sc;
+                    for (int kc : {1, 2, 4})
+                        for (int bl = 0; bl < 2; bl++) {
+                            if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol) || (bl && g.L % 4 != 0)) continue;
+                            StencilSched sc = best;
+                            sc.tc = t;
+                            sc.remap = rm;
+                            sc.kc = kc;
+                            sc.blocked = bl;
+                            for (int w = 0; w < 2; w++)
+                                S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                            (void)hipEventRecord(a, c->stream);
+                            for (int r = 0; r < 3; r++)
+                                S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                            (void)hipEventRecord(b, c->stream);
+                            (void)hipEventSynchronize(b);
+                            float ms = 0;
+                            (void)hipEventElapsedTime(&ms, a, b);
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                best = sc;
+                            }
                         }
-                    }
             c->timing = saved;
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
@@ -302,7 +306,7 @@ void launch_eo_merge(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* ev, c
 void launch_eo_hop64(dd_ctx* c, const Geo& g, const cpx<double>* Ueo, double a_self, double c_hop, int p_out, int dag,
                      const cpx<double>* in, const cpx<double>* self, cpx<double>* out, int ncol) {
     launch_eo_hop<double>(c, g, Ueo, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol,
-                          std::min(4, g.nt), 1, 0, nullptr, nullptr);
+                          std::min(4, g.nt), 1, 0, 0, nullptr, nullptr);
 }
 
 dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol, const cpx<double>* b,

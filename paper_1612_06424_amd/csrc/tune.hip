@@ -92,12 +92,13 @@ void tune_cache_load(dd_ctx* c) {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // key nt tc remap [kc]
+        // key nt tc remap [kc [blocked]]
         std::istringstream in(line);
         std::string key;
         StencilSched sc;
         if (!(in >> key >> sc.nt >> sc.tc >> sc.remap)) continue;
         if (!(in >> sc.kc)) sc.kc = 1;
+        if (!(in >> sc.blocked)) sc.blocked = 0;
         c->sched[key] = sc;
     }
 }
@@ -107,7 +108,7 @@ void tune_cache_store(dd_ctx* c, const std::string& key, const StencilSched& sc)
     const char* path = std::getenv("DD_TUNE_CACHE");
     if (path == nullptr || *path == 0) return;
     std::ofstream f(path, std::ios::app);
-    f << key << " " << sc.nt << " " << sc.tc << " " << sc.remap << " " << sc.kc << "\n";
+    f << key << " " << sc.nt << " " << sc.tc << " " << sc.remap << " " << sc.kc << " " << sc.blocked << "\n";
 }
 
 StencilSched stencil_sched(dd_ctx* c, const Geo& g, int kind, int ncol) {

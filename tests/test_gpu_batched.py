@@ -103,8 +103,8 @@ def test_batched_repeatable_and_matches_single(batch):
 @pytest.mark.parametrize("solver", [0, 1])
 def test_batched_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     """The XCD remap of the batched half hop gives bitwise the same mixed
-    solution; columns per workgroup and the chunk length change the rounding
-    only (agreement to 1e-8, iteration counts within a few).  Columns of a
+    solution; columns per workgroup, the chunk length and the tile shape change
+    the rounding only (agreement to 1e-8, iteration counts within a few).  Columns of a
     domain stop at different iterations, so stopped and running columns share
     workgroups."""
     dd = lib()
@@ -113,9 +113,10 @@ def test_batched_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     sig = "".join(f":{T}x{L}x{ncol}b{bc}" for (T, L, bc, _, ncol, _) in KC_BATCH)
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
     results, its = [], []
-    for tc, remap, kc in [(2, 0, 1), (2, 1, 1), (2, 0, 2), (2, 1, 4), (4, 1, 2)]:
-        path = tmp_path / f"shapes_{tc}_{remap}_{kc}.txt"
-        path.write_text(f"beo:0{sig} 256 {tc} {remap} 1\nbeo:1{sig} 256 {tc} {remap} {kc}\n")
+    for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 4, 0), (4, 1, 2, 0), (2, 0, 1, 1),
+                              (4, 1, 2, 1)]:
+        path = tmp_path / f"shapes_{tc}_{remap}_{kc}_{bl}.txt"
+        path.write_text(f"beo:0{sig} 256 {tc} {remap} 1 {bl}\nbeo:1{sig} 256 {tc} {remap} {kc} {bl}\n")
         monkeypatch.setenv("DD_TUNE_CACHE", str(path))
         ctx = dd.Context(8, 4, 0)
         stats = dd.block_solve_batched(ctx, items, p)

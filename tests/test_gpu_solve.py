@@ -202,8 +202,8 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     """The XCD remap of the half hop only moves work between workgroups: mixed
     solves give bitwise the same solution.  Columns per thread (the kernel is
     compiled once per count, and the compiler may contract multiply-adds
-    differently in each) and the chunk length (it regroups the partial sums)
-    change the rounding only: the solutions agree to 1e-8 with the same
+    differently in each), the chunk length and the tile shape (both regroup the
+    partial sums) change the rounding only: the solutions agree to 1e-8 with the same
     iteration counts within a few.  Gaussian and point sources stop at
     different iterations, so stopped columns share workgroups with running
     ones, whose launches must leave the stopped columns' vectors as they were
@@ -221,9 +221,10 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
     tail = f"12:{L}:{T}:{dom[1]}:0"
     xs, its = [], []
-    for tc, remap, kc in [(2, 0, 1), (2, 1, 1), (2, 0, 2), (2, 1, 4), (4, 1, 2)]:
-        path = tmp_path / f"shapes_{tc}_{remap}_{kc}.txt"
-        path.write_text(f"eo:0:{tail} 256 {tc} {remap} 1\neo:1:{tail} 256 {tc} {remap} {kc}\n")
+    for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 4, 0), (4, 1, 2, 0), (2, 0, 1, 1),
+                              (4, 1, 2, 1)]:
+        path = tmp_path / f"shapes_{tc}_{remap}_{kc}_{bl}.txt"
+        path.write_text(f"eo:0:{tail} 256 {tc} {remap} 1 {bl}\neo:1:{tail} 256 {tc} {remap} {kc} {bl}\n")
         monkeypatch.setenv("DD_TUNE_CACHE", str(path))
         ctx = dd.Context(T, L, bc)
         x, stats = dd.block_solve(ctx, Ud, kappa, bd, dom, p)
