@@ -15,7 +15,7 @@
 namespace dd {
 
 constexpr int kBlock = 256;   // threads per workgroup for site-parallel kernels
-constexpr int kElems = 4;     // elements per thread of the solver vector kernels
+constexpr int kElems = 8;     // elements per thread of the solver vector kernels
 
 // Minimum resident waves per SIMD asked of the stencil kernels (bounds their
 // register use): [0] FP64, [1] FP32, for the time-sweep and the half-hop kernels.
