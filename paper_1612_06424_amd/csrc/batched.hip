@@ -71,6 +71,7 @@ __global__ __launch_bounds__(NT) void k_bdslash(const BDom* __restrict__ doms, i
 struct BEODom {
     Geo g;
     const void* Ueo;   // its checkerboard-ordered links, cpx<R>
+    const void* Ueo12; // the same links as two rows each (FP32 batches whose links are SU(3)), or null
     double mass;       // 1 / (2 kappa)
     long long hoff;    // element offset of its column 0 in the half-field work vectors
     int ncol, seg0, blk0;
@@ -85,8 +86,9 @@ static_assert(sizeof(BEODom) % 8 == 0, "descriptor layout must be the same on ho
 constexpr int kBeoNT = 256;
 
 // SCHUR = false: out = H_oe in (odd sites); SCHUR = true: out = m self - H_eo in / (4m) (even sites).
-// A workgroup serves KC columns of its domain (every domain's ncol is a multiple of KC).
-template <typename R, int DAG, int EPI, bool SCHUR, int KC>
+// A workgroup serves KC columns of its domain (every domain's ncol is a multiple of KC);
+// REC: the links are read as two rows each (Ueo12, KC > 1 only).
+template <typename R, int DAG, int EPI, bool SCHUR, int KC, bool REC>
 __global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ doms, int ndom,
                                                    const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
                                                    cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
@@ -119,20 +121,21 @@ __global__ __launch_bounds__(kBeoNT) void k_beo_hop(const BEODom* __restrict__ d
                                                   aux != nullptr ? aux + off : nullptr, blk % d.ntile, blk / d.ntile,
                                                   d.tc, d.blocked, slot);
     else
-        eo_sweep_cols<R, DAG, EPI, kBeoNT, SCHUR, KC>(g, (const cpx<R>*)d.Ueo, a_self, c_hop, SCHUR ? 0 : 1,
+        eo_sweep_cols<R, DAG, EPI, kBeoNT, SCHUR, KC, REC>(g, (const cpx<R>*)(REC ? d.Ueo12 : d.Ueo), a_self, c_hop,
+                                                           SCHUR ? 0 : 1,
                                                       in + off, self != nullptr ? self + off : nullptr, out + off,
                                                       aux != nullptr ? aux + off : nullptr, live, blk % d.ntile,
                                                       blk / d.ntile, d.tc, d.blocked, slot, (size_t)d.nblk);
 }
 
-template <typename R, int DAG, bool SCHUR, int KC>
+template <typename R, int DAG, bool SCHUR, int KC, bool REC>
 void launch_beo_epi(hipStream_t s, int epi, unsigned nblk, const BEODom* doms, int ndom, const cpx<R>* in,
                     const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int remap, double* partial,
                     const ColState* st) {
     const dim3 grid(nblk), block(kBeoNT);
 #define DD_BEO_CASE(E)                                                                                             \
-    hipLaunchKernelGGL((k_beo_hop<R, DAG, E, SCHUR, KC>), grid, block, 0, s, doms, ndom, in, self, out, aux, remap, \
-                       partial, st)
+    hipLaunchKernelGGL((k_beo_hop<R, DAG, E, SCHUR, KC, REC>), grid, block, 0, s, doms, ndom, in, self, out, aux, \
+                       remap, partial, st)
     switch (epi) {
         case EPI_STORE: DD_BEO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_BEO_CASE(EPI_DOT_AUX); break;
@@ -143,21 +146,23 @@ void launch_beo_epi(hipStream_t s, int epi, unsigned nblk, const BEODom* doms, i
 #undef DD_BEO_CASE
 }
 
-// kc columns per workgroup: 1 in FP64, 1, 2 or 4 in FP32 (as for the single-system half hop)
+// kc columns per workgroup: 1 in FP64, 1 or 2 in FP32 (as for the single-system half hop);
+// rec: kc > 1 launches read the two-row links
 template <typename R, int DAG, bool SCHUR>
-void launch_beo(hipStream_t s, int kc, int epi, unsigned nblk, const BEODom* doms, int ndom, const cpx<R>* in,
-                const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int remap, double* partial, const ColState* st) {
+void launch_beo(hipStream_t s, int kc, bool rec, int epi, unsigned nblk, const BEODom* doms, int ndom,
+                const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int remap, double* partial,
+                const ColState* st) {
+#define DD_BEO_KC(K, REC) \
+    launch_beo_epi<R, DAG, SCHUR, K, REC>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st)
     if constexpr (sizeof(R) == 4) {
-        if (kc == 4) {
-            launch_beo_epi<R, DAG, SCHUR, 4>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st);
-            return;
-        }
         if (kc == 2) {
-            launch_beo_epi<R, DAG, SCHUR, 2>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st);
+            if (rec) DD_BEO_KC(2, true);
+            else DD_BEO_KC(2, false);
             return;
         }
     }
-    launch_beo_epi<R, DAG, SCHUR, 1>(s, epi, nblk, doms, ndom, in, self, out, aux, remap, partial, st);
+    DD_BEO_KC(1, false);
+#undef DD_BEO_KC
 }
 
 template <typename R, int DAG, int NT>
@@ -302,6 +307,7 @@ struct BatchEOSystem : System {
     unsigned nblk64 = 0, nblk32 = 0;   // workgroups of a launch per precision
     int remap[2] = {0, 0};             // XCD-contiguous workgroup ranges per precision
     int kc[2] = {1, 1};                // columns per workgroup per precision
+    bool rec32 = false;                // FP32 descriptors carry two-row links
     cpx<double>* tmp64 = nullptr;
     cpx<float>* tmp32 = nullptr;
 
@@ -311,31 +317,36 @@ struct BatchEOSystem : System {
         const unsigned nblk = this->nblk != 0 ? this->nblk : (sizeof(R) == 8 ? nblk64 : nblk32);
         const int rm = remap[sizeof(R) == 8 ? 0 : 1];
         const int k = kc[sizeof(R) == 8 ? 0 : 1];
+        const bool rec = sizeof(R) == 4 && rec32 && k > 1;
         for (int half = 0; half < 2; half++) {
             const int e = half ? epi : EPI_STORE;
             hipEvent_t ev = nullptr;
             if (c->timing) timing_begin(c, &ev);
             if (half == 0) {
                 if (dag)
-                    launch_beo<R, 1, false>(c->stream, k, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, rm, partial, st);
+                    launch_beo<R, 1, false>(c->stream, k, rec, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, rm,
+                                            partial, st);
                 else
-                    launch_beo<R, 0, false>(c->stream, k, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, rm, partial, st);
+                    launch_beo<R, 0, false>(c->stream, k, rec, e, nblk, dv, ndom, in, nullptr, tmp, nullptr, rm,
+                                            partial, st);
             } else {
-                if (dag) launch_beo<R, 1, true>(c->stream, k, e, nblk, dv, ndom, tmp, in, out, aux, rm, partial, st);
-                else launch_beo<R, 0, true>(c->stream, k, e, nblk, dv, ndom, tmp, in, out, aux, rm, partial, st);
+                if (dag) launch_beo<R, 1, true>(c->stream, k, rec, e, nblk, dv, ndom, tmp, in, out, aux, rm, partial, st);
+                else launch_beo<R, 0, true>(c->stream, k, rec, e, nblk, dv, ndom, tmp, in, out, aux, rm, partial, st);
             }
             if (c->timing) {
-                // per output half site: input, output (+ self, + aux) spinors; every link of a domain once
+                // per output half site: input, output (+ self, + aux) spinors; every link of a domain
+                // once, as stored (18 or 12 reals)
                 double sc = 0, s = 0;
                 for (const BEODom& d : host) {
                     sc += (double)(d.g.nsite >> 1) * d.ncol;
                     s += (double)(d.g.nsite >> 1);
                 }
                 const double extra = (half ? 24.0 : 0.0) + (e == EPI_DOT_AUX || e == EPI_RESID ? 24.0 : 0.0);
-                const double bytes = ((48.0 + extra) * sc + 144.0 * s) * sizeof(R);
+                const double bytes = ((48.0 + extra) * sc + (rec ? 96.0 : 144.0) * s) * sizeof(R);
                 const std::string name = std::string("k_beo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                          std::to_string(dag ? 1 : 0) + ", " + std::to_string(e) + ", " +
-                                         (half ? "true, " : "false, ") + std::to_string(k) + ">";
+                                         (half ? "true, " : "false, ") + std::to_string(k) +
+                                         (rec ? ", true>" : ", false>");
                 timing_end(c, ev, name, bytes);
             }
         }
@@ -452,22 +463,28 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
                          cpx<double>* xcat, SolveResult* res, std::vector<double>* rel) {
     const int n = (int)its.size();
     dd_status e = DD_OK;
-    std::vector<long long> hoff(n), eoff(n);
-    long long nhalf = 0, nl = 0;
+    std::vector<long long> hoff(n), eoff(n), e12off(n);
+    long long nhalf = 0, nl = 0, nl12 = 0;
     for (int i = 0; i < n; i++) {
         hoff[i] = nhalf;
         eoff[i] = nl;
+        e12off[i] = nl12;
         nhalf += (long long)its[i].ncol * 12 * (its[i].g.nsite >> 1);
         nl += (long long)36 * its[i].g.nsite;
+        nl12 += (long long)24 * its[i].g.nsite;
     }
     const bool mixed = p.prec == DD_MIXED;
     cpx<double>* U64 = (cpx<double>*)workspace(c, W_EO_U64, (size_t)nl * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
     cpx<float>* U32 = nullptr;
+    cpx<float>* U32c = nullptr;  // two rows per link, used while every domain's links are SU(3)
     if (mixed) {
         U32 = (cpx<float>*)workspace(c, W_U32, (size_t)nl * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
+        U32c = (cpx<float>*)workspace(c, W_U32C, (size_t)nl12 * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
     }
+    bool su3_all = mixed;
     cpx<double>* bb = (cpx<double>*)workspace(c, W_EO_B, 2 * (size_t)nhalf * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
     cpx<double>* xx = (cpx<double>*)workspace(c, W_EO_X, 2 * (size_t)nhalf * sizeof(cpx<double>), &e);
@@ -479,7 +496,13 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
         const Item& it = its[i];
         const double m = 1.0 / (2.0 * it.kappa);
         launch_links_eo<double>(c, it.g, it.U64, U64 + eoff[i]);
-        if (mixed) launch_links_eo<float>(c, it.g, it.U64, U32 + eoff[i]);
+        if (mixed) {
+            launch_links_eo<float>(c, it.g, it.U64, U32 + eoff[i]);
+            bool su3 = false;
+            e = links_eo12(c, it.g, it.U64, U32c + e12off[i], &su3);
+            if (e != DD_OK) return e;
+            su3_all = su3_all && su3;
+        }
         launch_eo_split(c, it.g, it.ncol, bcat + it.voff, b_e + hoff[i], b_o + hoff[i]);
         // b_e' = b_e + (1/(2m)) H_eo b_o
         launch_eo_hop64(c, it.g, U64 + eoff[i], 1.0, 0.5 / m, 0, 0, b_o + hoff[i], b_e + hoff[i], bhat + hoff[i],
@@ -493,6 +516,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
     S.nelem = (size_t)nhalf;
     S.graph = true;
     S.has32 = mixed;
+    S.rec32 = su3_all;
     S.tmp64 = (cpx<double>*)workspace(c, W_EO_T64, (size_t)nhalf * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
     if (mixed) {
@@ -510,6 +534,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             std::memset(&d, 0, sizeof(d));
             d.g = it.g;
             d.Ueo = kind == 0 ? (const void*)(U64 + eoff[i]) : (const void*)(U32 + eoff[i]);
+            d.Ueo12 = kind == 1 && su3_all ? (const void*)(U32c + e12off[i]) : nullptr;
             d.mass = 1.0 / (2.0 * it.kappa);
             d.hoff = hoff[i];
             d.ncol = it.ncol;
@@ -550,10 +575,10 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
     for (int kind = 0; kind < (mixed ? 2 : 1); kind++) {
         const std::string key = "beo:" + std::to_string(kind) + sig;
         int tc = 4, rmap = 0, kcb = 1, blk = 0;
-        // columns per workgroup: FP32 may share link loads between 2 or 4 columns of a domain
+        // columns per workgroup: FP32 may share link loads between 2 columns of a domain
         auto kc_ok = [&](int kc) {
             if (kc == 1) return true;
-            if (kind == 0 || (kc != 2 && kc != 4)) return false;
+            if (kind == 0 || kc != 2) return false;
             for (const Item& it : its)
                 if (it.ncol % kc != 0) return false;
             return true;
@@ -580,7 +605,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
             bool any4 = false;  // some domain can take brick tiles
             for (const Item& it : its) any4 = any4 || it.g.L % 4 == 0;
             for (int t : {1, 2, 4, 8}) {
-                for (int kc : {1, 2, 4}) {
+                for (int kc : {1, 2}) {
                     for (int bl = 0; bl < (any4 ? 2 : 1); bl++) {
                         if (!kc_ok(kc)) continue;
                         S.kc[kind] = kc;

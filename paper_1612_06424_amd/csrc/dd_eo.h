@@ -42,13 +42,33 @@ __device__ __forceinline__ void bload_link(rsrc_t u, uint32_t ls, int sl, cpx<R>
     for (int k = 0; k < 9; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
 }
 
+// The same link from its first two rows (REC: links stored as 12 reals).  An
+// SU(3) matrix is unitary with unit determinant, so its third row is the
+// complex conjugate of the cross product of the first two.
+template <typename R, bool REC>
+__device__ __forceinline__ void bload_link_r(rsrc_t u, uint32_t ls, int sl, cpx<R> (&w)[9]) {
+    if constexpr (!REC) {
+        bload_link<R>(u, ls, sl, w);
+    } else {
+        const uint32_t vo = (uint32_t)sl * (uint32_t)sizeof(cpx<R>);
+#pragma unroll
+        for (int k = 0; k < 6; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
+        const cpx<R> c6 = w[1] * w[5] - w[2] * w[4];
+        const cpx<R> c7 = w[2] * w[3] - w[0] * w[5];
+        const cpx<R> c8 = w[0] * w[4] - w[1] * w[3];
+        w[6] = mk<R>(c6.re, -c6.im);
+        w[7] = mk<R>(c7.re, -c7.im);
+        w[8] = mk<R>(c8.re, -c8.im);
+    }
+}
+
 // One spatial hop for KC columns: the link is loaded once and transports the
 // projected neighbour of every column.
-template <typename R, int MU, int SGN, bool BWD, int KC>
+template <typename R, int MU, int SGN, bool BWD, int KC, bool REC>
 __device__ __forceinline__ void bhop_cols(cpx<R> (&a)[KC][12], rsrc_t f, uint32_t cs, uint32_t fs, int nb, rsrc_t u,
                                           uint32_t ls, int sl) {
     cpx<R> w[9];
-    bload_link<R>(u, ls, sl, w);
+    bload_link_r<R, REC>(u, ls, sl, w);
 #pragma unroll
     for (int k = 0; k < KC; k++) {
         cpx<R> p[12];
@@ -262,8 +282,9 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
 // the sums of column k go to slot + 3 k slot_col.  Column k's output is
 // written only if bit k of live is set (a stopped column keeps its vectors):
 // its stores go through a buffer resource of size 0 otherwise, which drops
-// them without a branch.
-template <typename R, int DAG, int EPI, int NT, bool SELF, int KC>
+// them without a branch.  REC: Ueo holds only the first two rows of every link
+// (Ueo12[mu][k < 6][parity][nsite / 2]) and the third is rebuilt (bload_link_r).
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC>
 __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
                                               int p_out, const cpx<R>* __restrict__ in,
                                               const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
@@ -276,7 +297,8 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
     const uint32_t cs = (uint32_t)nh * CB;
     const uint32_t fs = 12u * cs;  // column stride (bytes)
     const uint32_t ls = 2u * (uint32_t)nh * CB;
-    const uint32_t ubytes = 17u * (uint32_t)nh * CB;
+    constexpr int NROW = REC ? 6 : 9;  // stored rows of a link
+    const uint32_t ubytes = (uint32_t)(2 * NROW - 1) * (uint32_t)nh * CB;
     constexpr int FW = DAG ? +1 : -1;
     constexpr int BW = -FW;
     constexpr bool has_self = SELF || EPI == EPI_TS;
@@ -305,8 +327,8 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
         rsrc_t uf[4], ub[4];
 #pragma unroll
         for (int mu = 0; mu < 4; mu++) {
-            uf[mu] = make_rsrc(Ueo + (size_t)(mu * 18 + p_out) * nh, ubytes);
-            ub[mu] = make_rsrc(Ueo + (size_t)(mu * 18 + 1 - p_out) * nh, ubytes);
+            uf[mu] = make_rsrc(Ueo + (size_t)(mu * 2 * NROW + p_out) * nh, ubytes);
+            ub[mu] = make_rsrc(Ueo + (size_t)(mu * 2 * NROW + 1 - p_out) * nh, ubytes);
         }
         const int dyp = (y == L - 1) ? -(L - 1) * L : L, dym = (y == 0) ? (L - 1) * L : -L;
         const int dzp = (z == L - 1) ? -(L - 1) * L2 : L2, dzm = (z == 0) ? (L - 1) * L2 : -L2;
@@ -348,7 +370,7 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
                 const R ph = (tg == 0) ? R(g.bc) : R(1);
                 if (ph != R(0)) {
                     cpx<R> w[9];
-                    bload_link<R>(ub[0], ls, ((tl > 0 ? tl - 1 : nt - 1) * L3 + sp) >> 1, w);
+                    bload_link_r<R, REC>(ub[0], ls, ((tl > 0 ? tl - 1 : nt - 1) * L3 + sp) >> 1, w);
 #pragma unroll
                     for (int k = 0; k < KC; k++) {
                         cpx<R> t[6];
@@ -371,7 +393,7 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
                 for (int k = 0; k < KC; k++) {
                     cpx<R> p[12];
                     bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, (endt ? sp : s + L3) >> 1, p);
-                    if (k == 0 && ph != R(0)) bload_link<R>(uf[0], ls, h, w);
+                    if (k == 0 && ph != R(0)) bload_link_r<R, REC>(uf[0], ls, h, w);
                     if (ph != R(0)) {
                         cpx<R> hf[6];
                         project<R, 0, FW>(p, hf);
@@ -383,12 +405,12 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
                 }
             }
             const int dxp = (x == L - 1) ? -(L - 1) : 1, dxm = (x == 0) ? (L - 1) : -1;
-            bhop_cols<R, 1, FW, false, KC>(a, rf, cs, fs, (s + dxp) >> 1, uf[1], ls, h);
-            bhop_cols<R, 1, BW, true, KC>(a, rf, cs, fs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1);
-            bhop_cols<R, 2, FW, false, KC>(a, rf, cs, fs, (s + dyp) >> 1, uf[2], ls, h);
-            bhop_cols<R, 2, BW, true, KC>(a, rf, cs, fs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1);
-            bhop_cols<R, 3, FW, false, KC>(a, rf, cs, fs, (s + dzp) >> 1, uf[3], ls, h);
-            bhop_cols<R, 3, BW, true, KC>(a, rf, cs, fs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1);
+            bhop_cols<R, 1, FW, false, KC, REC>(a, rf, cs, fs, (s + dxp) >> 1, uf[1], ls, h);
+            bhop_cols<R, 1, BW, true, KC, REC>(a, rf, cs, fs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1);
+            bhop_cols<R, 2, FW, false, KC, REC>(a, rf, cs, fs, (s + dyp) >> 1, uf[2], ls, h);
+            bhop_cols<R, 2, BW, true, KC, REC>(a, rf, cs, fs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1);
+            bhop_cols<R, 3, FW, false, KC, REC>(a, rf, cs, fs, (s + dzp) >> 1, uf[3], ls, h);
+            bhop_cols<R, 3, BW, true, KC, REC>(a, rf, cs, fs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1);
 
             const uint32_t vo = (uint32_t)h * CB;
 #pragma unroll

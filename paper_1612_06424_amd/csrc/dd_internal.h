@@ -172,6 +172,7 @@ enum Slot {
     W_PART, W_STATE, W_STATE32, W_DOTS,
     W_AUX0, W_AUX1, W_AUX2, W_AUX3, W_AUX4,
     W_SEGS, W_SEGN, W_EO_B, W_EO_X, W_EO_BHAT, W_EO_T64, W_EO_T32, W_EO_U64, W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
+    W_U32C, W_LDEV,
     W_NSLOTS
 };
 
@@ -334,6 +335,11 @@ dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd
 // Even-odd preconditioned solve of one lattice or slab (evenodd.hip); usable
 // when the lattice is bipartite: L even, and nt even for a whole lattice.
 bool eo_applicable(const Geo& g);
+// FP32 checkerboard links of field g as two rows each (Ueo12[mu][k < 6][parity][nsite / 2]);
+// *su3 tells whether every link's third row is the conjugated cross product of
+// the first two within 1e-6 (so that the two rows determine the link to FP32
+// precision).
+dd_status links_eo12(dd_ctx* c, const Geo& g, const cpx<double>* U, cpx<float>* Ueo12, bool* su3);
 // checkerboard-ordered links of the field g (Ueo[mu][k][parity][nsite/2]) from U[mu][k][V]
 template <typename R>
 void launch_links_eo(dd_ctx* c, const Geo& g, const cpx<double>* U, cpx<R>* Ueo);

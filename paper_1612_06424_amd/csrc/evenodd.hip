@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "dd_eo.h"
 
@@ -21,8 +22,8 @@ namespace {
 
 // Workgroup -> (group of KC columns fastest, tile of NT pairs of a slice, chunk
 // of tc_len slices); partial slot of (col, block) = col * nblk + block.  ncol is
-// a multiple of KC.
-template <typename R, int DAG, int EPI, int NT, bool SELF, int KC>
+// a multiple of KC.  REC: U holds two rows per link (KC > 1 only).
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC>
 __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self,
                                                              R c_hop, int p_out, const cpx<R>* __restrict__ in,
                                                              const cpx<R>* __restrict__ self,
@@ -48,10 +49,10 @@ __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R
                                              aux != nullptr ? aux + off : nullptr, blk % ntile, blk / ntile, tc_len,
                                              blocked, slot);
     else
-        eo_sweep_cols<R, DAG, EPI, NT, SELF, KC>(g, U, a_self, c_hop, p_out, in + off,
-                                                 self != nullptr ? self + off : nullptr, out + off,
-                                                 aux != nullptr ? aux + off : nullptr, live, blk % ntile, blk / ntile,
-                                                 tc_len, blocked, slot, (size_t)nblk);
+        eo_sweep_cols<R, DAG, EPI, NT, SELF, KC, REC>(g, U, a_self, c_hop, p_out, in + off,
+                                                      self != nullptr ? self + off : nullptr, out + off,
+                                                      aux != nullptr ? aux + off : nullptr, live, blk % ntile,
+                                                      blk / ntile, tc_len, blocked, slot, (size_t)nblk);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -98,19 +99,58 @@ __global__ __launch_bounds__(kBlock) void k_links_eo(Geo g, const cpx<double>* _
     }
 }
 
+// Ueo12[mu][k][parity][nsite / 2], k < 6: rows 0 and 1 of every link in FP32;
+// dev[block] = the largest difference (FP64, max norm) between a link's third
+// row and the conjugated cross product of its first two, over the block's
+// sites (NaN if any entry is not finite)
+__global__ __launch_bounds__(kBlock) void k_links_eo12(Geo g, const cpx<double>* __restrict__ U,
+                                                       cpx<float>* __restrict__ Ueo, double* __restrict__ dev) {
+    const int s = (int)(blockIdx.x * kBlock + threadIdx.x);
+    double d = 0;
+    auto worse = [](double a, double b) { return (b > a || b != b) ? b : a; };
+    if (s < g.nsite) {
+        const int tl = s / g.L3, sp = s - tl * g.L3;
+        const int t = g.t0 + tl;
+        const size_t sl = (size_t)(t >= g.T ? t - g.T : t) * g.L3 + sp;
+        const int par = (tl + sp % g.L + (sp / g.L) % g.L + sp / g.L2) & 1;
+        const size_t nh = (size_t)(g.nsite >> 1);
+        for (int mu = 0; mu < 4; mu++) {
+            cpx<double> w[9];
+            for (int k = 0; k < 9; k++) w[k] = U[(size_t)(mu * 9 + k) * g.vlink + sl];
+            for (int k = 0; k < 6; k++)
+                Ueo[((size_t)(mu * 6 + k) * 2 + par) * nh + (size_t)(s >> 1)] = cpx<float>{(float)w[k].re, (float)w[k].im};
+            const cpx<double> c[3] = {w[1] * w[5] - w[2] * w[4], w[2] * w[3] - w[0] * w[5], w[0] * w[4] - w[1] * w[3]};
+            for (int k = 0; k < 3; k++) {
+                d = worse(d, fabs(w[6 + k].re - c[k].re));
+                d = worse(d, fabs(w[6 + k].im + c[k].im));
+            }
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) d = worse(d, __shfl_xor(d, off, kWave));
+    __shared__ double sh[kBlock / kWave];
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int k = 1; k < kBlock / kWave; k++) m = worse(m, sh[k]);
+        dev[blockIdx.x] = m;
+    }
+}
+
 constexpr int kEoNT = 256;
 
 // workgroups per column: tiles of kEoNT pairs per slice x chunks of tc slices
 int eo_blocks(const Geo& g, int tc) { return (((g.L3 >> 1) + kEoNT - 1) / kEoNT) * ((g.nt + tc - 1) / tc); }
 
-template <typename R, int DAG, bool SELF, int KC>
+template <typename R, int DAG, bool SELF, int KC, bool REC>
 void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
                    const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
                    int remap, int blocked, double* partial, const ColState* st) {
     const dim3 block(kEoNT);
 #define DD_EO_CASE(E)                                                                                            \
-    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF, KC>), grid, block, 0, s, g, U, a_self, c_hop, p_out, in, \
-                       self, out, aux, ncol, tc, remap, blocked, partial, st)
+    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF, KC, REC>), grid, block, 0, s, g, U, a_self, c_hop, p_out, \
+                       in, self, out, aux, ncol, tc, remap, blocked, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_EO_CASE(EPI_DOT_AUX); break;
@@ -122,49 +162,52 @@ void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>
 }
 
 // Columns per thread of the half-hop sweep that a launch may use: FP32 shares
-// each link load between up to 4 columns; FP64 already needs the whole
-// register file for one.
+// each link load between 2 columns (221 VGPRs, two waves per SIMD; 4 columns
+// need AGPRs and were never faster); FP64 already needs the whole register
+// file for one.
 template <typename R>
 bool eo_kc_ok(int kc, int ncol) {
     if (sizeof(R) == 8) return kc == 1;
-    return (kc == 1 || kc == 2 || kc == 4) && ncol % kc == 0;
+    return (kc == 1 || kc == 2) && ncol % kc == 0;
 }
 
 template <typename R, int D, bool SF>
-void launch_eo_kc(hipStream_t s, int kc, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop,
-                  int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                  int remap, int blocked, double* partial, const ColState* st) {
+void launch_eo_kc(hipStream_t s, int kc, bool rec, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self,
+                  R c_hop, int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol,
+                  int tc, int remap, int blocked, double* partial, const ColState* st) {
+#define DD_EO_KC(K, REC)                                                                                         \
+    launch_eo_epi<R, D, SF, K, REC>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, \
+                                    blocked, partial, st)
     if constexpr (sizeof(R) == 4) {
-        if (kc == 4) {
-            launch_eo_epi<R, D, SF, 4>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap,
-                                       blocked, partial, st);
-            return;
-        }
         if (kc == 2) {
-            launch_eo_epi<R, D, SF, 2>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap,
-                                       blocked, partial, st);
+            if (rec) DD_EO_KC(2, true);
+            else DD_EO_KC(2, false);
             return;
         }
     }
-    launch_eo_epi<R, D, SF, 1>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, blocked,
-                               partial, st);
+    DD_EO_KC(1, false);
+#undef DD_EO_KC
 }
 
 // out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
 // time chunks of tc slices, kc columns per thread (eo_kc_ok), workgroups
-// optionally in XCD-contiguous ranges, tiles as rows or bricks (pair_site)
+// optionally in XCD-contiguous ranges, tiles as rows or bricks (pair_site).
+// U: the checkerboard links; U12 (nullable): the same links as two rows each,
+// which launches with kc > 1 read instead.
 template <typename R>
-void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, double c_hop, int p_out, int dag,
-                   int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
-                   int kc, int remap, int blocked, double* partial, const ColState* st) {
+void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, double a_self, double c_hop,
+                   int p_out, int dag, int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux,
+                   int ncol, int tc, int kc, int remap, int blocked, double* partial, const ColState* st) {
     if (!eo_kc_ok<R>(kc, ncol)) kc = 1;
     if (g.L % 4 != 0) blocked = 0;
+    const bool rec = U12 != nullptr && kc > 1;
+    if (rec) U = U12;
     const dim3 grid((unsigned)(eo_blocks(g, tc) * (ncol / kc)));
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_EO_LAUNCH(D, SF)                                                                                           \
-    launch_eo_kc<R, D, SF>(c->stream, kc, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, ncol, tc, \
-                           remap, blocked, partial, st)
+    launch_eo_kc<R, D, SF>(c->stream, kc, rec, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, \
+                           ncol, tc, remap, blocked, partial, st)
     const bool sf = self != nullptr && a_self != 0;
     if (dag) {
         if (sf) DD_EO_LAUNCH(1, true);
@@ -176,14 +219,16 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, double a_self, doub
 #undef DD_EO_LAUNCH
     if (c->timing) {
         // per output half site: the input spinor, the output (+ self / aux when read), and the
-        // links: every link of the field is used once by one output site of a given parity
+        // links as stored (18 or 12 reals): every link of the field is used once by one output
+        // site of a given parity
         const double nh = (double)(g.nsite >> 1);
         const double extra = (a_self != 0 || epi == EPI_TS ? 24.0 : 0.0) +
                              (epi == EPI_DOT_AUX || epi == EPI_RESID ? 24.0 : 0.0);
-        const double bytes = nh * ((48.0 + extra) * ncol + 144.0) * sizeof(R);
+        const double bytes = nh * ((48.0 + extra) * ncol + (rec ? 96.0 : 144.0)) * sizeof(R);
         const std::string name = std::string("k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
-                                 std::to_string(kEoNT) + (sf ? ", true, " : ", false, ") + std::to_string(kc) + ">";
+                                 std::to_string(kEoNT) + (sf ? ", true, " : ", false, ") + std::to_string(kc) +
+                                 (rec ? ", true>" : ", false>");
         timing_end(c, ev, name, bytes);
     }
 }
@@ -194,6 +239,7 @@ struct EOSystem : System {
     Geo g{};
     const cpx<double>* U64 = nullptr;  // checkerboard-ordered links of the field (Ueo)
     const cpx<float>* U32 = nullptr;
+    const cpx<float>* U32c = nullptr;  // two rows per link, where the links are SU(3)
     double m = 0;  // 1 / (2 kappa)
     int dag = 0;
     int ncol = 0;
@@ -203,31 +249,32 @@ struct EOSystem : System {
     // columns per thread, tile shape
     StencilSched sh[2];
     template <typename R>
-    void schur(const cpx<R>* UR, cpx<R>* tmp, const StencilSched& sc, int d, int epi, const cpx<R>* in, cpx<R>* out,
-               const cpx<R>* aux, double* partial, const ColState* st) {
-        launch_eo_hop<R>(c, g, UR, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, sc.tc, sc.kc, sc.remap,
-                         sc.blocked, partial, st);
-        launch_eo_hop<R>(c, g, UR, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, sc.tc, sc.kc, sc.remap,
+    void schur(const cpx<R>* UR, const cpx<R>* UR12, cpx<R>* tmp, const StencilSched& sc, int d, int epi,
+               const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, double* partial, const ColState* st) {
+        launch_eo_hop<R>(c, g, UR, UR12, 0.0, 1.0, 1, d, EPI_STORE, in, nullptr, tmp, nullptr, ncol, sc.tc, sc.kc,
+                         sc.remap, sc.blocked, partial, st);
+        launch_eo_hop<R>(c, g, UR, UR12, m, -0.25 / m, 0, d, epi, tmp, in, out, aux, ncol, sc.tc, sc.kc, sc.remap,
                          sc.blocked, partial, st);
     }
     void apply64(int d, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux, double* partial,
                  const ColState* st) override {
-        schur<double>(U64, tmp64, sh[0], d ^ dag, epi, in, out, aux, partial, st);
+        schur<double>(U64, nullptr, tmp64, sh[0], d ^ dag, epi, in, out, aux, partial, st);
     }
     void apply32(int d, int epi, const cpx<float>* in, cpx<float>* out, const cpx<float>* aux, double* partial,
                  const ColState* st) override {
-        schur<float>(U32, tmp32, sh[1], d ^ dag, epi, in, out, aux, partial, st);
+        schur<float>(U32, U32c, tmp32, sh[1], d ^ dag, epi, in, out, aux, partial, st);
     }
 };
 
 // Launch shape of the half-hop sweep for one precision: timed on the Schur
 // operator of this geometry and column count at first use (chunks of 1, 2,
-// 4, 8 slices, workgroups in hardware order or XCD-contiguous ranges, 1, 2 or
-// 4 columns per thread where allowed, row or brick tiles), cached in the
+// 4, 8 slices, workgroups in hardware order or XCD-contiguous ranges, 1 or 2
+// columns per thread where allowed, row or brick tiles), cached in the
 // context like the stencil shapes; small fields take 4 slices, no remap, one
 // column, row tiles, untimed.
 template <typename R>
-StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, const cpx<R>* in, cpx<R>* out) {
+StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, const cpx<R>* UR12, cpx<R>* tmp, const cpx<R>* in,
+                     cpx<R>* out) {
     const Geo& g = S.g;
     const std::string key = std::string("eo:") + (sizeof(R) == 8 ? "0" : "1") + ":" + std::to_string(S.ncol) + ":" +
                             std::to_string(g.L) + ":" + std::to_string(g.T) + ":" + std::to_string(g.nt) + ":" +
@@ -246,7 +293,7 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, cons
             float best_ms = 1e30f;
             for (int t : {1, 2, 4, 8})
                 for (int rm = 0; rm < 2; rm++)
-                    for (int kc : {1, 2, 4})
+                    for (int kc : {1, 2})
                         for (int bl = 0; bl < 2; bl++) {
                             if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol) || (bl && g.L % 4 != 0)) continue;
                             StencilSched sc = best;
@@ -255,10 +302,10 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, cons
                             sc.kc = kc;
                             sc.blocked = bl;
                             for (int w = 0; w < 2; w++)
-                                S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                                S.schur<R>(UR, UR12, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
                             (void)hipEventRecord(a, c->stream);
                             for (int r = 0; r < 3; r++)
-                                S.schur<R>(UR, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                                S.schur<R>(UR, UR12, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
                             (void)hipEventRecord(b, c->stream);
                             (void)hipEventSynchronize(b);
                             float ms = 0;
@@ -284,6 +331,21 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, cpx<R>* tmp, cons
 // same parity when nt is odd, unless time_bc = 0 drops it.
 bool eo_applicable(const Geo& g) { return g.L % 2 == 0 && (!g.whole || g.nt % 2 == 0 || g.bc == 0); }
 
+dd_status links_eo12(dd_ctx* c, const Geo& g, const cpx<double>* U, cpx<float>* Ueo12, bool* su3) {
+    const int nblk = (g.nsite + kBlock - 1) / kBlock;
+    dd_status e = DD_OK;
+    double* dev = (double*)workspace(c, W_LDEV, (size_t)nblk * sizeof(double), &e);
+    if (e != DD_OK) return e;
+    hipLaunchKernelGGL(k_links_eo12, dim3((unsigned)nblk), dim3(kBlock), 0, c->stream, g, U, Ueo12, dev);
+    std::vector<double> h((size_t)nblk);
+    DD_HIP(c, hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    bool ok = true;
+    for (double v : h) ok = ok && v <= 1e-6;
+    *su3 = ok;
+    return DD_OK;
+}
+
 template <typename R>
 void launch_links_eo(dd_ctx* c, const Geo& g, const cpx<double>* U, cpx<R>* Ueo) {
     hipLaunchKernelGGL(k_links_eo<R>, dim3((unsigned)((g.nsite + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, g,
@@ -305,7 +367,7 @@ void launch_eo_merge(dd_ctx* c, const Geo& g, int ncol, const cpx<double>* ev, c
 }
 void launch_eo_hop64(dd_ctx* c, const Geo& g, const cpx<double>* Ueo, double a_self, double c_hop, int p_out, int dag,
                      const cpx<double>* in, const cpx<double>* self, cpx<double>* out, int ncol) {
-    launch_eo_hop<double>(c, g, Ueo, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol,
+    launch_eo_hop<double>(c, g, Ueo, nullptr, a_self, c_hop, p_out, dag, EPI_STORE, in, self, out, nullptr, ncol,
                           std::min(4, g.nt), 1, 0, 0, nullptr, nullptr);
 }
 
@@ -345,18 +407,24 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
         if (e != DD_OK) return e;
         hipLaunchKernelGGL(k_links_eo<float>, dim3(glink), dim3(kBlock), 0, c->stream, g, U, U32);
         S.U32 = U32;
+        cpx<float>* U32c = (cpx<float>*)workspace(c, W_U32C, (size_t)24 * g.nsite * sizeof(cpx<float>), &e);
+        if (e != DD_OK) return e;
+        bool su3 = false;
+        e = links_eo12(c, g, U, U32c, &su3);
+        if (e != DD_OK) return e;
+        if (su3) S.U32c = U32c;
         S.tmp32 = (cpx<float>*)workspace(c, W_EO_T32, nhalf * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
         S.has32 = true;
     }
     // launch shapes (tuned on two half-field work vectors whose contents do not matter)
-    S.sh[0] = eo_tune<double>(c, S, Ueo64, S.tmp64, bhat, xx);
+    S.sh[0] = eo_tune<double>(c, S, Ueo64, nullptr, S.tmp64, bhat, xx);
     if (S.has32) {
         cpx<float>* a32 = (cpx<float>*)workspace(c, W_R32, nhalf * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
         cpx<float>* b32 = (cpx<float>*)workspace(c, W_RH32, nhalf * sizeof(cpx<float>), &e);
         if (e != DD_OK) return e;
-        S.sh[1] = eo_tune<float>(c, S, S.U32, S.tmp32, a32, b32);
+        S.sh[1] = eo_tune<float>(c, S, S.U32, S.U32c, S.tmp32, a32, b32);
     }
     SegLayout lay;
     const int n = (int)(12 * nh);

@@ -113,7 +113,7 @@ def test_batched_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     sig = "".join(f":{T}x{L}x{ncol}b{bc}" for (T, L, bc, _, ncol, _) in KC_BATCH)
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
     results, its = [], []
-    for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 4, 0), (4, 1, 2, 0), (2, 0, 1, 1),
+    for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 2, 0), (4, 1, 2, 0), (2, 0, 1, 1),
                               (4, 1, 2, 1)]:
         path = tmp_path / f"shapes_{tc}_{remap}_{kc}_{bl}.txt"
         path.write_text(f"beo:0{sig} 256 {tc} {remap} 1 {bl}\nbeo:1{sig} 256 {tc} {remap} {kc} {bl}\n")

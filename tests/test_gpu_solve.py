@@ -221,7 +221,7 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
     tail = f"12:{L}:{T}:{dom[1]}:0"
     xs, its = [], []
-    for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 4, 0), (4, 1, 2, 0), (2, 0, 1, 1),
+    for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 2, 0), (4, 1, 2, 0), (2, 0, 1, 1),
                               (4, 1, 2, 1)]:
         path = tmp_path / f"shapes_{tc}_{remap}_{kc}_{bl}.txt"
         path.write_text(f"eo:0:{tail} 256 {tc} {remap} 1 {bl}\neo:1:{tail} 256 {tc} {remap} {kc} {bl}\n")
@@ -235,6 +235,36 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     for x, it in zip(xs[2:], its[2:]):
         assert relerr(dd.unpack_field(x), dd.unpack_field(xs[0])) < 1e-8
         assert abs(it - its[0]) <= 4
+
+
+def test_two_row_links_only_for_su3(tmp_path, monkeypatch):
+    """FP32 half hops with two columns per thread read every link as its first
+    two rows (the third rebuilt as their conjugated cross product) only when the
+    links are SU(3); links scaled by 1.05 are not, keep all nine entries, and
+    both mixed solves reach the oracle's solution."""
+    dd = lib()
+    step("two-row FP32 links")
+    T, L, bc, dom, kappa = 16, 8, -1, (4, 8), 0.13
+    U = random_links(T, L, 0.3, 2800)
+    b = gaussian_field(dom[1] * L ** 3, 4, 2801)
+    tail = f"4:{L}:{T}:{dom[1]}:0"
+    path = tmp_path / "shapes.txt"
+    path.write_text(f"eo:0:{tail} 256 2 0 1 0\neo:1:{tail} 256 2 0 2 0\n")
+    monkeypatch.setenv("DD_TUNE_CACHE", str(path))
+    for scale in (1.0, 1.05):
+        Us = U * scale
+        ctx = dd.Context(T, L, bc)
+        dd.set_kernel_timing(ctx, True)
+        x, st = dd.block_solve(ctx, dd.pack_links(Us), kappa, dd.pack_field(b), dom,
+                               dd.solver_params(tol=1e-10, prec=dd.DD_MIXED))
+        assert max(st["true_rel_resid"]) <= 1e-10
+        names = list(dd.kernel_timing(ctx))
+        two_row = [n for n in names if n.startswith("k_eo_hop<float") and n.endswith(", 2, true>")]
+        full = [n for n in names if n.startswith("k_eo_hop<float") and n.endswith(", 2, false>")]
+        assert (len(two_row) > 0, len(full) > 0) == ((True, False) if scale == 1.0 else (False, True)), names
+        ref, _, _, ost = O.solve(Us, kappa, T, L, bc, b, dom=dom, tol=1e-13, method=1)
+        assert ost == 0
+        assert relerr(dd.unpack_field(x), ref) < 1e-6
 
 
 def test_even_odd_adjoint_and_fallback():
