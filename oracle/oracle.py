@@ -203,16 +203,27 @@ def domain_distances(T, bc, domains):
     return d
 
 
+def extended_domain(T, dom, overlap):
+    """The slab dom = (t0, nt) grown by `overlap` time slices on both sides (mod T):
+    Gamma-bar = Gamma plus the boundary layer of thickness Delta of Sec. 3.2."""
+    t0, nt = dom
+    return ((t0 - overlap) % T, nt + 2 * overlap)
+
+
 def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100000,
-                          method=0, eta=None):
+                          method=0, eta=None, overlap=0):
     """Factorised point-to-all propagator across time-slab domains.
 
     domains: list of (t0, nt) partitioning [0, T); the source must lie in
     domains[0].  With psi_0 = D_L0^-1 eta (first case, Eq. 13, factorised
     term) and, outward by block distance d,
-        psi_k = - D_Lk^-1 sum_{j : d(j) = d(k) - 1} D_{Lk,Lj} psi_j
-    (second case, Eq. 14 with the overlap region empty, iterated over the
-    chain of regions), the result is S_fact = sum_k psi_k.  Returns
+        psi_k = - D_Lk^-1 sum_{j : d(j) = d(k) - 1} D_{Lk,Lj} h_j
+    (second case, Eq. 14, iterated over the chain of regions), the result is
+    S_fact = sum_k psi_k.  The field h_j that crosses the frontier is the
+    solution of domain j's equation (same source) on its extension Lj-bar =
+    Lj grown by `overlap` slices on both time sides, restricted to Lj: for two
+    domains h_0 = [D_Gamma-bar^-1 eta] on Gamma, i.e. Eq. 14 with an overlap
+    region of thickness Delta = overlap (h_j = psi_j for Delta = 0).  Returns
     (S_fact (12, V, 12), per-domain solve info).
     """
     U = _links(U)
@@ -228,7 +239,7 @@ def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100
     if any(dd is None for dd in dist):
         raise ValueError("domains are not connected")
     order = sorted(range(len(domains)), key=lambda k: dist[k])
-    psi = {}
+    hop = {}
     info = {}
     S = np.zeros((eta.shape[0], V, 12), dtype=np.complex128)
     for k in order:
@@ -239,11 +250,21 @@ def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100
             rhs = np.zeros((eta.shape[0], dk[1] * L3, 12), dtype=np.complex128)
             for j in range(len(domains)):
                 if dist[j] == dist[k] - 1:
-                    rhs -= block_apply(U, kappa, T, L, bc, dk, domains[j], psi[j])
+                    rhs -= block_apply(U, kappa, T, L, bc, dk, domains[j], hop[j])
         x, it, rr, st = solve(U, kappa, T, L, bc, rhs, dom=dk, tol=tol, maxit=maxit, method=method)
-        psi[k] = x
         info[k] = dict(iters=it, relres=rr, status=st)
         slab_insert(T, L, S, dk, x)
+        hop[k] = x
+        if overlap > 0 and any(dist[j] == dist[k] + 1 for j in range(len(domains))):
+            ext = extended_domain(T, dk, overlap)
+            if ext[1] >= T:
+                raise ValueError("overlap too thick for slab %d" % k)
+            a, b = overlap * L3, (overlap + dk[1]) * L3
+            rhs_ext = np.zeros((eta.shape[0], ext[1] * L3, 12), dtype=np.complex128)
+            rhs_ext[:, a:b] = rhs
+            xe, it, rr, st = solve(U, kappa, T, L, bc, rhs_ext, dom=ext, tol=tol, maxit=maxit, method=method)
+            info[k]["extended"] = dict(iters=it, relres=rr, status=st)
+            hop[k] = xe[:, a:b]
     return S, info
 
 

@@ -7,6 +7,8 @@
   form of the first case (Eq. 13) and the exact first equality of the second case (Eq. 14);
 - the factorised chain against dense block products, and the identity that feeding the
   exact propagator into the frontier hop reproduces the exact propagator;
+- overlap regions (Delta > 0): the chain against dense block products, the form of the
+  correction (Eq. 15) and its fall-off with Delta;
 - the pion correlator (Eq. 4): free-field closed form, time-reflection symmetry,
   positivity and invariance under a random gauge transformation.
 """
@@ -141,6 +143,88 @@ def test_factorised_chain_vs_dense(domains, bc):
     for k, dk in enumerate(domains):
         got = O.slab_extract(T, L, S, dk).reshape(12, -1).T
         assert np.linalg.norm(got - psi[k]) <= 1e-11 * np.linalg.norm(psi[k])
+
+
+@pytest.mark.parametrize("domains,overlap", [([(0, 6), (6, 6)], 1), ([(0, 6), (6, 6)], 2),
+                                             ([(0, 3), (3, 3), (6, 3), (9, 3)], 2),
+                                             ([(10, 4), (2, 5), (7, 3)], 1)])
+@pytest.mark.parametrize("bc", [-1, 0])
+def test_factorised_overlap_vs_dense(domains, overlap, bc):
+    """The chain with overlap regions against dense block products: every domain
+    that feeds a frontier hop is solved on its extension (Delta slices on both
+    time sides, P D P of the grown slab) and only the part on the domain crosses
+    the frontier; S_fact on each domain stays the unextended solve."""
+    T, L, kappa = 12, 2, 0.14
+    if bc == 0 and domains[0][0] != 0:
+        pytest.skip("open time edge: slabs must start at 0 for a chain")
+    U = random_links(T, L, 0.5, 62)
+    src = (domains[0][0] + 1, 1, 0, 1)
+    S, info = O.factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-13, overlap=overlap)
+    dist = O.domain_distances(T, bc, domains)
+    eta = point_sources(T, L, *src)
+    n = len(domains)
+    blk = {(a, b): dense_block(U, kappa, T, L, bc, domains[a], domains[b]) for a in range(n) for b in range(n)}
+    psi, hop = {}, {}
+    for k in sorted(range(n), key=lambda k: dist[k]):
+        if dist[k] == 0:
+            rhs = O.slab_extract(T, L, eta, domains[k]).reshape(12, -1).T
+        else:
+            rhs = -sum(blk[(k, j)] @ hop[j] for j in range(n) if dist[j] == dist[k] - 1)
+        psi[k] = np.linalg.solve(blk[(k, k)], rhs)
+        hop[k] = psi[k]
+        if any(dist[j] == dist[k] + 1 for j in range(n)):
+            ext = ((domains[k][0] - overlap) % T, domains[k][1] + 2 * overlap)
+            a, b = overlap * L ** 3 * 12, (overlap + domains[k][1]) * L ** 3 * 12
+            rext = np.zeros((ext[1] * L ** 3 * 12, 12), complex)
+            rext[a:b] = rhs
+            hop[k] = np.linalg.solve(dense_block(U, kappa, T, L, bc, ext, ext), rext)[a:b]
+            assert "extended" in info[k]
+    for k, dk in enumerate(domains):
+        got = O.slab_extract(T, L, S, dk).reshape(12, -1).T
+        assert np.linalg.norm(got - psi[k]) <= 1e-11 * np.linalg.norm(psi[k])
+
+
+def test_overlap_correction_form():
+    """Two regions, Delta = 2 (Eqs. 14 and 15, with the indices of Eq. 15 read as
+    for x in Gamma, y in Gamma*): on Gamma*, S_exact - S_fact =
+    D_Gamma*^-1 D_{Gamma*,Gamma} ([D_Gamma-bar^-1]_{Gamma Gamma} - S_Gamma^-1) eta,
+    with S_Gamma^-1 = [D^-1]_{Gamma Gamma} (Eq. 10)."""
+    T, L, kappa, bc, dlt = 12, 2, 0.14, -1, 2
+    U = random_links(T, L, 0.5, 63)
+    G, Gs = (0, 6), (6, 6)
+    src = (2, 0, 1, 1)
+    Sf, _ = O.factorized_propagator(U, kappa, T, L, bc, src, [G, Gs], tol=1e-13, overlap=dlt)
+    Se, _ = O.exact_propagator(U, kappa, T, L, bc, src, tol=1e-13)
+    D = dense_block(U, kappa, T, L, bc, None, None)
+    n0 = G[1] * L ** 3 * 12
+    SG = np.linalg.inv(D)[:n0, :n0]
+    Gb = O.extended_domain(T, G, dlt)
+    a = dlt * L ** 3 * 12
+    DGb = np.linalg.inv(dense_block(U, kappa, T, L, bc, Gb, Gb))[a:a + n0, a:a + n0]
+    eta = O.slab_extract(T, L, point_sources(T, L, *src), G).reshape(12, -1).T
+    corr = np.linalg.solve(dense_block(U, kappa, T, L, bc, Gs, Gs),
+                           dense_block(U, kappa, T, L, bc, Gs, G) @ ((DGb - SG) @ eta))
+    got = (O.slab_extract(T, L, Se, Gs) - O.slab_extract(T, L, Sf, Gs)).reshape(12, -1).T
+    ref = np.linalg.norm(O.slab_extract(T, L, Se, Gs))
+    # both sides carry the solves' rounding, ~1e-13 of the propagator; the correction is ~1e-5 of it
+    assert np.linalg.norm(got - corr) <= 1e-11 * ref
+    assert np.linalg.norm(corr) > 1e-6 * ref
+
+
+def test_overlap_correction_shrinks():
+    """The correction on Gamma* falls quickly as the overlap grows (Sec. 3.2:
+    suppressed like exp(-M_pi Delta / 2)): a heavy quark on 16x4^3, two slabs."""
+    T, L, bc, kappa = 16, 4, -1, 0.11
+    U = random_links(T, L, 0.3, 91)
+    src = (3, 1, 2, 0)
+    doms = [(0, 8), (8, 8)]
+    Se, _ = O.exact_propagator(U, kappa, T, L, bc, src, tol=1e-13)
+    ref = np.linalg.norm(O.slab_extract(T, L, Se, doms[1]))
+    err = []
+    for dlt in range(3):
+        Sf, _ = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=1e-13, overlap=dlt)
+        err.append(np.linalg.norm(O.slab_extract(T, L, Se - Sf, doms[1])) / ref)
+    assert err[0] > 3 * err[1] > 9 * err[2] > 0
 
 
 def test_exact_propagator_through_frontier_hop():
