@@ -12,6 +12,9 @@ already resident in HBM:
   factorised propagator across the four slabs [0,16) [16,32) [32,48) [48,64)
             (mixed solves, frontier hops) and the exact whole-lattice propagator,
             then the pion correlators C_fact(t), C_exact(t)
+  overlap   the same factorised propagator with overlap regions of 8 time slices
+            (Sec. 3.2: the slabs that feed a frontier are also solved on their
+            extension) and the correction of its correlator
   batched   96 independent Dirichlet domains of uneven sizes, 12 sources each
   force     S = phi^+ (D^+ D)^-1 phi on a 32x16^3 Dirichlet domain and its link
             force through the hand-written adjoint (torch.autograd)
@@ -40,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,batched,force")
+    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (10 times), the reference that scales "
                          "the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -97,7 +100,8 @@ def main():
     import paper_1612_06424_amd.dd as dd
     from paper_1612_06424_amd.inputs import WORKLOADS, batched_domains, gaussian_field, random_links
 
-    parts = set(args.parts.split(",")) if args.parts != "all" else {"stencil", "solve", "fact", "batched", "force"}
+    parts = set(args.parts.split(",")) if args.parts != "all" else {"stencil", "solve", "fact", "overlap", "batched",
+                                                                     "force"}
     if args.no_batched:
         parts.discard("batched")
     torch.cuda.set_device(0)
@@ -170,6 +174,8 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / n
 
+    corr_ref = {}  # the exact correlator of the latest step, for the overlap correction
+
     def step(record):
         ph = {}
         if "stencil" in parts:
@@ -209,7 +215,21 @@ def main():
                 for t in (0, 8, 16, 32):
                     ph["factorised"][f"C_exact[{t}]"] = float(Ce[t])
                     ph["factorised"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
+            corr_ref["Ce"] = Ce
             del Sf, Se
+        if "overlap" in parts:
+            t0 = time.perf_counter()
+            Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx, overlap=8)
+            Cf = dd.pion_correlator(ctx, Sf, src[0])
+            nd = len(w["domains"])
+            ph["factorised_overlap8"] = dict(ms=(time.perf_counter() - t0) * 1e3,
+                                             slab_iters=[s["iters"] for s in fst[:nd]],
+                                             max_true_rel_resid=max(max(s["true_rel_resid"]) for s in fst[:nd]))
+            if record and "Ce" in corr_ref:
+                Ce = corr_ref["Ce"]
+                for t in (0, 8, 16, 32):
+                    ph["factorised_overlap8"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
+            del Sf
         if "batched" in parts:
             t0 = time.perf_counter()
             bst = dd.block_solve_batched(bctx, bitems, pmx)
@@ -268,7 +288,7 @@ def main():
         "dtype": "c128+c64",
         "data": "synthetic",
         "config": {"workload": "64x32^3 Wilson-Dirac, antiperiodic time, eps=0.15, kappa=0.135; "
-                               "12-source solves on the 16x32^3 slab; 4-slab factorised propagator; "
+                               "12-source solves on the 16x32^3 slab; 4-slab factorised propagator (overlap 0 and 8); "
                                "96 uneven Dirichlet domains; 32x16^3 force",
                    "lattice": [T, L, L, L], "kappa": kappa, "tol": w["tol"],
                    "parts": sorted(parts)},

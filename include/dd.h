@@ -161,13 +161,19 @@ dd_status dd_block_solve(dd_ctx* ctx, const void* U, double kappa, const dd_doma
  * src = {t, x, y, z} across time slabs doms[0..ndom-1], which partition
  * [0, T) with src in doms[0]:
  *   psi_0 = D_L0^-1 eta                                   (Sec. 3.1, Eq. 13)
- *   psi_k = -D_Lk^-1 sum_{j: d(j) = d(k)-1} D_{Lk,Lj} psi_j (Sec. 3.2, Eq. 14,
- *            overlap Delta = 0, chained outward by block distance d on the
- *            graph of non-zero blocks of D)
+ *   psi_k = -D_Lk^-1 sum_{j: d(j) = d(k)-1} D_{Lk,Lj} h_j   (Sec. 3.2, Eq. 14,
+ *            chained outward by block distance d on the graph of non-zero
+ *            blocks of D)
  *   S_fact = sum_k psi_k.
+ * h_j is what crosses the frontier: psi_j for overlap = 0; for overlap =
+ * Delta > 0 the solution of slab j's equation (same source) on slab j grown by
+ * Delta time slices on both sides (Gamma-bar, the overlap region of Sec. 3.2),
+ * restricted to slab j.  Every slab with a slab beyond it must satisfy
+ * nt + 2 Delta < T (else DD_ERR_ARG).
  * S_fact (and S_exact = D^-1 eta if not NULL) are complex128 [12][12][V].
- * overlap must be 0 (a thicker overlap region is not built).  stats: NULL or
- * ndom + 1 entries (per slab, then the whole-lattice solve).  Synchronises.
+ * stats: NULL or ndom + 1 entries (per slab, then the whole-lattice solve; a
+ * slab's entry adds the iterations and time of its extended solve, and its
+ * residuals are the larger of the two solves').  Synchronises.
  */
 dd_status dd_factorized_propagator(dd_ctx* ctx, const void* U, double kappa, const int src[4],
                                    const dd_domain* doms, int ndom, int overlap,

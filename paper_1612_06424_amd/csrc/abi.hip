@@ -291,7 +291,7 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
     if (c == nullptr) return DD_ERR_ARG;
     dd_status e;
     if ((e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK) return e;
-    if (overlap != 0) return fail(c, DD_ERR_UNSUPPORTED, "overlap regions (Delta > 0) are not built");
+    if (overlap < 0) return fail(c, DD_ERR_ARG, "overlap must be >= 0");
     if (src == nullptr || doms == nullptr || ndom < 2) return fail(c, DD_ERR_ARG, "need a source and >= 2 slabs");
     const dd_lattice& lat = c->lat;
     const int T = lat.T, L = lat.L, L3 = L * L * L;
@@ -338,6 +338,16 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
             }
     }
     if ((int)order.size() != ndom) return fail(c, DD_ERR_ARG, "slabs are not connected by D");
+    // slabs whose solution crosses a frontier outward; with overlap regions they are also
+    // solved on their extension (overlap slices more on both time sides), which must stay
+    // shorter than the lattice
+    std::vector<char> feeds(ndom, 0);
+    for (int a = 0; a < ndom; a++)
+        for (int b : adj[a])
+            if (dist[b] == dist[a] + 1) feeds[a] = 1;
+    for (int k = 0; k < ndom; k++)
+        if (overlap > 0 && feeds[k] && doms[k].nt + 2 * overlap >= T)
+            return fail(c, DD_ERR_ARG, "overlap too thick for slab " + std::to_string(k));
 
     const size_t V = vlink(lat);
     CHECK_PTR(c, U, 36 * V * 16, 16, "U");
@@ -357,6 +367,19 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
     for (int k = 0; k < ndom; k++) maxslab = std::max(maxslab, (size_t)144 * doms[k].nt * L3);
     cpx<double>* rhs = (cpx<double>*)workspace(c, W_AUX3, std::max(maxslab, S_exact ? 144 * V : 0) * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
+    // the fields that cross frontiers (psi itself without overlap regions), and the source
+    // and solution on an extended slab
+    cpx<double>* hop = psi;
+    cpx<double>* ext = nullptr;
+    size_t maxext = 0;
+    if (overlap > 0) {
+        hop = (cpx<double>*)workspace(c, W_AUX0, tot * sizeof(cpx<double>), &e);
+        if (e != DD_OK) return e;
+        for (int k = 0; k < ndom; k++)
+            if (feeds[k]) maxext = std::max(maxext, (size_t)144 * (doms[k].nt + 2 * overlap) * L3);
+        ext = (cpx<double>*)workspace(c, W_AUX1, 2 * maxext * sizeof(cpx<double>), &e);
+        if (e != DD_OK) return e;
+    }
 
     const int ssp = (src[3] * L + src[2]) * L + src[1];
     dd_status worst = DD_OK;
@@ -370,7 +393,7 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
             launch_zero<double>(c, (size_t)144 * nsite, rhs);
             for (int j = 0; j < ndom; j++)
                 if (dist[j] == dist[k] - 1 && std::find(adj[k].begin(), adj[k].end(), j) != adj[k].end())
-                    launch_frontier(c, lat, (const cpx<double>*)U, dk, doms[j], 12, psi + base[j], rhs, -1.0);
+                    launch_frontier(c, lat, (const cpx<double>*)U, dk, doms[j], 12, hop + base[j], rhs, -1.0);
         }
         DD_HIP(c, hipGetLastError());
         const Geo g = make_geo(lat, &dk);
@@ -378,6 +401,29 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
         if (e != DD_OK && e != DD_ERR_NOCONV) return e;
         if (e == DD_ERR_NOCONV) worst = e;
         launch_slab_scatter(c, lat, dk, 12, psi + base[k], (cpx<double>*)S_fact);
+        if (overlap > 0 && feeds[k]) {
+            // the same source on the slab grown by overlap slices on both sides; its part on
+            // slab k is what crosses the frontiers (Sec. 3.2, Gamma-bar)
+            const int ntb = dk.nt + 2 * overlap;
+            const dd_domain dx{((dk.t0 - overlap) % T + T) % T, ntb};
+            cpx<double>*rx = ext, *xx = ext + maxext;
+            launch_zero<double>(c, (size_t)144 * ntb * L3, rx);
+            launch_slab_embed(c, L3, ntb, overlap, dk.nt, 12, rhs, rx, 0);
+            DD_HIP(c, hipGetLastError());
+            dd_solve_stats sx;
+            e = solve(c, (const cpx<double>*)U, kappa, make_geo(lat, &dx), 12, rx, xx, *p, stats ? &sx : nullptr, 0);
+            if (e != DD_OK && e != DD_ERR_NOCONV) return e;
+            if (e == DD_ERR_NOCONV) worst = e;
+            if (stats) {
+                dd_solve_stats& sk = stats[k];
+                sk.iters += sx.iters;
+                sk.updates += sx.updates;
+                sk.restarts += sx.restarts;
+                sk.ms += sx.ms;
+                for (int j = 0; j < 12; j++) sk.true_rel_resid[j] = std::max(sk.true_rel_resid[j], sx.true_rel_resid[j]);
+            }
+            launch_slab_embed(c, L3, ntb, overlap, dk.nt, 12, hop + base[k], xx, 1);
+        }
     }
     if (S_exact) {
         launch_point_source(c, (int)V, src[0] * L3 + ssp, rhs);

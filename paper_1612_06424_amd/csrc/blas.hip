@@ -278,6 +278,14 @@ void launch_slab_gather(dd_ctx* c, const dd_lattice& lat, const dd_domain& dom, 
                        0, c->stream, lat.T, L3, dom.t0, dom.nt, 1, const_cast<cpx<double>*>(whole), part);
 }
 
+void launch_slab_embed(dd_ctx* c, int L3, int nt_big, int off, int nt, int ncol, cpx<double>* part,
+                       cpx<double>* big, int dir) {
+    // the big slab plays the whole lattice of k_slab_copy: nt_big slices, part at slices [off, off + nt)
+    const int n = nt * L3;
+    hipLaunchKernelGGL(k_slab_copy, dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)(12 * ncol)), dim3(kBlock),
+                       0, c->stream, nt_big, L3, off, nt, dir, big, part);
+}
+
 void launch_point_source(dd_ctx* c, int nsite, int site, cpx<double>* eta) {
     launch_zero<double>(c, (size_t)144 * nsite, eta);
     hipLaunchKernelGGL(k_point_source, dim3(1), dim3(64), 0, c->stream, nsite, site, eta);

@@ -374,6 +374,10 @@ void launch_slab_scatter(dd_ctx* c, const dd_lattice& lat, const dd_domain& dom,
                          const cpx<double>* part, cpx<double>* whole);
 void launch_slab_gather(dd_ctx* c, const dd_lattice& lat, const dd_domain& dom, int ncol,
                         const cpx<double>* whole, cpx<double>* part);
+// compact slab field (nt slices) <-> the slices [off, off + nt) of a compact slab
+// field of nt_big slices; dir 0: part -> big, 1: big -> part
+void launch_slab_embed(dd_ctx* c, int L3, int nt_big, int off, int nt, int ncol, cpx<double>* part,
+                       cpx<double>* big, int dir);
 void launch_point_source(dd_ctx* c, int nsite, int site, cpx<double>* eta);
 // pion correlator: per-slice partial sums then fixed-order reduction
 void launch_pion(dd_ctx* c, const dd_lattice& lat, int ncol, const cpx<double>* S, int t_src,

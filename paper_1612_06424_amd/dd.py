@@ -192,8 +192,9 @@ def block_solve(ctx, U, kappa, b, dom=None, params=None, x=None, allow_noconv=Fa
     return x, stats.as_dict()
 
 
-def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_fact=None, S_exact=None):
-    """S_fact (and S_exact) as complex128 (12, 12, V).  Returns (S_fact, S_exact or None, stats)."""
+def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_fact=None, S_exact=None, overlap=0):
+    """S_fact (and S_exact) as complex128 (12, 12, V), with overlap regions of `overlap` time
+    slices.  Returns (S_fact, S_exact or None, stats)."""
     params = params or solver_params()
     V = ctx.V
     if S_fact is None:
@@ -204,7 +205,7 @@ def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_
     darr = (dd_domain * len(doms))(*[dd_domain(int(a), int(b)) for a, b in doms])
     stats = (dd_solve_stats * (len(doms) + 1))()
     ctx._check(_lib.dd_factorized_propagator(
-        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), srcarr, darr, len(doms), 0, C.byref(params),
+        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), srcarr, darr, len(doms), int(overlap), C.byref(params),
         _ptr(S_fact, torch.complex128, "S_fact"),
         _ptr(S_exact, torch.complex128, "S_exact") if exact else None, stats))
     return S_fact, (S_exact if exact else None), [s.as_dict() for s in stats]

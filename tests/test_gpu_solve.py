@@ -116,6 +116,46 @@ def test_factorised_four_slabs_with_wrap(prec):
     assert np.abs(C - Cr).max() / Cr.max() < (1e-10 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("case", ["two-slabs-1", "two-slabs-3", "ring-2", "dirichlet-2"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_factorised_overlap_vs_oracle(case, prec):
+    """Overlap regions (Sec. 3.2, Delta > 0): the slabs that feed a frontier are also
+    solved on their extension; S_fact and its correlator against the oracle."""
+    dd = lib()
+    step(f"factorised overlap {case} {prec}")
+    T, L, kappa = 16, 4, 0.13
+    geo = {"two-slabs-1": (-1, [(0, 8), (8, 8)], (3, 1, 2, 0), 1),
+           "two-slabs-3": (-1, [(0, 8), (8, 8)], (3, 1, 2, 0), 3),
+           "ring-2": (-1, [(14, 4), (2, 4), (6, 4), (10, 4)], (15, 1, 2, 3), 2),
+           "dirichlet-2": (0, [(0, 6), (6, 5), (11, 5)], (2, 0, 1, 3), 2)}
+    bc, doms, src, dlt = geo[case]
+    U = random_links(T, L, 0.3, 2400)
+    Sf_ref, _ = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=1e-13, overlap=dlt)
+    ctx = dd.Context(T, L, bc)
+    p = dd.solver_params(tol=1e-13 if prec == "fp64" else 1e-10,
+                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED)
+    Sf, _, stats = dd.factorized_propagator(ctx, dd.pack_links(U), kappa, src, doms, p, overlap=dlt)
+    bar = 1e-10 if prec == "fp64" else 1e-6
+    assert relerr(dd.unpack_field(Sf), Sf_ref) < bar
+    C = dd.pion_correlator(ctx, Sf, src[0])
+    Cr = O.pion_correlator(T, L, Sf_ref, src[0])
+    assert np.abs(C - Cr).max() / Cr.max() < bar
+    assert all(max(st["true_rel_resid"]) <= p.tol for st in stats[:len(doms)])
+
+
+def test_factorised_overlap_errors():
+    dd = lib()
+    step("factorised overlap errors")
+    T, L, bc = 16, 4, -1
+    U = random_links(T, L, 0.3, 2401)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U)
+    for dlt in (-1, 4):  # negative; 8 + 2 * 4 slices is the whole lattice
+        with pytest.raises(dd.DDError) as e:
+            dd.factorized_propagator(ctx, Ud, 0.13, (3, 1, 2, 0), [(0, 8), (8, 8)], overlap=dlt)
+        assert e.value.status == dd.DD_ERR_ARG
+
+
 def test_domain_action_force_vs_oracle():
     dd = lib()
     step("domain action + force")
