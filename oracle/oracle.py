@@ -203,6 +203,66 @@ def domain_distances(T, bc, domains):
     return d
 
 
+def orthonormalize(V):
+    """An orthonormal basis of the span of the fields V (n, ...): the Q factor of the
+    QR factorisation (numpy) of V flattened to n columns, reshaped like V."""
+    n = V.shape[0]
+    Q, _ = np.linalg.qr(np.asarray(V, dtype=np.complex128).reshape(n, -1).T)
+    return np.ascontiguousarray(Q.T).reshape(V.shape)
+
+
+def hop_spin_projector(sign):
+    """(1 + sign gamma_0) / 2 on the 12 (spin, colour) components, c = 3 spin + colour:
+    the spin projection that the time hop leaving a slice forward (sign = +1, towards
+    t + 1) or backward (sign = -1) applies to the field on that slice (Sec. 5, D_w)."""
+    g0 = gamma_matrices()[0]
+    return np.kron((np.eye(4) + sign * g0) / 2, np.eye(3))
+
+
+def projection_basis(U, kappa, T, L, bc, pi_dom, t_slice, sign, v0, n_iter, tol=1e-12, method=0):
+    """Quark-line projection vectors (Sec. 3.3) for the frontier hop that leaves time
+    slice t_slice forward (sign = +1) or backward (-1), N_m = len(v0):
+      inverse iteration of the Wilson-Dirac operator of the slab pi_dom around the
+      frontier, V <- orthonormalize(D_Pi^-1 V), n_iter times from orthonormalize(v0)
+      (v0: N_m fields on pi_dom), then
+      phi = orthonormalize((1 + sign gamma_0)/2 V restricted to t_slice),
+    N_m orthonormal vectors on the slice in the range of the hop's spin projector (the
+    6 L^3 entries per column that cross the frontier).  Returns (phi (N_m, L^3, 12), V)."""
+    U = _links(U)
+    L3 = L ** 3
+    t0, nt = _norm_dom(T, pi_dom)
+    k = (t_slice - t0) % T
+    if k >= nt:
+        raise ValueError("t_slice outside pi_dom")
+    if len(v0) > 6 * L3:
+        raise ValueError("more vectors than the 6 L^3 entries of a frontier slice")
+    V = orthonormalize(np.asarray(v0, dtype=np.complex128))
+    for _ in range(n_iter):
+        V, _, _, st = solve(U, kappa, T, L, bc, V, dom=pi_dom, tol=tol, method=method)
+        if st != 0:
+            raise RuntimeError("inverse iteration solve did not converge")
+        V = orthonormalize(V)
+    W = V.reshape(len(V), nt, L3, 12)[:, k] @ hop_spin_projector(sign).T
+    return orthonormalize(W), V
+
+
+def _project_slices(T, L, dom, field, projections):
+    """field (ncol, |dom|, 12) with every time slice t of dom that is a key of projections
+    replaced by P_L field = sum_i phi_i (phi_i^+ field) on that slice (Eq. 16)."""
+    if not projections:
+        return field
+    t0, nt = _norm_dom(T, dom)
+    L3 = L ** 3
+    out = field.reshape(field.shape[0], nt, L3, 12).copy()
+    for t, phi in projections.items():
+        k = (t - t0) % T
+        if k < nt:
+            P = phi.reshape(len(phi), -1)
+            x = out[:, k].reshape(field.shape[0], -1)
+            out[:, k] = ((x @ P.conj().T) @ P).reshape(field.shape[0], L3, 12)
+    return out.reshape(field.shape)
+
+
 def extended_domain(T, dom, overlap):
     """The slab dom = (t0, nt) grown by `overlap` time slices on both sides (mod T):
     Gamma-bar = Gamma plus the boundary layer of thickness Delta of Sec. 3.2."""
@@ -211,7 +271,7 @@ def extended_domain(T, dom, overlap):
 
 
 def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100000,
-                          method=0, eta=None, overlap=0):
+                          method=0, eta=None, overlap=0, projections=None):
     """Factorised point-to-all propagator across time-slab domains.
 
     domains: list of (t0, nt) partitioning [0, T); the source must lie in
@@ -223,8 +283,10 @@ def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100
     solution of domain j's equation (same source) on its extension Lj-bar =
     Lj grown by `overlap` slices on both time sides, restricted to Lj: for two
     domains h_0 = [D_Gamma-bar^-1 eta] on Gamma, i.e. Eq. 14 with an overlap
-    region of thickness Delta = overlap (h_j = psi_j for Delta = 0).  Returns
-    (S_fact (12, V, 12), per-domain solve info).
+    region of thickness Delta = overlap (h_j = psi_j for Delta = 0).  With
+    projections = {t: phi} (projection_basis), the quark line is cut at every
+    frontier slice t: h_j on slice t is replaced by P_L h_j, P_L = sum_i phi_i
+    phi_i^+ (Eqs. 15-16).  Returns (S_fact (12, V, 12), per-domain solve info).
     """
     U = _links(U)
     L3 = L ** 3
@@ -250,7 +312,8 @@ def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100
             rhs = np.zeros((eta.shape[0], dk[1] * L3, 12), dtype=np.complex128)
             for j in range(len(domains)):
                 if dist[j] == dist[k] - 1:
-                    rhs -= block_apply(U, kappa, T, L, bc, dk, domains[j], hop[j])
+                    hj = _project_slices(T, L, domains[j], hop[j], projections)
+                    rhs -= block_apply(U, kappa, T, L, bc, dk, domains[j], hj)
         x, it, rr, st = solve(U, kappa, T, L, bc, rhs, dom=dk, tol=tol, maxit=maxit, method=method)
         info[k] = dict(iters=it, relres=rr, status=st)
         slab_insert(T, L, S, dk, x)

@@ -1,0 +1,98 @@
+"""Pins of the oracle's quark-line projection (Sec. 3.3, Eqs. 15-16).
+
+- the projection vectors are orthonormal and lie in the range of the frontier hop's
+  spin projector (1 +- gamma_0)/2;
+- with a complete basis (all 6 L^3 vectors of a frontier slice) the projected
+  factorised propagator is the unprojected one;
+- inverse iteration on the slab around the frontier converges to the invariant subspace
+  of the eigenvalues of smallest modulus of the dense D_Pi;
+- the projected chain against dense block products.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+from paper_1612_06424_amd.inputs import gaussian_field, point_sources, random_links
+from test_oracle_solve import dense_block
+
+T, L, KAPPA = 8, 2, 0.14
+L3 = L ** 3
+
+
+def _basis(U, bc, pi_dom, t, sign, n, seed, n_iter=4):
+    v0 = gaussian_field(pi_dom[1] * L3, n, seed)
+    return O.projection_basis(U, KAPPA, T, L, bc, pi_dom, t, sign, v0, n_iter, tol=1e-13)
+
+
+def test_basis_orthonormal_in_spin_projector_range():
+    U = random_links(T, L, 0.5, 71)
+    for sign, t in ((+1, 3), (-1, 4)):
+        phi, _ = _basis(U, -1, (2, 4), t, sign, 10, 72)
+        P = phi.reshape(10, -1)
+        assert np.abs(P.conj() @ P.T - np.eye(10)).max() < 1e-13
+        assert np.abs(phi @ O.hop_spin_projector(sign).T - phi).max() < 1e-13
+        # the other projector annihilates it
+        assert np.abs(phi @ O.hop_spin_projector(-sign).T).max() < 1e-13
+
+
+@pytest.mark.parametrize("bc", [-1, 0])
+def test_complete_basis_is_no_approximation(bc):
+    """All 6 L^3 directions of every frontier slice: P_L is the spin projector the hop
+    applies anyway, so the projected propagator equals the unprojected one."""
+    U = random_links(T, L, 0.5, 73)
+    doms = [(0, 4), (4, 4)]
+    src = (1, 0, 1, 1)
+    proj = {3: _basis(U, bc, (2, 4), 3, +1, 6 * L3, 74)[0]}  # leaves slab 0 forward at t = 3
+    if bc != 0:
+        proj[0] = _basis(U, bc, (6, 4), 0, -1, 6 * L3, 75)[0]  # and backward across the time edge
+    S0, _ = O.factorized_propagator(U, KAPPA, T, L, bc, src, doms, tol=1e-13)
+    S1, _ = O.factorized_propagator(U, KAPPA, T, L, bc, src, doms, tol=1e-13, projections=proj)
+    assert np.linalg.norm(S1 - S0) <= 1e-11 * np.linalg.norm(S0)
+    # a smaller basis is an approximation
+    small = {t: p[:12] for t, p in proj.items()}
+    S2, _ = O.factorized_propagator(U, KAPPA, T, L, bc, src, doms, tol=1e-13, projections=small)
+    assert np.linalg.norm(S2 - S0) > 1e-6 * np.linalg.norm(S0)
+
+
+def test_inverse_iteration_finds_the_low_modes():
+    """V after n inverse iterations spans the invariant subspace of the N_m eigenvalues
+    of D_Pi of smallest modulus (error ~ |lambda_m / lambda_{m+1}|^n)."""
+    U = random_links(T, L, 0.5, 76)
+    pi = (3, 2)
+    A = dense_block(U, KAPPA, T, L, -1, pi, pi)
+    lam, vec = sla.eig(A)
+    order = np.argsort(np.abs(lam))
+    ratios = [np.abs(lam[order[m - 1]]) / np.abs(lam[order[m]]) for m in range(4, 13)]
+    m = 4 + int(np.argmin(ratios))
+    r = min(ratios)
+    n_iter = int(min(400, np.ceil(np.log(1e-11) / np.log(r))))
+    _, V = _basis(U, -1, pi, 3, +1, m, 77, n_iter=n_iter)
+    QV, _ = np.linalg.qr(V.reshape(m, -1).T)
+    QE, _ = np.linalg.qr(vec[:, order[:m]])
+    assert np.abs(QV @ QV.conj().T - QE @ QE.conj().T).max() < 1e-7
+
+
+def test_projected_chain_vs_dense():
+    """S_fact on slab 1 = -D_11^-1 D_10 P_L D_00^-1 eta, P_L acting on the frontier slices
+    of slab 0 (t = 3 forward, t = 0 backward across the time edge); slab 0 keeps D_00^-1 eta."""
+    U = random_links(T, L, 0.5, 78)
+    doms = [(0, 4), (4, 4)]
+    src = (2, 1, 0, 1)
+    proj = {3: _basis(U, -1, (2, 4), 3, +1, 10, 79)[0], 0: _basis(U, -1, (6, 4), 0, -1, 9, 80)[0]}
+    S, _ = O.factorized_propagator(U, KAPPA, T, L, -1, src, doms, tol=1e-13, projections=proj)
+    D00 = dense_block(U, KAPPA, T, L, -1, doms[0], doms[0])
+    D11 = dense_block(U, KAPPA, T, L, -1, doms[1], doms[1])
+    D10 = dense_block(U, KAPPA, T, L, -1, doms[1], doms[0])
+    eta = O.slab_extract(T, L, point_sources(T, L, *src), doms[0]).reshape(12, -1).T
+    h0 = np.linalg.solve(D00, eta)                       # (|slab 0| 12, 12 columns)
+    n = L3 * 12
+    PL = np.eye(h0.shape[0], dtype=complex)
+    for t, phi in proj.items():
+        Q = phi.reshape(len(phi), -1).T                   # (L^3 12, N_m)
+        PL[t * n:(t + 1) * n, t * n:(t + 1) * n] = Q @ Q.conj().T
+    psi1 = -np.linalg.solve(D11, D10 @ (PL @ h0))
+    got1 = O.slab_extract(T, L, S, doms[1]).reshape(12, -1).T
+    got0 = O.slab_extract(T, L, S, doms[0]).reshape(12, -1).T
+    assert np.linalg.norm(got1 - psi1) <= 1e-11 * np.linalg.norm(psi1)
+    assert np.linalg.norm(got0 - h0) <= 1e-11 * np.linalg.norm(h0)
