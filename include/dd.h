@@ -61,7 +61,7 @@ typedef enum {
     DD_ERR_HIP = -2,         /* a HIP runtime call failed */
     DD_ERR_NOMEM = -3,       /* workspace allocation failed */
     DD_ERR_NOCONV = -4,      /* solver hit max_iter; x holds the last iterate */
-    DD_ERR_BREAKDOWN = -5,   /* non-finite values (NaN/Inf) in the iteration */
+    DD_ERR_BREAKDOWN = -5,   /* non-finite values (NaN/Inf) in the iteration, or dependent vectors */
     DD_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
 } dd_status;
 
@@ -179,6 +179,44 @@ dd_status dd_factorized_propagator(dd_ctx* ctx, const void* U, double kappa, con
                                    const dd_domain* doms, int ndom, int overlap,
                                    const dd_solver_params* params, void* S_fact, void* S_exact,
                                    dd_solve_stats* stats);
+
+/*
+ * Quark-line projection vectors (Sec. 3.3, Eqs. 15-16): an orthonormal basis
+ * phi_1..phi_nvec of the field on the time slice t_slice (global time, inside
+ * the slab pi) that a frontier hop reads, for the hop leaving the slice forward
+ * (sign = +1: towards t_slice + 1, spin projector (1 + gamma_0)/2) or backward
+ * (sign = -1: (1 - gamma_0)/2).
+ *   V <- v0, orthonormalised; n_iter times V <- orthonormalise(D_pi^-1 V)
+ *   (inverse iteration on the slab pi, DD_MAX_RHS columns per solve);
+ *   phi = orthonormalise((1 + sign gamma_0)/2 (V on slice t_slice)).
+ * Orthonormalisation is Cholesky QR applied twice, in FP64.
+ * v0: complex128 [nvec][12][pi->nt L^3] (device, read only); phi: complex128
+ * [nvec][12][L^3] (device, output).  1 <= nvec <= min(256, 6 L^3),
+ * n_iter >= 0.  Returns DD_ERR_BREAKDOWN if the vectors are linearly dependent
+ * in FP64 (e.g. nvec above the rank of the projected slice), DD_ERR_NOCONV if a
+ * solve missed tol (phi is still written).  stats (may be NULL): summed
+ * iterations and time, nrhs = nvec, true_rel_resid[0] = the largest final
+ * residual of all solves.  Synchronises.
+ */
+dd_status dd_projection_basis(dd_ctx* ctx, const void* U, double kappa, const dd_domain* pi,
+                              int t_slice, int sign, int nvec, int n_iter, const void* v0, void* phi,
+                              const dd_solver_params* params, dd_solve_stats* stats);
+
+/*
+ * dd_factorized_propagator with the quark line cut on nproj time slices
+ * (Sec. 3.3, Eq. 16): the field that crosses the frontiers, h_j, has its
+ * slice proj_t[i] replaced by P_L h_j = sum_a phi_a (phi_a^+ h_j) over the
+ * proj_nvec[i] orthonormal vectors proj_phi[i] (complex128 [nvec][12][L^3],
+ * device; e.g. from dd_projection_basis).  S_fact on each slab stays that
+ * slab's unprojected solution.  proj_t, proj_nvec and proj_phi are host
+ * arrays of nproj entries; slices are distinct, 1 <= proj_nvec[i] <=
+ * min(256, 6 L^3).  nproj = 0 is dd_factorized_propagator.  Synchronises.
+ */
+dd_status dd_factorized_propagator_projected(dd_ctx* ctx, const void* U, double kappa, const int src[4],
+                                             const dd_domain* doms, int ndom, int overlap, int nproj,
+                                             const int* proj_t, const int* proj_nvec,
+                                             const void* const* proj_phi, const dd_solver_params* params,
+                                             void* S_fact, void* S_exact, dd_solve_stats* stats);
 
 /*
  * Pion two-point function of a whole-lattice propagator S (complex128

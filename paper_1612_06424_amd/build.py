@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdd.so")
-SOURCES = ["abi.hip", "dirac.hip", "blas.hip", "krylov.hip", "solver.hip", "evenodd.hip", "batched.hip", "tune.hip"]
+SOURCES = ["abi.hip", "dirac.hip", "blas.hip", "krylov.hip", "solver.hip", "evenodd.hip", "batched.hip", "tune.hip",
+           "projection.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

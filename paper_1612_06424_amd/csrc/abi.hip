@@ -285,9 +285,12 @@ dd_status dd_block_solve(dd_ctx* c, const void* U, double kappa, const dd_domain
     return solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)b, (cpx<double>*)x, *p, stats, 0);
 }
 
-dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const int src[4], const dd_domain* doms,
-                                   int ndom, int overlap, const dd_solver_params* p, void* S_fact, void* S_exact,
-                                   dd_solve_stats* stats) {
+// The factorised propagator with optional quark-line projections: nproj slices
+// proj_t[i] (global time) whose crossing field is replaced by P_L = sum over the
+// proj_nvec[i] vectors phi_i phi_i^+ of proj_phi[i] (Sec. 3.3, Eq. 16).
+static dd_status factorized(dd_ctx* c, const void* U, double kappa, const int src[4], const dd_domain* doms, int ndom,
+                     int overlap, int nproj, const int* proj_t, const int* proj_nvec, const void* const* proj_phi,
+                     const dd_solver_params* p, void* S_fact, void* S_exact, dd_solve_stats* stats) {
     if (c == nullptr) return DD_ERR_ARG;
     dd_status e;
     if ((e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK) return e;
@@ -353,6 +356,19 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
     CHECK_PTR(c, U, 36 * V * 16, 16, "U");
     CHECK_PTR(c, S_fact, 144 * V * 16, 16, "S_fact");
     if (S_exact) CHECK_PTR(c, S_exact, 144 * V * 16, 16, "S_exact");
+    if (nproj < 0) return fail(c, DD_ERR_ARG, "nproj must be >= 0");
+    if (nproj > 0 && (proj_t == nullptr || proj_nvec == nullptr || proj_phi == nullptr))
+        return fail(c, DD_ERR_ARG, "projection arrays are NULL");
+    std::vector<char> projected(T, 0);
+    for (int i = 0; i < nproj; i++) {
+        const int t = proj_t[i], nv = proj_nvec[i];
+        if (t < 0 || t >= T) return fail(c, DD_ERR_ARG, "projection slice outside [0, T)");
+        if (projected[t]) return fail(c, DD_ERR_ARG, "slice " + std::to_string(t) + " projected twice");
+        projected[t] = 1;
+        if (nv < 1 || nv > std::min(kMaxProjVec, 6 * L3))
+            return fail(c, DD_ERR_ARG, "projection basis size must be in [1, min(256, 6 L^3)]");
+        CHECK_PTR(c, proj_phi[i], (size_t)nv * 12 * L3 * 16, 16, "proj_phi");
+    }
 
     // per-slab solutions psi_k, stored compactly one after the other
     std::vector<size_t> base(ndom);
@@ -424,6 +440,14 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
             }
             launch_slab_embed(c, L3, ntb, overlap, dk.nt, 12, hop + base[k], xx, 1);
         }
+        // the quark line is cut on the projected slices of this slab's crossing field
+        // (S_fact on the slab keeps the unprojected solution, already scattered)
+        for (int i = 0; feeds[k] && i < nproj; i++) {
+            const int kl = ((proj_t[i] - dk.t0) % T + T) % T;
+            if (kl >= dk.nt) continue;
+            e = project_slice(c, L3, dk.nt, kl, 12, hop + base[k], proj_nvec[i], (const cpx<double>*)proj_phi[i]);
+            if (e != DD_OK) return e;
+        }
     }
     if (S_exact) {
         launch_point_source(c, (int)V, src[0] * L3 + ssp, rhs);
@@ -436,6 +460,47 @@ dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const
     DD_HIP(c, hipStreamSynchronize(c->stream));
     if (worst != DD_OK) return fail(c, worst, "a slab or whole-lattice solve did not converge: " + c->err);
     return DD_OK;
+}
+
+dd_status dd_factorized_propagator(dd_ctx* c, const void* U, double kappa, const int src[4], const dd_domain* doms,
+                                   int ndom, int overlap, const dd_solver_params* p, void* S_fact, void* S_exact,
+                                   dd_solve_stats* stats) {
+    return factorized(c, U, kappa, src, doms, ndom, overlap, 0, nullptr, nullptr, nullptr, p, S_fact, S_exact,
+                      stats);
+}
+
+dd_status dd_factorized_propagator_projected(dd_ctx* c, const void* U, double kappa, const int src[4],
+                                             const dd_domain* doms, int ndom, int overlap, int nproj,
+                                             const int* proj_t, const int* proj_nvec, const void* const* proj_phi,
+                                             const dd_solver_params* p, void* S_fact, void* S_exact,
+                                             dd_solve_stats* stats) {
+    return factorized(c, U, kappa, src, doms, ndom, overlap, nproj, proj_t, proj_nvec, proj_phi, p, S_fact,
+                      S_exact, stats);
+}
+
+dd_status dd_projection_basis(dd_ctx* c, const void* U, double kappa, const dd_domain* pi, int t_slice, int sign,
+                              int nvec, int n_iter, const void* v0, void* phi, const dd_solver_params* p,
+                              dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if (pi == nullptr) return fail(c, DD_ERR_ARG, "pi is NULL");
+    if ((e = check_dom(c, pi)) != DD_OK || (e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK)
+        return e;
+    const dd_lattice& lat = c->lat;
+    const int T = lat.T, L3 = lat.L * lat.L * lat.L;
+    if (t_slice < 0 || t_slice >= T) return fail(c, DD_ERR_ARG, "t_slice outside [0, T)");
+    const int k = ((t_slice - pi->t0) % T + T) % T;
+    if (k >= pi->nt) return fail(c, DD_ERR_ARG, "t_slice outside the slab");
+    if (sign != 1 && sign != -1) return fail(c, DD_ERR_ARG, "sign must be +1 or -1");
+    if (nvec < 1 || nvec > std::min(kMaxProjVec, 6 * L3))
+        return fail(c, DD_ERR_ARG, "nvec must be in [1, min(256, 6 L^3)]");
+    if (n_iter < 0) return fail(c, DD_ERR_ARG, "n_iter must be >= 0");
+    const Geo g = make_geo(lat, pi);
+    CHECK_PTR(c, U, 36 * vlink(lat) * 16, 16, "U");
+    CHECK_PTR(c, v0, (size_t)nvec * 12 * g.nsite * 16, 16, "v0");
+    CHECK_PTR(c, phi, (size_t)nvec * 12 * L3 * 16, 16, "phi");
+    return projection_basis(c, (const cpx<double>*)U, kappa, g, k, sign, nvec, n_iter, (const cpx<double>*)v0,
+                            (cpx<double>*)phi, *p, stats);
 }
 
 dd_status dd_pion_correlator(dd_ctx* c, const void* S, int ncol, int t_src, double* C_host) {

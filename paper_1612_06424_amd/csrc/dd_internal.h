@@ -172,7 +172,7 @@ enum Slot {
     W_PART, W_STATE, W_STATE32, W_DOTS,
     W_AUX0, W_AUX1, W_AUX2, W_AUX3, W_AUX4,
     W_SEGS, W_SEGN, W_EO_B, W_EO_X, W_EO_BHAT, W_EO_T64, W_EO_T32, W_EO_U64, W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
-    W_U32C, W_LDEV,
+    W_U32C, W_LDEV, W_PROJ_V, W_PROJ_G, W_PROJ_R,
     W_NSLOTS
 };
 
@@ -395,5 +395,17 @@ void timing_harvest(dd_ctx* c);
 dd_status solve(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int ncol,
                 const cpx<double>* b, cpx<double>* x, const dd_solver_params& p,
                 dd_solve_stats* stats, int dag);
+
+// ---------------------------------------------------------------- quark-line projection
+constexpr int kMaxProjVec = 256;  // vectors per projection basis
+// phi ([nvec][12][L^3]) = orthonormal basis for the quark line leaving slice k of
+// the slab g forward (sign +1) or backward (-1), by n_iter inverse iterations
+// from v0 ([nvec][12][g.nsite])
+dd_status projection_basis(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, int k, int sign, int nvec,
+                           int n_iter, const cpx<double>* v0, cpx<double>* phi, const dd_solver_params& p,
+                           dd_solve_stats* stats);
+// slice k of field ([ncol][12][nt L^3]) <- sum_i phi_i phi_i^+ (that slice)
+dd_status project_slice(dd_ctx* c, int L3, int nt, int k, int ncol, cpx<double>* field, int nvec,
+                        const cpx<double>* phi);
 
 }  // namespace dd

@@ -37,7 +37,7 @@ EXPORTS = [
     "dd_create", "dd_destroy", "dd_last_error", "dd_apply_dirac", "dd_frontier_hop", "dd_block_solve",
     "dd_factorized_propagator", "dd_pion_correlator", "dd_block_solve_backward", "dd_domain_action",
     "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing_count",
-    "dd_kernel_timing",
+    "dd_kernel_timing", "dd_projection_basis", "dd_factorized_propagator_projected",
 ]
 
 
@@ -79,6 +79,11 @@ _sig = {
                         C.POINTER(dd_solve_stats)], _i),
     "dd_factorized_propagator": ([_vp, _vp, _d, C.POINTER(C.c_int), C.POINTER(dd_domain), _i, _i,
                                   C.POINTER(dd_solver_params), _vp, _vp, C.POINTER(dd_solve_stats)], _i),
+    "dd_factorized_propagator_projected": ([_vp, _vp, _d, C.POINTER(C.c_int), C.POINTER(dd_domain), _i, _i, _i,
+                                            C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(_vp),
+                                            C.POINTER(dd_solver_params), _vp, _vp, C.POINTER(dd_solve_stats)], _i),
+    "dd_projection_basis": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _i, _i, _i, _vp, _vp,
+                             C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
     "dd_pion_correlator": ([_vp, _vp, _i, _i, C.POINTER(C.c_double)], _i),
     "dd_block_solve_backward": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, _vp,
                                  C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
@@ -192,9 +197,11 @@ def block_solve(ctx, U, kappa, b, dom=None, params=None, x=None, allow_noconv=Fa
     return x, stats.as_dict()
 
 
-def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_fact=None, S_exact=None, overlap=0):
+def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_fact=None, S_exact=None, overlap=0,
+                          projections=None):
     """S_fact (and S_exact) as complex128 (12, 12, V), with overlap regions of `overlap` time
-    slices.  Returns (S_fact, S_exact or None, stats)."""
+    slices and the quark line cut on the slices t of projections = {t: phi} (phi complex128
+    (nvec, 12, L^3)).  Returns (S_fact, S_exact or None, stats)."""
     params = params or solver_params()
     V = ctx.V
     if S_fact is None:
@@ -204,11 +211,37 @@ def factorized_propagator(ctx, U, kappa, src, doms, params=None, exact=False, S_
     srcarr = (C.c_int * 4)(*[int(v) for v in src])
     darr = (dd_domain * len(doms))(*[dd_domain(int(a), int(b)) for a, b in doms])
     stats = (dd_solve_stats * (len(doms) + 1))()
-    ctx._check(_lib.dd_factorized_propagator(
-        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), srcarr, darr, len(doms), int(overlap), C.byref(params),
-        _ptr(S_fact, torch.complex128, "S_fact"),
-        _ptr(S_exact, torch.complex128, "S_exact") if exact else None, stats))
+    if projections:
+        ts = sorted(projections)
+        n = len(ts)
+        ctx._check(_lib.dd_factorized_propagator_projected(
+            ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), srcarr, darr, len(doms), int(overlap), n,
+            (C.c_int * n)(*[int(t) for t in ts]), (C.c_int * n)(*[int(projections[t].shape[0]) for t in ts]),
+            (_vp * n)(*[_ptr(projections[t], torch.complex128, "phi") for t in ts]), C.byref(params),
+            _ptr(S_fact, torch.complex128, "S_fact"),
+            _ptr(S_exact, torch.complex128, "S_exact") if exact else None, stats))
+    else:
+        ctx._check(_lib.dd_factorized_propagator(
+            ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), srcarr, darr, len(doms), int(overlap),
+            C.byref(params), _ptr(S_fact, torch.complex128, "S_fact"),
+            _ptr(S_exact, torch.complex128, "S_exact") if exact else None, stats))
     return S_fact, (S_exact if exact else None), [s.as_dict() for s in stats]
+
+
+def projection_basis(ctx, U, kappa, pi, t_slice, sign, v0, n_iter, params=None, phi=None, allow_noconv=False):
+    """Quark-line projection vectors phi (complex128 (nvec, 12, L^3)) of the hop leaving slice
+    t_slice of the slab pi = (t0, nt) forward (sign +1) or backward (-1), by n_iter inverse
+    iterations from v0 (complex128 (nvec, 12, nt L^3)).  Returns (phi, stats)."""
+    params = params or solver_params()
+    nvec = v0.shape[0]
+    if phi is None:
+        phi = torch.empty((nvec, 12, ctx.L ** 3), dtype=torch.complex128, device=v0.device)
+    stats = dd_solve_stats()
+    ctx._check(_lib.dd_projection_basis(
+        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), _dom(pi), int(t_slice), int(sign), nvec,
+        int(n_iter), _ptr(v0, torch.complex128, "v0"), _ptr(phi, torch.complex128, "phi"), C.byref(params),
+        C.byref(stats)), allow=(DD_ERR_NOCONV,) if allow_noconv else ())
+    return phi, stats.as_dict()
 
 
 def pion_correlator(ctx, S, t_src):
