@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force")
+    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection "
+                    "(all = every part but projection, which takes about a minute a step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (10 times), the reference that scales "
                          "the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -155,6 +156,14 @@ def main():
         bctx = dd.Context(8, 8, 0)
         log(f"batched inputs: {len(bitems)} domains, {sum(b['b'].shape[2] for b in bitems)} sites "
             f"({time.time() - t0:.1f}s)")
+    if "projection" in parts:
+        # quark-line projection at the frontier between t = 15 and 16: N_m = 120 vectors, 10
+        # inverse iterations on the 16 slices [8, 24) around it, seeded Gaussian start vectors
+        proj_pi, proj_t, proj_nvec, proj_iter = (8, 16), 15, 120, 10
+        gp = torch.Generator(device=dev)
+        gp.manual_seed(w["stencil_seed"] + 1)
+        proj_v0 = torch.randn((proj_nvec, 12, proj_pi[1] * L ** 3), dtype=torch.complex128, device=dev,
+                              generator=gp)
     if "force" in parts:
         wf = WORKLOADS["force-32x16^3"]
         Uf = dd.pack_links(random_links(wf["T"], wf["L"], wf["eps"], wf["link_seed"]))
@@ -230,6 +239,24 @@ def main():
                 for t in (0, 8, 16, 32):
                     ph["factorised_overlap8"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
             del Sf
+        if "projection" in parts:
+            t0 = time.perf_counter()
+            phi, pst = dd.projection_basis(ctx, U64, kappa, proj_pi, proj_t, +1, proj_v0, proj_iter, pmx)
+            t1 = time.perf_counter()
+            Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx,
+                                                  projections={proj_t: phi})
+            Cf = dd.pion_correlator(ctx, Sf, src[0])
+            t2 = time.perf_counter()
+            nd = len(w["domains"])
+            ph["projection"] = dict(ms=(t2 - t0) * 1e3, ms_basis=(t1 - t0) * 1e3, ms_propagator=(t2 - t1) * 1e3,
+                                    nvec=proj_nvec, inverse_iterations=proj_iter, basis_iters=pst["iters"],
+                                    basis_max_true_rel_resid=pst["true_rel_resid"][0],
+                                    slab_iters=[s["iters"] for s in fst[:nd]])
+            if record and "Ce" in corr_ref:
+                Ce = corr_ref["Ce"]
+                for t in (0, 8, 16, 32):
+                    ph["projection"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
+            del Sf, phi
         if "batched" in parts:
             t0 = time.perf_counter()
             bst = dd.block_solve_batched(bctx, bitems, pmx)
