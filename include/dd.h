@@ -181,7 +181,7 @@ dd_status dd_factorized_propagator(dd_ctx* ctx, const void* U, double kappa, con
                                    dd_solve_stats* stats);
 
 /*
- * Quark-line projection vectors (Sec. 3.3, Eqs. 15-16): an orthonormal basis
+ * Quark-line projection vectors (Sec. 3.3, Eqs. 16-17): an orthonormal basis
  * phi_1..phi_nvec of the field on the time slice t_slice (global time, inside
  * the slab pi) that a frontier hop reads, for the hop leaving the slice forward
  * (sign = +1: towards t_slice + 1, spin projector (1 + gamma_0)/2) or backward
@@ -204,7 +204,7 @@ dd_status dd_projection_basis(dd_ctx* ctx, const void* U, double kappa, const dd
 
 /*
  * dd_factorized_propagator with the quark line cut on nproj time slices
- * (Sec. 3.3, Eq. 16): the field that crosses the frontiers, h_j, has its
+ * (Sec. 3.3, Eqs. 16-17): the field that crosses the frontiers, h_j, has its
  * slice proj_t[i] replaced by P_L h_j = sum_a phi_a (phi_a^+ h_j) over the
  * proj_nvec[i] orthonormal vectors proj_phi[i] (complex128 [nvec][12][L^3],
  * device; e.g. from dd_projection_basis).  S_fact on each slab stays that

@@ -286,7 +286,7 @@ def factorized_propagator(U, kappa, T, L, bc, src, domains, tol=1e-12, maxit=100
     region of thickness Delta = overlap (h_j = psi_j for Delta = 0).  With
     projections = {t: phi} (projection_basis), the quark line is cut at every
     frontier slice t: h_j on slice t is replaced by P_L h_j, P_L = sum_i phi_i
-    phi_i^+ (Eqs. 15-16).  Returns (S_fact (12, V, 12), per-domain solve info).
+    phi_i^+ (Eqs. 16-17).  Returns (S_fact (12, V, 12), per-domain solve info).
     """
     U = _links(U)
     L3 = L ** 3
@@ -349,6 +349,57 @@ def pion_correlator(T, L, S, t_src):
     C = (_c.c_double * T)()
     lib().ora_pion(T, L, S.shape[0], _ptr(S), int(t_src), C)
     return np.array(list(C))
+
+
+def hop_power(U, kappa, T, L, bc, psi, n, dom=None):
+    """(kappa D_hop)^n psi on the whole lattice or the slab dom, with kappa D_hop = 1 - 2 kappa D
+    (the definition 2 kappa D = 1 - kappa D_hop of Sec. 5; on a slab D is the Dirichlet block)."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    for _ in range(n):
+        out = out - 2.0 * kappa * apply_dirac(U, kappa, T, L, bc, out, dom)
+    return out
+
+
+def disconnected_traces(U, kappa, T, L, bc, eta, domains=None, n_hop=8, tol=1e-12, maxit=100000, method=0):
+    """Per-source, per-time-slice stochastic estimates of sum_xvec tr{gamma5 D_Lambda^-1(x, x)}
+    (Eq. 27 of Sec. 5, with the Dirichlet block D_Lambda of each domain of
+    Sec. 4.1 in place of D):
+      tau[i, t] = sum_xvec eta_i^+(x) [(kappa D_hop)^n_hop D_Lambda^-1 gamma5 eta_i](x),  x_0 = t,
+    eta: (nsrc, V, 12) whole-lattice sources; each domain (t0, nt) of `domains` (None = the
+    whole lattice) solves with the restriction of eta to it and fills the slices it covers.
+    Returns tau (nsrc, T) complex (zero on slices no domain covers)."""
+    L3 = L ** 3
+    eta = np.asarray(eta, dtype=np.complex128)
+    nsrc = eta.shape[0]
+    tau = np.zeros((nsrc, T), dtype=np.complex128)
+    for dom in (domains if domains is not None else [None]):
+        t0, nt = _norm_dom(T, dom)
+        e = slab_extract(T, L, eta, dom) if dom is not None else eta
+        x, _, _, st = solve(U, kappa, T, L, bc, gamma5(e), dom=dom, tol=tol, maxit=maxit, method=method)
+        if st != 0:
+            raise RuntimeError("disconnected-trace solve did not converge")
+        y = hop_power(U, kappa, T, L, bc, x, n_hop, dom)
+        prod = (e.conj() * y).reshape(nsrc, nt, L3 * 12).sum(axis=2)
+        for k in range(nt):
+            tau[:, (t0 + k) % T] = prod[:, k]
+    return tau
+
+
+def disconnected_correlator(L, tau):
+    """Two-trace product of the disconnected contraction, summed over xvec and yvec (W_Pd of
+    Eq. 4; its factorised term W_Pd^(f) of Eq. 19 when tau holds the traces of the domains that
+    contain x_0 and y_0):
+      C[y0, x0] = 1/L^3 * 1/(n (n - 1)) sum_{i != j} tau_i(x0) tau_j(y0)
+    over distinct sources, so that the estimate of the product is unbiased.  tau: (n, T).
+    Returns C (T, T) complex."""
+    tau = np.asarray(tau, dtype=np.complex128)
+    n = tau.shape[0]
+    C = np.zeros((tau.shape[1], tau.shape[1]), dtype=np.complex128)
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                C += np.outer(tau[j], tau[i])
+    return C / (n * (n - 1) * L ** 3)
 
 
 def link_grad(T, L, bc, dom, X, Y, coeff=1.0, grad=None):

@@ -1,4 +1,4 @@
-// projection.hip -- quark-line projection (Sec. 3.3, Eqs. 15-16).
+// projection.hip -- quark-line projection (Sec. 3.3, Eqs. 16-17).
 //
 // The factorised propagator crosses a frontier through the field on one time
 // slice (the slice the frontier hop reads).  Projecting that field on N_m

@@ -1,4 +1,4 @@
-"""GPU parity of the quark-line projection (Sec. 3.3, Eqs. 15-16) against the oracle.
+"""GPU parity of the quark-line projection (Sec. 3.3, Eqs. 16-17) against the oracle.
 
 - projection vectors: orthonormal, in the range of the hop's spin projector, and
   spanning the oracle's subspace (bases agree up to a unitary, so the projectors

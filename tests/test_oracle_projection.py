@@ -1,4 +1,4 @@
-"""Pins of the oracle's quark-line projection (Sec. 3.3, Eqs. 15-16).
+"""Pins of the oracle's quark-line projection (Sec. 3.3, Eqs. 16-17).
 
 - the projection vectors are orthonormal and lie in the range of the frontier hop's
   spin projector (1 +- gamma_0)/2;
