@@ -43,8 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection "
-                    "(all = every part but projection, which takes about a minute a step)")
+    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection,disconnected "
+                    "(all = every part but projection and disconnected, which take about a minute a step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (10 times), the reference that scales "
                          "the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -164,6 +164,13 @@ def main():
         gp.manual_seed(w["stencil_seed"] + 1)
         proj_v0 = torch.randn((proj_nvec, 12, proj_pi[1] * L ** 3), dtype=torch.complex128, device=dev,
                               generator=gp)
+    if "disconnected" in parts:
+        # disconnected pseudoscalar: Dirichlet domains [0, 33) and [33, 64) (the cut between
+        # slices 32 and 33), 100 Gaussian volume sources, 8 powers of kappa D_hop
+        disc_doms, disc_nsrc, disc_hop = [(0, 33), (33, 31)], 100, 8
+        gd = torch.Generator(device=dev)
+        gd.manual_seed(w["stencil_seed"] + 2)
+        disc_eta = torch.randn((disc_nsrc, 12, V), dtype=torch.complex128, device=dev, generator=gd)
     if "force" in parts:
         wf = WORKLOADS["force-32x16^3"]
         Uf = dd.pack_links(random_links(wf["T"], wf["L"], wf["eps"], wf["link_seed"]))
@@ -257,6 +264,24 @@ def main():
                 for t in (0, 8, 16, 32):
                     ph["projection"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
             del Sf, phi
+        if "disconnected" in parts:
+            t0 = time.perf_counter()
+            tau_f, dst = dd.disconnected_traces(ctx, U64, kappa, disc_eta, disc_doms, disc_hop, pmx)
+            Cf = dd.disconnected_correlator(ctx, tau_f)
+            t1 = time.perf_counter()
+            tau_w, wst = dd.disconnected_traces(ctx, U64, kappa, disc_eta, None, disc_hop, pmx)
+            Cw = dd.disconnected_correlator(ctx, tau_w)
+            t2 = time.perf_counter()
+            ph["disconnected"] = dict(ms=(t2 - t0) * 1e3, ms_domains=(t1 - t0) * 1e3, ms_whole=(t2 - t1) * 1e3,
+                                      nsrc=disc_nsrc, n_hop=disc_hop, domain_iters=[s["iters"] for s in dst],
+                                      whole_iters=wst[0]["iters"],
+                                      max_true_rel_resid=max(max(s["true_rel_resid"]) for s in dst + wst))
+            if record:
+                for d in (2, 8, 16, 32):  # x0, y0 equidistant from the cut at 32
+                    x0, y0 = 32 - d // 2, 32 + d // 2
+                    ph["disconnected"][f"C_f[{d}]"] = float(Cf[y0, x0].real)
+                    ph["disconnected"][f"C_full[{d}]"] = float(Cw[y0, x0].real)
+            del tau_f, tau_w
         if "batched" in parts:
             t0 = time.perf_counter()
             bst = dd.block_solve_batched(bctx, bitems, pmx)

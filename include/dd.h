@@ -219,6 +219,36 @@ dd_status dd_factorized_propagator_projected(dd_ctx* ctx, const void* U, double 
                                              void* S_fact, void* S_exact, dd_solve_stats* stats);
 
 /*
+ * Stochastic traces of the disconnected pseudoscalar contraction (Sec. 4.1,
+ * Eqs. 18-19, with the estimator of Sec. 5, Eq. 27):
+ *   tau[i][t] = sum_xvec eta_i^+(x) [(kappa D_hop)^n_hop D_Lambda^-1 gamma5 eta_i](x),
+ * x_0 = t, for every source i and every slice t of the slabs doms[0..ndom-1]
+ * (disjoint; D_Lambda is the Dirichlet block of the slab holding t and
+ * kappa D_hop = 1 - 2 kappa D_Lambda), or of the whole lattice with D when
+ * doms = NULL and ndom = 0.  For n_hop <= 8 its mean over Gaussian sources is
+ * sum_xvec tr{gamma5 D_Lambda^-1(x, x)} (the paper uses n_hop = 8).
+ * eta: complex128 [nsrc][12][V] whole-lattice sources (device, read only);
+ * tau: complex128 [nsrc][T] (device, output; zero on slices no slab covers).
+ * Sources are solved DD_MAX_RHS at a time.  0 <= n_hop <= 16.  stats: NULL or
+ * max(ndom, 1) entries, one per domain, summed over its solves
+ * (true_rel_resid[j] = the largest over sources j mod DD_MAX_RHS).  Returns
+ * DD_ERR_NOCONV if a solve missed tol (tau still written).  Synchronises.
+ */
+dd_status dd_disconnected_traces(dd_ctx* ctx, const void* U, double kappa, const dd_domain* doms, int ndom,
+                                 int nsrc, const void* eta, int n_hop, const dd_solver_params* params,
+                                 void* tau, dd_solve_stats* stats);
+
+/*
+ * Two-trace product of the disconnected contraction over distinct sources
+ * (W_Pd of Eq. 4 summed over xvec and yvec; its factorised term W_Pd^(f) of
+ * Eq. 19 when tau comes from slabs holding x_0 and y_0):
+ *   C_host[y0][x0] = 1/(nsrc (nsrc - 1) L^3) sum_{i != j} tau[i][x0] tau[j][y0],
+ * complex (2 T^2 doubles, host, output).  tau: complex128 [nsrc][T] (device),
+ * nsrc >= 2.  Synchronises.
+ */
+dd_status dd_disconnected_correlator(dd_ctx* ctx, int nsrc, const void* tau, double* C_host);
+
+/*
  * Pion two-point function of a whole-lattice propagator S (complex128
  * [ncol][12][V]) from a source on time slice t_src (Eq. 4, connected W_Pc):
  *   C_host[t] = sum_xvec sum_{c,j} |S_cj((t_src + t) mod T, xvec)|^2, t = 0..T-1,

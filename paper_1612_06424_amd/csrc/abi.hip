@@ -503,6 +503,45 @@ dd_status dd_projection_basis(dd_ctx* c, const void* U, double kappa, const dd_d
                             (cpx<double>*)phi, *p, stats);
 }
 
+dd_status dd_disconnected_traces(dd_ctx* c, const void* U, double kappa, const dd_domain* doms, int ndom, int nsrc,
+                                 const void* eta, int n_hop, const dd_solver_params* p, void* tau,
+                                 dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK) return e;
+    const dd_lattice& lat = c->lat;
+    const int T = lat.T;
+    if (nsrc < 1) return fail(c, DD_ERR_ARG, "nsrc must be >= 1");
+    if (n_hop < 0 || n_hop > 16) return fail(c, DD_ERR_ARG, "n_hop must be in [0, 16]");
+    if (doms == nullptr && ndom != 0) return fail(c, DD_ERR_ARG, "doms is NULL but ndom != 0");
+    if (doms != nullptr) {
+        if (ndom < 1) return fail(c, DD_ERR_ARG, "ndom must be >= 1");
+        std::vector<char> used(T, 0);
+        for (int k = 0; k < ndom; k++) {
+            if ((e = check_dom(c, &doms[k])) != DD_OK) return e;
+            for (int j = 0; j < doms[k].nt; j++) {
+                const int t = (doms[k].t0 + j) % T;
+                if (used[t]) return fail(c, DD_ERR_ARG, "domains overlap");
+                used[t] = 1;
+            }
+        }
+    }
+    const size_t V = vlink(lat);
+    CHECK_PTR(c, U, 36 * V * 16, 16, "U");
+    CHECK_PTR(c, eta, (size_t)nsrc * 12 * V * 16, 16, "eta");
+    CHECK_PTR(c, tau, (size_t)nsrc * T * 16, 16, "tau");
+    return disconnected_traces(c, (const cpx<double>*)U, kappa, doms, ndom, nsrc, (const cpx<double>*)eta, n_hop, *p,
+                               (cpx<double>*)tau, stats);
+}
+
+dd_status dd_disconnected_correlator(dd_ctx* c, int nsrc, const void* tau, double* C_host) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (nsrc < 2) return fail(c, DD_ERR_ARG, "nsrc must be >= 2 (the product runs over distinct sources)");
+    if (C_host == nullptr) return fail(c, DD_ERR_ARG, "C_host is NULL");
+    CHECK_PTR(c, tau, (size_t)nsrc * c->lat.T * 16, 16, "tau");
+    return disconnected_correlator(c, nsrc, (const cpx<double>*)tau, C_host);
+}
+
 dd_status dd_pion_correlator(dd_ctx* c, const void* S, int ncol, int t_src, double* C_host) {
     if (c == nullptr) return DD_ERR_ARG;
     if (ncol < 1 || ncol > 4 * DD_MAX_RHS) return fail(c, DD_ERR_ARG, "ncol out of range");

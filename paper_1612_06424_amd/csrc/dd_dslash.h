@@ -24,6 +24,8 @@
 //   EPI_TS       <D in, in>, |D in|^2   (BiCGStab omega)
 //   EPI_RESID    stores aux - D in and its norm^2 (true residual)
 //   EPI_NORM     |D in|^2               (CGNR)
+//   EPI_HOP      nothing; stores kappa D_hop in (the hopping term alone, Sec. 5:
+//                2 kappa D = 1 - kappa D_hop), with `mass` carrying kappa
 #pragma once
 
 #include "dd_internal.h"
@@ -133,7 +135,8 @@ __device__ __forceinline__ void dslash_tile(const Geo& g, const cpx<R>* __restri
             for (int c = 0; c < 12; c++) {
                 const uint32_t so = (uint32_t)c * cs;
                 const cpx<R> pc = cur[c];
-                cpx<R> r = mk<R>(mass * pc.re - half * a[c].re, mass * pc.im - half * a[c].im);
+                cpx<R> r = EPI == EPI_HOP ? mk<R>(mass * a[c].re, mass * a[c].im)
+                                          : mk<R>(mass * pc.re - half * a[c].re, mass * pc.im - half * a[c].im);
                 cpx<R> q = mk<R>(0, 0);
                 if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
                 if (EPI == EPI_RESID) r = q - r;
@@ -159,7 +162,7 @@ __device__ __forceinline__ void dslash_tile(const Geo& g, const cpx<R>* __restri
             }
         }
     }
-    if (EPI != EPI_STORE) block_sum3<NT>(d0, d1, d2, slot);
+    if (EPI != EPI_STORE && EPI != EPI_HOP) block_sum3<NT>(d0, d1, d2, slot);
 }
 
 }  // namespace dd

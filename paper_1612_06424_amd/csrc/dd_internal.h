@@ -172,7 +172,7 @@ enum Slot {
     W_PART, W_STATE, W_STATE32, W_DOTS,
     W_AUX0, W_AUX1, W_AUX2, W_AUX3, W_AUX4,
     W_SEGS, W_SEGN, W_EO_B, W_EO_X, W_EO_BHAT, W_EO_T64, W_EO_T32, W_EO_U64, W_BATCH0, W_BATCH1, W_BATCH2, W_BATCH3, W_BATCH4,
-    W_U32C, W_LDEV, W_PROJ_V, W_PROJ_G, W_PROJ_R,
+    W_U32C, W_LDEV, W_PROJ_V, W_PROJ_G, W_PROJ_R, W_DISC0, W_DISC1, W_DISC2, W_DISC3,
     W_NSLOTS
 };
 
@@ -198,7 +198,8 @@ enum Epi {
     EPI_DOT_AUX,     // out = M in; partial <aux, out>
     EPI_TS,          // out = M in; partials <out, in>, |out|^2
     EPI_RESID,       // out = aux - M in; partial |out|^2
-    EPI_NORM         // out = M in; partial |out|^2
+    EPI_NORM,        // out = M in; partial |out|^2
+    EPI_HOP          // out = kappa D_hop in = in - 2 kappa D in (no mass term, no partials; dag = 0)
 };
 
 // M = D (dag = 0) or D^+ = gamma5 D gamma5 (dag = 1) on the field geometry g.
@@ -407,5 +408,15 @@ dd_status projection_basis(dd_ctx* c, const cpx<double>* U, double kappa, const 
 // slice k of field ([ncol][12][nt L^3]) <- sum_i phi_i phi_i^+ (that slice)
 dd_status project_slice(dd_ctx* c, int L3, int nt, int k, int ncol, cpx<double>* field, int nvec,
                         const cpx<double>* phi);
+
+// ---------------------------------------------------------------- disconnected contraction
+// tau ([nsrc][T], device) = per-source, per-slice estimates of tr{gamma5 D_Lambda^-1} with
+// n_hop powers of kappa D_hop, over the slabs doms (NULL: the whole lattice); eta
+// [nsrc][12][V].  stats: NULL or one entry per domain.  Synchronises.
+dd_status disconnected_traces(dd_ctx* c, const cpx<double>* U, double kappa, const dd_domain* doms, int ndom,
+                              int nsrc, const cpx<double>* eta, int n_hop, const dd_solver_params& p,
+                              cpx<double>* tau, dd_solve_stats* stats);
+// C_host[y0][x0] (complex, T x T) = the two-trace product over distinct sources
+dd_status disconnected_correlator(dd_ctx* c, int nsrc, const cpx<double>* tau, double* C_host);
 
 }  // namespace dd

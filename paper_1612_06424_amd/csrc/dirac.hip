@@ -52,6 +52,10 @@ void launch_epi(dd_ctx* c, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R 
             hipLaunchKernelGGL((k_dslash<R, DAG, EPI_RESID, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
                                out, aux, ncol, tc, remap, partial, st);
             break;
+        case EPI_HOP:
+            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_HOP, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
+                               out, aux, ncol, tc, remap, partial, st);
+            break;
         default:
             hipLaunchKernelGGL((k_dslash<R, DAG, EPI_NORM, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
                                out, aux, ncol, tc, remap, partial, st);
@@ -80,7 +84,7 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
                          int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol,
                          double* partial, const ColState* st) {
     const dim3 grid((unsigned)stencil_blocks(g, sc) * (unsigned)ncol);
-    const R mass = R(1.0 / (2.0 * kappa));
+    const R mass = R(epi == EPI_HOP ? kappa : 1.0 / (2.0 * kappa));  // EPI_HOP scales the hop by kappa
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_NT_CASE(NTV)                                                                                     \

@@ -38,6 +38,7 @@ EXPORTS = [
     "dd_factorized_propagator", "dd_pion_correlator", "dd_block_solve_backward", "dd_domain_action",
     "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing_count",
     "dd_kernel_timing", "dd_projection_basis", "dd_factorized_propagator_projected",
+    "dd_disconnected_traces", "dd_disconnected_correlator",
 ]
 
 
@@ -85,6 +86,9 @@ _sig = {
     "dd_projection_basis": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _i, _i, _i, _vp, _vp,
                              C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
     "dd_pion_correlator": ([_vp, _vp, _i, _i, C.POINTER(C.c_double)], _i),
+    "dd_disconnected_traces": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _i, _vp, _i, C.POINTER(dd_solver_params),
+                                _vp, C.POINTER(dd_solve_stats)], _i),
+    "dd_disconnected_correlator": ([_vp, _i, _vp, C.POINTER(C.c_double)], _i),
     "dd_block_solve_backward": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, _vp,
                                  C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
     "dd_domain_action": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, C.POINTER(C.c_double),
@@ -249,6 +253,32 @@ def pion_correlator(ctx, S, t_src):
     out = (C.c_double * ctx.T)()
     ctx._check(_lib.dd_pion_correlator(ctx._h, _ptr(S, torch.complex128, "S"), S.shape[0], int(t_src), out))
     return np.array(list(out))
+
+
+def disconnected_traces(ctx, U, kappa, eta, doms=None, n_hop=8, params=None, tau=None, allow_noconv=False):
+    """Per-source, per-slice stochastic traces tau (complex128 (nsrc, T)) of gamma5 D_Lambda^-1
+    with n_hop powers of kappa D_hop, from whole-lattice sources eta (complex128 (nsrc, 12, V)),
+    over the slabs doms (None: the whole lattice).  Returns (tau, per-domain stats)."""
+    params = params or solver_params()
+    nsrc = eta.shape[0]
+    if tau is None:
+        tau = torch.empty((nsrc, ctx.T), dtype=torch.complex128, device=eta.device)
+    nd = len(doms) if doms else 0
+    darr = (dd_domain * nd)(*[dd_domain(int(a), int(b)) for a, b in doms]) if nd else None
+    stats = (dd_solve_stats * max(nd, 1))()
+    ctx._check(_lib.dd_disconnected_traces(
+        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), darr, nd, nsrc, _ptr(eta, torch.complex128, "eta"),
+        int(n_hop), C.byref(params), _ptr(tau, torch.complex128, "tau"), stats),
+        allow=(DD_ERR_NOCONV,) if allow_noconv else ())
+    return tau, [s.as_dict() for s in stats]
+
+
+def disconnected_correlator(ctx, tau):
+    """C[y0, x0] = 1/(n (n-1) L^3) sum_{i != j} tau_i(x0) tau_j(y0) as numpy complex128 (T, T)."""
+    out = (C.c_double * (2 * ctx.T * ctx.T))()
+    ctx._check(_lib.dd_disconnected_correlator(ctx._h, tau.shape[0], _ptr(tau, torch.complex128, "tau"), out))
+    a = np.array(list(out)).reshape(ctx.T, ctx.T, 2)
+    return a[..., 0] + 1j * a[..., 1]
 
 
 def block_solve_backward(ctx, U, kappa, x, grad_x, dom=None, params=None, grad_U=None):

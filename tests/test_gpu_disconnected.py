@@ -1,0 +1,129 @@
+"""GPU parity of the disconnected-contraction traces (Sec. 4.1, Eqs. 18-19; the estimator of
+Sec. 5, Eq. 27) and of the two-trace product against the oracle, plus a property of the
+64x32^3 workload the bench times.
+
+Bars: FP64 within 1e-10 of the oracle (relative norm of tau), mixed within 1e-6; the product
+within 1e-12 of max|tau|^2 / L^3 on identical traces.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import gaussian_field, lib, random_links, relerr, step
+from paper_1612_06424_amd.inputs import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+
+_REF = {}  # oracle traces, shared by the two precisions
+
+
+def _ref(U, kappa, T, L, bc, eta, doms, n_hop):
+    key = (T, L, bc, str(doms), eta.shape[0], n_hop)
+    if key not in _REF:
+        _REF[key] = O.disconnected_traces(U, kappa, T, L, bc, eta, doms, n_hop=n_hop, tol=1e-13, method=1)
+    return _REF[key]
+
+
+def _params(dd, prec):
+    return dd.solver_params(tol=1e-13 if prec == "fp64" else 1e-10, max_iter=20000,
+                            prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED, solver=dd.DD_CGNR)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("T,L,bc,doms,nsrc", [
+    (16, 4, -1, [(0, 9), (9, 7)], 14),            # two slabs, 12 + 2 sources
+    (16, 4, -1, None, 13),                         # whole lattice
+    (16, 4, 0, [(14, 5), (3, 11)], 5),             # a slab across the (Dirichlet) time edge
+    (12, 5, -1, [(2, 4), (7, 3)], 3),              # odd L, slabs not covering the lattice
+])
+def test_traces_vs_oracle(prec, T, L, bc, doms, nsrc):
+    dd = lib()
+    kappa = 0.13
+    U = random_links(T, L, 0.3, 3000 + T + L)
+    eta = gaussian_field(T * L ** 3, nsrc, 3001)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U)
+    p = _params(dd, prec)
+    bar = 1e-10 if prec == "fp64" else 1e-6
+    for n_hop in (0, 1, 8):
+        step(f"disconnected traces T={T} L={L} bc={bc} doms={doms} nsrc={nsrc} n_hop={n_hop} {prec}")
+        ref = _ref(U, kappa, T, L, bc, eta, doms, n_hop)
+        tau, stats = dd.disconnected_traces(ctx, Ud, kappa, dd.pack_field(eta), doms, n_hop, p)
+        got = tau.cpu().numpy()
+        assert relerr(got, ref) < bar, n_hop
+        assert len(stats) == (len(doms) if doms else 1)
+        assert all(s["nrhs"] == nsrc and s["iters"] > 0 for s in stats)
+        assert all(max(s["true_rel_resid"]) <= p.tol for s in stats)
+        if doms:
+            covered = {(t0 + k) % T for t0, nt in doms for k in range(nt)}
+            assert all(np.all(got[:, t] == 0) for t in range(T) if t not in covered)
+
+
+def test_correlator_vs_oracle():
+    dd = lib()
+    step("disconnected correlator")
+    T, L = 16, 4
+    ctx = dd.Context(T, L, -1)
+    rng = np.random.default_rng(3002)
+    for n in (2, 13, 100):
+        tau = rng.standard_normal((n, T)) + 1j * rng.standard_normal((n, T))
+        C = dd.disconnected_correlator(ctx, torch.as_tensor(tau).to("cuda"))
+        ref = O.disconnected_correlator(L, tau)
+        assert np.abs(C - ref).max() < 1e-12 * np.abs(tau).max() ** 2 / L ** 3
+
+
+def test_errors():
+    dd = lib()
+    step("disconnected errors")
+    T, L = 16, 4
+    ctx = dd.Context(T, L, -1)
+    Ud = dd.pack_links(random_links(T, L, 0.3, 3003))
+    eta = torch.zeros((2, 12, T * L ** 3), dtype=torch.complex128, device="cuda")
+    for kw in (dict(doms=[(0, 9), (8, 4)]), dict(n_hop=-1), dict(n_hop=17)):
+        with pytest.raises(dd.DDError) as e:
+            dd.disconnected_traces(ctx, Ud, 0.13, eta, **kw)
+        assert e.value.status == dd.DD_ERR_ARG
+    with pytest.raises(dd.DDError) as e:
+        dd.disconnected_correlator(ctx, torch.zeros((1, T), dtype=torch.complex128, device="cuda"))
+    assert e.value.status == dd.DD_ERR_ARG
+
+
+def test_hop_identity_on_the_64x32_workload():
+    """H^8 D^-1 = D^-1 - 2 kappa sum_{k<8} H^k (H = kappa D_hop = 1 - 2 kappa D), so per source
+    and slice tau(n_hop = 8) = tau(n_hop = 0) - 2 kappa sum_{k<8} [eta^+ H^k gamma5 eta](t):
+    checked on 12 sources on the two Dirichlet slabs [0, 33) and [33, 64) of the 64x32^3
+    workload, in the launch shapes the bench uses; the right-hand side needs only D."""
+    dd = lib()
+    w = WORKLOADS["64x32^3"]
+    T, L, kappa = w["T"], w["L"], w["kappa"]
+    L3 = L ** 3
+    step("disconnected hop identity 64x32^3")
+    U = dd.pack_links(random_links(T, L, w["eps"], w["link_seed"]))
+    ctx = dd.Context(T, L, w["bc"])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3004)
+    eta = torch.randn((12, 12, T * L3), dtype=torch.complex128, device="cuda", generator=g)
+    doms = [(0, 33), (33, 31)]
+    p = dd.solver_params(tol=1e-10, max_iter=20000, prec=dd.DD_MIXED, solver=dd.DD_CGNR)
+    tau0, _ = dd.disconnected_traces(ctx, U, kappa, eta, doms, 0, p)
+    tau8, _ = dd.disconnected_traces(ctx, U, kappa, eta, doms, 8, p)
+    rhs = torch.zeros_like(tau0)
+    for t0, nt in doms:
+        e = eta[:, :, t0 * L3:(t0 + nt) * L3].contiguous()
+        v = e.clone()
+        v[:, 6:] = -v[:, 6:]                                  # gamma5 eta
+        acc = torch.zeros((12, nt), dtype=torch.complex128, device="cuda")
+        for k in range(8):
+            acc += (e.conj() * v).reshape(12, 12, nt, L3).sum(dim=(1, 3))
+            Dv = dd.apply_dirac(ctx, U, kappa, v, (t0, nt))
+            v = v - 2 * kappa * Dv
+        rhs[:, t0:t0 + nt] = acc
+    want = tau0 - 2 * kappa * rhs
+    # both sides carry the mixed solves' error (true residual 1e-10): the mixed bar
+    assert (torch.linalg.vector_norm(tau8 - want) / torch.linalg.vector_norm(tau0)).item() < 1e-6
+    # hermitian per source on each slab
+    for t0, nt in doms:
+        tot = tau8[:, t0:t0 + nt].sum(dim=1)
+        assert (tot.imag.abs().max() / tot.abs().max()).item() < 1e-6
