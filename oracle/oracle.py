@@ -402,6 +402,75 @@ def disconnected_correlator(L, tau):
     return C / (n * (n - 1) * L ** 3)
 
 
+def charge_conjugation():
+    """C = gamma_0 gamma_2: C gamma_mu C^-1 = -gamma_mu^T in the oracle's basis (the nucleon
+    interpolator's charge conjugation, which the text leaves to its conventions)."""
+    g = gamma_matrices()
+    return g[0] @ g[2]
+
+
+def nucleon_parity_projector():
+    """P_- = (1 - gamma_0)/2 of the factorised nucleon contractions (Eqs. 23-24)."""
+    return 0.5 * (np.eye(4) - gamma_matrices()[0])
+
+
+def baryon_blocks(L, s):
+    """Colourless spinors of Eq. 25, summed over each time slice of the field:
+      B[t, i, j, k, alpha] = sum_xvec eps^{abc} (s_i^{aT}(x) C gamma5 s_j^b(x)) s_k^c_alpha(x)
+    for s (n, nt L^3, 12) (component = spin * 3 + colour).  Returns (nt, n, n, n, 4)."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    nt = s.shape[1] // L ** 3
+    q = s.reshape(n, nt, L ** 3, 4, 3)
+    eps = np.zeros((3, 3, 3))
+    for a, b, c in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        eps[a, b, c] = 1.0
+        eps[b, a, c] = -1.0
+    cg5 = charge_conjugation() @ gamma_matrices()[4]
+    return np.einsum("abc,itxra,rs,jtxsb,ktxpc->tijkp", eps, q, cg5, q, q, optimize=True)
+
+
+def nucleon_lines(U, kappa, T, L, bc, gbar, gstar, t_phi, phi, x0, tol=1e-12, maxit=100000, method=0):
+    """The two factors of each projected quark line (Eq. 26):
+      xi_i^T(x) = [phi_i^+ D_Gbar^-1](x) on the time slice x0 of Gbar, and
+      eta_i(y) = [D_Gstar^-1 D_{Gstar, dGstar} phi_i](y) on Gstar,
+    phi (n, L^3, 12) living on the slice t_phi of Gbar just outside Gstar (D_{Gstar,dGstar}
+    is the frontier block of D from that slice into Gstar).  xi_i(x) = conj([D_Gbar^-1+ phi_i](x)),
+    and D^-1+ = gamma5 D^-1 gamma5 (gamma5-hermiticity).  Returns (xi (n, L^3, 12),
+    eta (n, |Gstar|, 12))."""
+    L3 = L ** 3
+    phi = np.asarray(phi, dtype=np.complex128)
+    n = phi.shape[0]
+    gb0, gbn = _norm_dom(T, gbar)
+    kp = (t_phi - gb0) % T
+    kx = (x0 - gb0) % T
+    if kp >= gbn or kx >= gbn:
+        raise ValueError("t_phi and x0 must lie in Gbar")
+    src = np.zeros((n, gbn * L3, 12), dtype=np.complex128)
+    src[:, kp * L3:(kp + 1) * L3] = phi
+    z, _, _, st = solve(U, kappa, T, L, bc, gamma5(src), dom=gbar, tol=tol, maxit=maxit, method=method)
+    if st != 0:
+        raise RuntimeError("nucleon line solve on Gbar did not converge")
+    xi = np.conj(gamma5(z))[:, kx * L3:(kx + 1) * L3]
+    b = block_apply(U, kappa, T, L, bc, gstar, (t_phi, 1), phi)
+    eta, _, _, st = solve(U, kappa, T, L, bc, b, dom=gstar, tol=tol, maxit=maxit, method=method)
+    if st != 0:
+        raise RuntimeError("nucleon line solve on Gstar did not converge")
+    return xi, eta
+
+
+def nucleon_factorized(L, Bx, By):
+    """Factorised nucleon Wick contractions summed over xvec and yvec (Eqs. 22-24):
+      W1[y0, x0] = - sum_{ijk} Bx[x0, j, i, k]^T gamma5 P_- By[y0, i, j, k]
+      W2[y0, x0] = - sum_{ijk} Bx[x0, k, i, j]^T gamma5 P_- By[y0, i, j, k]
+    with Bx the blocks of the xi lines and By those of the eta lines (baryon_blocks).
+    Returns (W1, W2, C_f = (W1 - W2) / L^3), each (nty, ntx)."""
+    M = gamma_matrices()[4] @ nucleon_parity_projector()
+    W1 = -np.einsum("xjika,ab,yijkb->yx", Bx, M, By, optimize=True)
+    W2 = -np.einsum("xkija,ab,yijkb->yx", Bx, M, By, optimize=True)
+    return W1, W2, (W1 - W2) / L ** 3
+
+
 def link_grad(T, L, bc, dom, X, Y, coeff=1.0, grad=None):
     """grad += coeff * d/dU [-2 Re <Y, D_Lambda X>] at fixed X, Y, shape (V, 4, 3, 3)."""
     t0, nt = _norm_dom(T, dom)
