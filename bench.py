@@ -248,10 +248,10 @@ def main():
             del Sf
         if "projection" in parts:
             t0 = time.perf_counter()
-            phi, pst = dd.projection_basis(ctx, U64, kappa, proj_pi, proj_t, +1, proj_v0, proj_iter, pmx)
+            basis, pst = dd.projection_basis(ctx, U64, kappa, proj_pi, proj_t, +1, proj_v0, proj_iter, pmx)
             t1 = time.perf_counter()
             Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx,
-                                                  projections={proj_t: phi})
+                                                  projections={proj_t: basis})
             Cf = dd.pion_correlator(ctx, Sf, src[0])
             t2 = time.perf_counter()
             nd = len(w["domains"])
@@ -263,7 +263,7 @@ def main():
                 Ce = corr_ref["Ce"]
                 for t in (0, 8, 16, 32):
                     ph["projection"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
-            del Sf, phi
+            del Sf, basis
         if "disconnected" in parts:
             t0 = time.perf_counter()
             tau_f, dst = dd.disconnected_traces(ctx, U64, kappa, disc_eta, disc_doms, disc_hop, pmx)
