@@ -249,6 +249,49 @@ dd_status dd_disconnected_traces(dd_ctx* ctx, const void* U, double kappa, const
 dd_status dd_disconnected_correlator(dd_ctx* ctx, int nsrc, const void* tau, double* C_host);
 
 /*
+ * The two factors of the quark lines of the factorised nucleon (Sec. 4.2,
+ * Eq. 26), cut by nvec orthonormal vectors phi_i on the time slice t_phi
+ * (complex128 [nvec][12][L^3], device; e.g. from dd_projection_basis):
+ *   xi_i^T(x) = [phi_i^+ D_gbar^-1](x) on the slice x0 of gbar, returned as
+ *     xi (complex128 [nvec][12][L^3]: xi_i(x) = conj([D_gbar^-1+ phi_i](x))),
+ *   eta_i(y) = [D_gstar^-1 D_{gstar, dgstar} phi_i](y) on the slab gstar
+ *     (complex128 [nvec][12][gstar->nt L^3]),
+ * so that D^-1(y, x) ~ -sum_i eta_i(y) xi_i^T(x) (Eq. 17).  t_phi and x0 lie in
+ * gbar, t_phi is a time neighbour of gstar outside it (the slice the frontier
+ * hop into gstar reads).  1 <= nvec <= min(256, 6 L^3).  stats: NULL or 2
+ * entries (the gbar solves with D^+, then the gstar solves).  Returns
+ * DD_ERR_NOCONV if a solve missed tol.  Synchronises.
+ */
+dd_status dd_nucleon_lines(dd_ctx* ctx, const void* U, double kappa, const dd_domain* gbar,
+                           const dd_domain* gstar, int t_phi, int nvec, const void* phi, int x0, void* xi,
+                           void* eta, const dd_solver_params* params, dd_solve_stats* stats);
+
+/*
+ * Colourless spinors of Eq. 25 summed over each time slice of nt slices:
+ *   B[t][k][alpha][i][j] = sum_xvec eps^{abc} (s_i^{aT} C gamma5 s_j^b)(x) s_k^c_alpha(x),
+ * C = gamma_0 gamma_2 in the library's chiral basis.  s: complex128
+ * [nvec][12][nt L^3] (device, read only); B: complex128 [nt][nvec][4][nvec][nvec]
+ * (device, output; must not overlap s).  1 <= nvec <= 256.  FP64 (the
+ * product over sites runs on the matrix cores through rocBLAS, in chunks of
+ * sites whose diquarks stay below 2 GiB; the environment variable
+ * DD_BLOCK_CHUNK caps the sites per chunk).  Asynchronous.
+ */
+dd_status dd_baryon_blocks(dd_ctx* ctx, int nvec, int nt, const void* s, void* B);
+
+/*
+ * The factorised nucleon Wick contractions summed over xvec and yvec
+ * (Eqs. 22-24), from blocks Bx of the xi lines on ntx source slices and By of
+ * the eta lines on nty sink slices (layout of dd_baryon_blocks):
+ *   W1[y][x] = -sum_{ijk} Bx[x](j, i, k)^T gamma5 P_- By[y](i, j, k),
+ *   W2[y][x] = -sum_{ijk} Bx[x](k, i, j)^T gamma5 P_- By[y](i, j, k),
+ * P_- = (1 - gamma_0)/2; C_N^(f)(y0, x0) = (W1 - W2) / L^3.  W_host: host,
+ * 2 x nty x ntx complex (W1 then W2, 4 nty ntx doubles).  Sums in a fixed order.
+ * Synchronises.
+ */
+dd_status dd_nucleon_contract(dd_ctx* ctx, int nvec, int ntx, const void* Bx, int nty, const void* By,
+                              double* W_host);
+
+/*
  * Pion two-point function of a whole-lattice propagator S (complex128
  * [ncol][12][V]) from a source on time slice t_src (Eq. 4, connected W_Pc):
  *   C_host[t] = sum_xvec sum_{c,j} |S_cj((t_src + t) mod T, xvec)|^2, t = 0..T-1,

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdd.so")
 SOURCES = ["abi.hip", "dirac.hip", "blas.hip", "krylov.hip", "solver.hip", "evenodd.hip", "batched.hip", "tune.hip",
-           "projection.hip", "disconnected.hip"]
+           "projection.hip", "disconnected.hip", "nucleon.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -48,7 +48,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
             objs = dict(zip(order, pool.map(compile_one, order)))
         tmp = LIB + ".tmp"
-        cmd = [hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", *[objs[s] for s in SOURCES], "-o", tmp]
+        cmd = [hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", *[objs[s] for s in SOURCES], "-o", tmp,
+               "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

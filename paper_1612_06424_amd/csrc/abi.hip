@@ -216,6 +216,7 @@ void dd_destroy(dd_ctx* c) {
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->host_state) (void)hipHostFree(c->host_state);
     if (c->host_dots) (void)hipHostFree(c->host_dots);
+    blas_release(c);
     delete c;
 }
 
@@ -540,6 +541,59 @@ dd_status dd_disconnected_correlator(dd_ctx* c, int nsrc, const void* tau, doubl
     if (C_host == nullptr) return fail(c, DD_ERR_ARG, "C_host is NULL");
     CHECK_PTR(c, tau, (size_t)nsrc * c->lat.T * 16, 16, "tau");
     return disconnected_correlator(c, nsrc, (const cpx<double>*)tau, C_host);
+}
+
+dd_status dd_nucleon_lines(dd_ctx* c, const void* U, double kappa, const dd_domain* gbar, const dd_domain* gstar,
+                           int t_phi, int nvec, const void* phi, int x0, void* xi, void* eta,
+                           const dd_solver_params* p, dd_solve_stats* stats) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (gbar == nullptr || gstar == nullptr) return fail(c, DD_ERR_ARG, "gbar and gstar must be slabs");
+    dd_status e;
+    if ((e = check_dom(c, gbar)) != DD_OK || (e = check_dom(c, gstar)) != DD_OK || (e = check_params(c, p)) != DD_OK ||
+        (e = check_kappa(c, kappa)) != DD_OK)
+        return e;
+    const dd_lattice& lat = c->lat;
+    const int T = lat.T, L3 = lat.L * lat.L * lat.L;
+    auto in = [&](const dd_domain& d, int t) { return t >= 0 && t < T && ((t - d.t0) % T + T) % T < d.nt; };
+    if (!in(*gbar, t_phi) || !in(*gbar, x0)) return fail(c, DD_ERR_ARG, "t_phi and x0 must lie in gbar");
+    if (in(*gstar, t_phi)) return fail(c, DD_ERR_ARG, "t_phi must lie outside gstar");
+    const bool before = (t_phi + 1) % T == gstar->t0, after = (gstar->t0 + gstar->nt) % T == t_phi;
+    const bool wrap_ok = lat.time_bc != 0 || (before ? t_phi != T - 1 : t_phi != 0);
+    if (!(before || after) || !wrap_ok) return fail(c, DD_ERR_ARG, "t_phi must be a time neighbour of gstar");
+    if (nvec < 1 || nvec > std::min(kMaxProjVec, 6 * L3))
+        return fail(c, DD_ERR_ARG, "nvec must be in [1, min(256, 6 L^3)]");
+    const size_t V = vlink(lat);
+    CHECK_PTR(c, U, 36 * V * 16, 16, "U");
+    CHECK_PTR(c, phi, (size_t)nvec * 12 * L3 * 16, 16, "phi");
+    CHECK_PTR(c, xi, (size_t)nvec * 12 * L3 * 16, 16, "xi");
+    CHECK_PTR(c, eta, (size_t)nvec * 12 * gstar->nt * L3 * 16, 16, "eta");
+    return nucleon_lines(c, (const cpx<double>*)U, kappa, *gbar, *gstar, t_phi, nvec, (const cpx<double>*)phi, x0,
+                         (cpx<double>*)xi, (cpx<double>*)eta, *p, stats);
+}
+
+dd_status dd_baryon_blocks(dd_ctx* c, int nvec, int nt, const void* s, void* B) {
+    if (c == nullptr) return DD_ERR_ARG;
+    const int L3 = c->lat.L * c->lat.L * c->lat.L;
+    if (nvec < 1 || nvec > kMaxProjVec) return fail(c, DD_ERR_ARG, "nvec must be in [1, 256]");
+    if (nt < 1 || nt > c->lat.T) return fail(c, DD_ERR_ARG, "nt must be in [1, T]");
+    CHECK_PTR(c, s, (size_t)nvec * 12 * nt * L3 * 16, 16, "s");
+    CHECK_PTR(c, B, (size_t)nt * 4 * nvec * nvec * nvec * 16, 16, "B");
+    const char* a = (const char*)s;
+    const char* b = (const char*)B;
+    const size_t na = (size_t)nvec * 12 * nt * L3 * 16, nb = (size_t)nt * 4 * nvec * nvec * nvec * 16;
+    if (a < b + nb && b < a + na) return fail(c, DD_ERR_ARG, "s and B overlap");
+    return baryon_blocks(c, nvec, nt, (const cpx<double>*)s, (cpx<double>*)B);
+}
+
+dd_status dd_nucleon_contract(dd_ctx* c, int nvec, int ntx, const void* Bx, int nty, const void* By, double* W_host) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (nvec < 1 || nvec > kMaxProjVec) return fail(c, DD_ERR_ARG, "nvec must be in [1, 256]");
+    if (ntx < 1 || nty < 1 || ntx > c->lat.T || nty > c->lat.T) return fail(c, DD_ERR_ARG, "ntx, nty must be in [1, T]");
+    if (W_host == nullptr) return fail(c, DD_ERR_ARG, "W_host is NULL");
+    const size_t sl = (size_t)4 * nvec * nvec * nvec * 16;
+    CHECK_PTR(c, Bx, ntx * sl, 16, "Bx");
+    CHECK_PTR(c, By, nty * sl, 16, "By");
+    return nucleon_contract(c, nvec, ntx, (const cpx<double>*)Bx, nty, (const cpx<double>*)By, W_host);
 }
 
 dd_status dd_pion_correlator(dd_ctx* c, const void* S, int ncol, int t_src, double* C_host) {

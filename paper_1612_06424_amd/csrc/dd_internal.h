@@ -160,6 +160,8 @@ struct dd_ctx {
     dd::ColState* host_state = nullptr;
     double* host_dots = nullptr;
     int host_n = 0;
+    // rocBLAS handle of the nucleon block products (created on first use)
+    void* blas = nullptr;
 };
 
 namespace dd {
@@ -418,5 +420,18 @@ dd_status disconnected_traces(dd_ctx* c, const cpx<double>* U, double kappa, con
                               cpx<double>* tau, dd_solve_stats* stats);
 // C_host[y0][x0] (complex, T x T) = the two-trace product over distinct sources
 dd_status disconnected_correlator(dd_ctx* c, int nsrc, const cpx<double>* tau, double* C_host);
+
+// ---------------------------------------------------------------- nucleon contraction
+// xi ([nvec][12][L^3], slice x0 of gbar) and eta ([nvec][12][|gstar|]) of the lines cut by phi
+// on slice t_phi; stats: NULL or 2 entries (the gbar and the gstar solves).  Synchronises.
+dd_status nucleon_lines(dd_ctx* c, const cpx<double>* U, double kappa, const dd_domain& gbar, const dd_domain& gstar,
+                        int t_phi, int nvec, const cpx<double>* phi, int x0, cpx<double>* xi, cpx<double>* eta,
+                        const dd_solver_params& p, dd_solve_stats* stats);
+// B[t][k][alpha][i][j] of the n fields s ([n][12][nt L^3]), summed per time slice
+dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<double>* B);
+// W_host[w][y][x] (complex) = W1 (w = 0), W2 (w = 1) of the blocks Bx (ntx slices), By (nty)
+dd_status nucleon_contract(dd_ctx* c, int n, int ntx, const cpx<double>* Bx, int nty, const cpx<double>* By,
+                           double* W_host);
+void blas_release(dd_ctx* c);
 
 }  // namespace dd

@@ -1,0 +1,326 @@
+// nucleon.hip -- the factorised nucleon contraction with projected quark lines
+// (Sec. 4.2, Eqs. 22-26).
+//
+// Each quark line from x in Gbar to y in Gstar is cut by the projector on N_m
+// vectors phi_i living on the slice t_phi just outside Gstar:
+//   D^-1(y, x) -> - sum_i eta_i(y) xi_i^T(x),
+//   xi_i^T(x) = [phi_i^+ D_Gbar^-1](x)  = conj([D_Gbar^-1+ phi_i](x)),
+//   eta_i(y)  = [D_Gstar^-1 D_{Gstar,dGstar} phi_i](y),
+// so the Wick contractions factorise into colourless spinors (Eq. 25)
+//   B[s_i, s_j, s_k](x)_alpha = eps^{abc} (s_i^{aT} C gamma5 s_j^b)(x) s_k^c_alpha(x),
+// summed over each time slice, one set built from three xi's at the source and
+// one from three eta's at every sink slice, contracted with gamma5 P_- (Eqs. 23-24).
+//
+// Blocks per slice are a dense contraction over the sites x and colours c:
+//   B[(k, alpha)][(i, j)] = sum_{x, c} E_c[(i, j)](x) s_k^c_alpha(x),
+//   E_c = eps^{abc} sum_{beta, gamma} s_i^a_beta (C gamma5)_{beta gamma} s_j^b_gamma,
+// an (N_m^2 x 3 X) by (3 X x 4 N_m) matrix product per chunk of X sites.  The
+// diquarks E (a hand-written kernel, HBM-bound) and the packed quark matrix are
+// written per chunk, and the product runs as one FP64 complex GEMM (rocBLAS,
+// matrix cores) accumulating into the slice's blocks.  About N_m flops per byte
+// of E, so the product, not the diquarks, bounds the time.
+//
+// Basis: chiral, component = spin * 3 + colour; gamma_0 = [[0, -1], [-1, 0]]
+// (2 x 2 blocks), gamma5 = diag(1, 1, -1, -1), C = gamma_0 gamma_2 (C gamma_mu
+// C^-1 = -gamma_mu^T), so C gamma5 has (0,1) = -1, (1,0) = +1, (2,3) = -1,
+// (3,2) = +1 and gamma5 P_- = gamma5 (1 - gamma_0)/2 = 1/2 [[1, 1], [-1, -1]].
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+
+#include <rocblas/rocblas.h>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+namespace {
+
+constexpr int kNB = 256;
+constexpr int kXT = 1;                   // sites per workgroup of the diquark kernel (LDS: 49 KB at 256 vectors)
+constexpr int kMaxN = kMaxProjVec;       // vectors per set of lines
+constexpr int kCChunk = 1 << 16;         // flat block entries per contraction workgroup
+
+__device__ inline cpx<double> cj(cpx<double> a) { return {a.re, -a.im}; }
+
+// xi[col][c][s] = conj(w[col][c][slice kx, s])
+__global__ __launch_bounds__(kNB) void k_conj_slice(int L3, int nsite, int kx, const cpx<double>* __restrict__ w,
+                                                    cpx<double>* __restrict__ xi) {
+    const int s = blockIdx.x * kNB + threadIdx.x;
+    const int cc = blockIdx.y;  // col * 12 + component
+    if (s >= L3) return;
+    xi[(size_t)cc * L3 + s] = cj(w[(size_t)cc * nsite + (size_t)kx * L3 + s]);
+}
+
+// Sp (column-major, 3X x 4n): row c X + x, column q = 4 k + alpha  <-  s_k^{alpha, c}(off + x)
+__global__ __launch_bounds__(kNB) void k_pack_quarks(int n, long long nsite, long long off, int X,
+                                                     const cpx<double>* __restrict__ s, cpx<double>* __restrict__ Sp) {
+    const int x = blockIdx.x * kNB + threadIdx.x;
+    const int qc = blockIdx.y;  // q * 3 + c
+    if (x >= X) return;
+    const int q = qc / 3, c = qc % 3;
+    const int k = q >> 2, al = q & 3;
+    Sp[(size_t)q * 3 * X + (size_t)c * X + x] = s[((size_t)k * 12 + al * 3 + c) * nsite + off + x];
+}
+
+// diquark of the colour pair (a, b): sum_{beta, gamma} s_i^a_beta (C gamma5)_{beta gamma} s_j^b_gamma
+__device__ inline cpx<double> diquark(const cpx<double>* si, const cpx<double>* sj, int a, int b) {
+    // (C gamma5): (0,1) = -1, (1,0) = +1, (2,3) = -1, (3,2) = +1
+    return si[3 + a] * sj[b] - si[a] * sj[3 + b] + si[9 + a] * sj[6 + b] - si[6 + a] * sj[9 + b];
+}
+
+// E (column-major, n^2 x 3X): row i n + j, column c X + x  <-  eps^{abc} diquark(a, b) at site off + x
+__global__ __launch_bounds__(kNB) void k_diquarks(int n, long long nsite, long long off, int X,
+                                                  const cpx<double>* __restrict__ s, cpx<double>* __restrict__ E) {
+    __shared__ cpx<double> sq[kXT][kMaxN][12];
+    const int x0 = blockIdx.x * kXT;
+    for (int e = threadIdx.x; e < kXT * n * 12; e += kNB) {
+        const int xt = e % kXT, rest = e / kXT;
+        const int comp = rest % 12, k = rest / 12;
+        const int x = x0 + xt;
+        sq[xt][k][comp] = x < X ? s[((size_t)k * 12 + comp) * nsite + off + x] : cpx<double>{0.0, 0.0};
+    }
+    __syncthreads();
+    const size_t M = (size_t)n * n;
+    for (int r = threadIdx.x; r < n * n; r += kNB) {
+        const int i = r / n, j = r % n;
+#pragma unroll
+        for (int xt = 0; xt < kXT; xt++) {
+            const int x = x0 + xt;
+            if (x >= X) break;
+            const cpx<double>* si = sq[xt][i];
+            const cpx<double>* sj = sq[xt][j];
+            // eps^{abc}: c = 0 from (1, 2), c = 1 from (2, 0), c = 2 from (0, 1), minus the swapped pair
+            E[r + (size_t)(0 * X + x) * M] = diquark(si, sj, 1, 2) - diquark(si, sj, 2, 1);
+            E[r + (size_t)(1 * X + x) * M] = diquark(si, sj, 2, 0) - diquark(si, sj, 0, 2);
+            E[r + (size_t)(2 * X + x) * M] = diquark(si, sj, 0, 1) - diquark(si, sj, 1, 0);
+        }
+    }
+}
+
+// P1[k][al][i][j] = B[k][al][j][i],  P2[k][al][i][j] = B[j][al][k][i]  (one slice, n^3 4 entries)
+__global__ __launch_bounds__(kNB) void k_block_perms(int n, const cpx<double>* __restrict__ B,
+                                                     cpx<double>* __restrict__ P1, cpx<double>* __restrict__ P2) {
+    const size_t f = (size_t)blockIdx.x * kNB + threadIdx.x;
+    const size_t n2 = (size_t)n * n, tot = 4 * n2 * n;
+    if (f >= tot) return;
+    const int j = (int)(f % n), i = (int)((f / n) % n), al = (int)((f / n2) % 4), k = (int)(f / (4 * n2));
+    P1[f] = B[(((size_t)k * 4 + al) * n + j) * n + i];
+    P2[f] = B[(((size_t)j * 4 + al) * n + k) * n + i];
+}
+
+// partial sums over a chunk of the flat index f = ((k 4 + al) n + i) n + j of
+//   sum P_x[f] (gamma5 P_- By_y)[f]  for W1 (P1) and W2 (P2)
+__global__ __launch_bounds__(kNB) void k_nucleon_partial(int n, int nchunk, int ntx, const cpx<double>* __restrict__ By,
+                                                         const cpx<double>* __restrict__ P1,
+                                                         const cpx<double>* __restrict__ P2,
+                                                         double* __restrict__ partial) {
+    const int chunk = blockIdx.x, yy = blockIdx.y, xx = blockIdx.z;
+    const size_t n2 = (size_t)n * n, sl = 4 * n2 * n;
+    const cpx<double>* by = By + (size_t)yy * sl;
+    const cpx<double>* p1 = P1 + (size_t)xx * sl;
+    const cpx<double>* p2 = P2 + (size_t)xx * sl;
+    const size_t f0 = (size_t)chunk * kCChunk, f1 = std::min(sl, f0 + kCChunk);
+    double a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+    for (size_t f = f0 + threadIdx.x; f < f1; f += kNB) {
+        const int al = (int)((f / n2) % 4);
+        // (gamma5 P_-)_{al, be} = +1/2 for be in {al, al + 2} (al < 2), -1/2 for be in {al - 2, al}
+        const size_t base = f - (size_t)al * n2;  // the al = 0 entry of this (k, i, j)
+        const cpx<double> u = by[base + (size_t)(al & 1) * n2], v = by[base + (size_t)((al & 1) + 2) * n2];
+        const double h = al < 2 ? 0.5 : -0.5;
+        const cpx<double> m = {h * (u.re + v.re), h * (u.im + v.im)};
+        const cpx<double> b1 = p1[f], b2 = p2[f];
+        a1r += b1.re * m.re - b1.im * m.im;
+        a1i += b1.re * m.im + b1.im * m.re;
+        a2r += b2.re * m.re - b2.im * m.im;
+        a2i += b2.re * m.im + b2.im * m.re;
+    }
+    __shared__ double sh[kNB / kWave][4];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a1r += __shfl_xor(a1r, off, kWave);
+        a1i += __shfl_xor(a1i, off, kWave);
+        a2r += __shfl_xor(a2r, off, kWave);
+        a2i += __shfl_xor(a2i, off, kWave);
+    }
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) {
+        sh[w][0] = a1r;
+        sh[w][1] = a1i;
+        sh[w][2] = a2r;
+        sh[w][3] = a2i;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double acc = 0;
+        for (int k = 0; k < kNB / kWave; k++) acc += sh[k][threadIdx.x];
+        partial[(((size_t)yy * ntx + xx) * nchunk + chunk) * 4 + threadIdx.x] = acc;
+    }
+}
+
+// W[w][y][x] (complex) = - sum of the chunk partials, in chunk order
+__global__ __launch_bounds__(kNB) void k_nucleon_final(int nty, int ntx, int nchunk, const double* __restrict__ partial,
+                                                       double* __restrict__ W) {
+    const int e = blockIdx.x * kNB + threadIdx.x;  // (y * ntx + x) * 2 + w
+    if (e >= nty * ntx * 2) return;
+    const int w = e % 2, yx = e / 2;
+    double re = 0, im = 0;
+    for (int c = 0; c < nchunk; c++) {
+        re += partial[((size_t)yx * nchunk + c) * 4 + 2 * w];
+        im += partial[((size_t)yx * nchunk + c) * 4 + 2 * w + 1];
+    }
+    W[((size_t)w * nty * ntx + yx) * 2] = -re;
+    W[((size_t)w * nty * ntx + yx) * 2 + 1] = -im;
+}
+
+rocblas_handle blas_handle(dd_ctx* c, dd_status* st) {
+    if (c->blas == nullptr) {
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success) {
+            *st = fail(c, DD_ERR_HIP, "rocblas_create_handle failed");
+            return nullptr;
+        }
+        c->blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)c->blas;
+    if (rocblas_set_stream(h, c->stream) != rocblas_status_success) {
+        *st = fail(c, DD_ERR_HIP, "rocblas_set_stream failed");
+        return nullptr;
+    }
+    return h;
+}
+
+}  // namespace
+
+void blas_release(dd_ctx* c) {
+    if (c->blas) (void)rocblas_destroy_handle((rocblas_handle)c->blas);
+    c->blas = nullptr;
+}
+
+dd_status nucleon_lines(dd_ctx* c, const cpx<double>* U, double kappa, const dd_domain& gbar, const dd_domain& gstar,
+                        int t_phi, int nvec, const cpx<double>* phi, int x0, cpx<double>* xi, cpx<double>* eta,
+                        const dd_solver_params& p, dd_solve_stats* stats) {
+    const dd_lattice& lat = c->lat;
+    const int T = lat.T, L3 = lat.L * lat.L * lat.L;
+    const Geo gb = make_geo(lat, &gbar), gs = make_geo(lat, &gstar);
+    const int kp = ((t_phi - gbar.t0) % T + T) % T, kx = ((x0 - gbar.t0) % T + T) % T;
+    const size_t nb = (size_t)DD_MAX_RHS * 12 * std::max(gb.nsite, gs.nsite);
+    dd_status e = DD_OK;
+    cpx<double>* rhs = (cpx<double>*)workspace(c, W_DISC0, nb * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* w = (cpx<double>*)workspace(c, W_DISC1, nb * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    dd_solve_stats tot[2];
+    std::memset(tot, 0, sizeof(tot));
+    tot[0].nrhs = tot[1].nrhs = nvec;
+    dd_status worst = DD_OK;
+    const dd_domain src{t_phi, 1};
+    for (int a0 = 0; a0 < nvec; a0 += DD_MAX_RHS) {
+        const int nc = std::min(DD_MAX_RHS, nvec - a0);
+        const cpx<double>* ph = phi + (size_t)a0 * 12 * L3;
+        // xi: D_Gbar^+ w = phi (placed on slice t_phi), xi = conj(w) on slice x0
+        launch_zero<double>(c, (size_t)nc * 12 * gb.nsite, rhs);
+        launch_slab_embed(c, L3, gb.nt, kp, 1, nc, const_cast<cpx<double>*>(ph), rhs, 0);
+        DD_HIP(c, hipGetLastError());
+        for (int side = 0; side < 2; side++) {
+            dd_solve_stats st;
+            if (side == 0) {
+                e = solve(c, U, kappa, gb, nc, rhs, w, p, &st, 1);
+            } else {
+                // eta: D_Gstar eta = D_{Gstar, dGstar} phi
+                launch_zero<double>(c, (size_t)nc * 12 * gs.nsite, rhs);
+                launch_frontier(c, lat, U, gstar, src, nc, ph, rhs, 1.0);
+                DD_HIP(c, hipGetLastError());
+                e = solve(c, U, kappa, gs, nc, rhs, eta + (size_t)a0 * 12 * gs.nsite, p, &st, 0);
+            }
+            if (e != DD_OK && e != DD_ERR_NOCONV) return e;
+            if (e == DD_ERR_NOCONV) worst = e;
+            tot[side].iters += st.iters;
+            tot[side].updates += st.updates;
+            tot[side].restarts += st.restarts;
+            tot[side].ms += st.ms;
+            for (int j = 0; j < nc; j++)
+                tot[side].true_rel_resid[(a0 + j) % DD_MAX_RHS] =
+                    std::max(tot[side].true_rel_resid[(a0 + j) % DD_MAX_RHS], st.true_rel_resid[j]);
+            if (side == 0) {
+                hipLaunchKernelGGL(k_conj_slice, dim3((unsigned)((L3 + kNB - 1) / kNB), (unsigned)(12 * nc)), dim3(kNB),
+                                   0, c->stream, L3, gb.nsite, kx, w, xi + (size_t)a0 * 12 * L3);
+                DD_HIP(c, hipGetLastError());
+            }
+        }
+    }
+    if (stats) {
+        stats[0] = tot[0];
+        stats[1] = tot[1];
+    }
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    if (worst != DD_OK) return fail(c, worst, "a nucleon line solve did not converge: " + c->err);
+    return DD_OK;
+}
+
+dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<double>* B) {
+    const int L3 = c->lat.L * c->lat.L * c->lat.L;
+    const long long nsite = (long long)nt * L3;
+    const size_t M = (size_t)n * n;
+    // sites per chunk: the diquarks of a chunk stay below 2 GiB
+    int X = (int)std::min<size_t>((size_t)L3, std::max<size_t>(64, ((size_t)1 << 31) / (M * 3 * sizeof(cpx<double>))));
+    if (const char* env = std::getenv("DD_BLOCK_CHUNK")) X = std::max(1, std::min(X, std::atoi(env)));  // tests
+    dd_status e = DD_OK;
+    cpx<double>* E = (cpx<double>*)workspace(c, W_DISC2, M * 3 * X * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* Sp = (cpx<double>*)workspace(c, W_DISC3, (size_t)3 * X * 4 * n * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    rocblas_handle h = blas_handle(c, &e);
+    if (h == nullptr) return e;
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    for (int t = 0; t < nt; t++) {
+        cpx<double>* Bt = B + (size_t)t * 4 * n * M;
+        for (int x0 = 0; x0 < L3; x0 += X) {
+            const int xc = std::min(X, L3 - x0);
+            const long long off = (long long)t * L3 + x0;
+            hipLaunchKernelGGL(k_pack_quarks, dim3((unsigned)((xc + kNB - 1) / kNB), (unsigned)(12 * n)), dim3(kNB), 0,
+                               c->stream, n, nsite, off, xc, s, Sp);
+            hipLaunchKernelGGL(k_diquarks, dim3((unsigned)((xc + kXT - 1) / kXT)), dim3(kNB), 0, c->stream, n, nsite,
+                               off, xc, s, E);
+            DD_HIP(c, hipGetLastError());
+            // Bt (n^2 x 4n, column-major) (+)= E (n^2 x 3 xc) Sp (3 xc x 4n)
+            const rocblas_status bs = rocblas_zgemm(
+                h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)M, 4 * n, 3 * xc, &one,
+                (const rocblas_double_complex*)E, (rocblas_int)M, (const rocblas_double_complex*)Sp, 3 * xc,
+                x0 == 0 ? &zero : &one, (rocblas_double_complex*)Bt, (rocblas_int)M);
+            if (bs != rocblas_status_success)
+                return fail(c, DD_ERR_HIP, std::string("rocblas_zgemm failed: ") + rocblas_status_to_string(bs));
+        }
+    }
+    DD_HIP(c, hipGetLastError());
+    return DD_OK;
+}
+
+dd_status nucleon_contract(dd_ctx* c, int n, int ntx, const cpx<double>* Bx, int nty, const cpx<double>* By,
+                           double* W_host) {
+    const size_t sl = (size_t)4 * n * n * n;
+    const int nchunk = (int)((sl + kCChunk - 1) / kCChunk);
+    dd_status e = DD_OK;
+    cpx<double>* P = (cpx<double>*)workspace(c, W_DISC2, 2 * (size_t)ntx * sl * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
+    cpx<double>* P1 = P;
+    cpx<double>* P2 = P + (size_t)ntx * sl;
+    double* part = (double*)workspace(c, W_DISC3, ((size_t)nty * ntx * nchunk * 4 + (size_t)nty * ntx * 4) *
+                                                      sizeof(double), &e);
+    if (e != DD_OK) return e;
+    double* Wd = part + (size_t)nty * ntx * nchunk * 4;
+    for (int x = 0; x < ntx; x++)
+        hipLaunchKernelGGL(k_block_perms, dim3((unsigned)((sl + kNB - 1) / kNB)), dim3(kNB), 0, c->stream, n,
+                           Bx + (size_t)x * sl, P1 + (size_t)x * sl, P2 + (size_t)x * sl);
+    hipLaunchKernelGGL(k_nucleon_partial, dim3((unsigned)nchunk, (unsigned)nty, (unsigned)ntx), dim3(kNB), 0,
+                       c->stream, n, nchunk, ntx, By, P1, P2, part);
+    hipLaunchKernelGGL(k_nucleon_final, dim3((unsigned)((nty * ntx * 2 + kNB - 1) / kNB)), dim3(kNB), 0, c->stream,
+                       nty, ntx, nchunk, part, Wd);
+    DD_HIP(c, hipGetLastError());
+    DD_HIP(c, hipMemcpyAsync(W_host, Wd, (size_t)nty * ntx * 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    return DD_OK;
+}
+
+}  // namespace dd

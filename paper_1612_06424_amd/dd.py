@@ -38,7 +38,8 @@ EXPORTS = [
     "dd_factorized_propagator", "dd_pion_correlator", "dd_block_solve_backward", "dd_domain_action",
     "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing_count",
     "dd_kernel_timing", "dd_projection_basis", "dd_factorized_propagator_projected",
-    "dd_disconnected_traces", "dd_disconnected_correlator",
+    "dd_disconnected_traces", "dd_disconnected_correlator", "dd_nucleon_lines", "dd_baryon_blocks",
+    "dd_nucleon_contract",
 ]
 
 
@@ -89,6 +90,10 @@ _sig = {
     "dd_disconnected_traces": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _i, _vp, _i, C.POINTER(dd_solver_params),
                                 _vp, C.POINTER(dd_solve_stats)], _i),
     "dd_disconnected_correlator": ([_vp, _i, _vp, C.POINTER(C.c_double)], _i),
+    "dd_nucleon_lines": ([_vp, _vp, _d, C.POINTER(dd_domain), C.POINTER(dd_domain), _i, _i, _vp, _i, _vp, _vp,
+                          C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
+    "dd_baryon_blocks": ([_vp, _i, _i, _vp, _vp], _i),
+    "dd_nucleon_contract": ([_vp, _i, _i, _vp, _i, _vp, C.POINTER(C.c_double)], _i),
     "dd_block_solve_backward": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, _vp,
                                  C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
     "dd_domain_action": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, C.POINTER(C.c_double),
@@ -279,6 +284,45 @@ def disconnected_correlator(ctx, tau):
     ctx._check(_lib.dd_disconnected_correlator(ctx._h, tau.shape[0], _ptr(tau, torch.complex128, "tau"), out))
     a = np.array(list(out)).reshape(ctx.T, ctx.T, 2)
     return a[..., 0] + 1j * a[..., 1]
+
+
+def nucleon_lines(ctx, U, kappa, gbar, gstar, t_phi, phi, x0, params=None, allow_noconv=False):
+    """xi (complex128 (nvec, 12, L^3), slice x0) and eta (complex128 (nvec, 12, |gstar|)) of the
+    quark lines cut by phi (complex128 (nvec, 12, L^3)) on slice t_phi.  Returns (xi, eta, stats)."""
+    params = params or solver_params()
+    nvec = phi.shape[0]
+    L3 = ctx.L ** 3
+    xi = torch.empty((nvec, 12, L3), dtype=torch.complex128, device=phi.device)
+    eta = torch.empty((nvec, 12, int(gstar[1]) * L3), dtype=torch.complex128, device=phi.device)
+    stats = (dd_solve_stats * 2)()
+    ctx._check(_lib.dd_nucleon_lines(
+        ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), _dom(gbar), _dom(gstar), int(t_phi), nvec,
+        _ptr(phi, torch.complex128, "phi"), int(x0), _ptr(xi, torch.complex128, "xi"),
+        _ptr(eta, torch.complex128, "eta"), C.byref(params), stats), allow=(DD_ERR_NOCONV,) if allow_noconv else ())
+    return xi, eta, [s.as_dict() for s in stats]
+
+
+def baryon_blocks(ctx, s, B=None):
+    """Blocks of Eq. 25 per time slice of s (complex128 (n, 12, nt L^3)) as complex128
+    (nt, n, 4, n, n), index [t][k][alpha][i][j]."""
+    n = s.shape[0]
+    nt = s.shape[2] // ctx.L ** 3
+    if B is None:
+        B = torch.empty((nt, n, 4, n, n), dtype=torch.complex128, device=s.device)
+    ctx._check(_lib.dd_baryon_blocks(ctx._h, n, nt, _ptr(s, torch.complex128, "s"), _ptr(B, torch.complex128, "B")))
+    return B
+
+
+def nucleon_contract(ctx, Bx, By):
+    """(W1, W2) as numpy complex128 (nty, ntx) from blocks of baryon_blocks."""
+    n = Bx.shape[1]
+    ntx, nty = Bx.shape[0], By.shape[0]
+    out = (C.c_double * (4 * nty * ntx))()
+    ctx._check(_lib.dd_nucleon_contract(ctx._h, n, ntx, _ptr(Bx, torch.complex128, "Bx"), nty,
+                                        _ptr(By, torch.complex128, "By"), out))
+    a = np.array(list(out)).reshape(2, nty, ntx, 2)
+    W = a[..., 0] + 1j * a[..., 1]
+    return W[0], W[1]
 
 
 def block_solve_backward(ctx, U, kappa, x, grad_x, dom=None, params=None, grad_U=None):
