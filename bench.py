@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection,disconnected "
-                    "(all = every part but projection and disconnected, which take about a minute a step)")
+    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection,disconnected,nucleon "
+                    "(all = every part but projection, disconnected and nucleon, which take one to a few "
+                    "minutes a step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (10 times), the reference that scales "
                          "the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -171,6 +172,15 @@ def main():
         gd = torch.Generator(device=dev)
         gd.manual_seed(w["stencil_seed"] + 2)
         disc_eta = torch.randn((disc_nsrc, 12, V), dtype=torch.complex128, device=dev, generator=gd)
+    if "nucleon" in parts:
+        # factorised nucleon: the 64x32^3 links with Dirichlet time walls (as the paper's open
+        # boundaries), Gbar = [0, 32) (Delta = 8), Gstar = [24, 64), the lines cut on slice 23 by
+        # 120 vectors from 10 inverse iterations on [16, 32), source slice x0 = 4
+        nctx = dd.Context(T, L, 0)
+        nuc_gbar, nuc_gstar, nuc_t, nuc_x0, nuc_n, nuc_iter, nuc_pi = (0, 32), (24, 40), 23, 4, 120, 10, (16, 16)
+        gn = torch.Generator(device=dev)
+        gn.manual_seed(w["stencil_seed"] + 3)
+        nuc_v0 = torch.randn((nuc_n, 12, nuc_pi[1] * L ** 3), dtype=torch.complex128, device=dev, generator=gn)
     if "force" in parts:
         wf = WORKLOADS["force-32x16^3"]
         Uf = dd.pack_links(random_links(wf["T"], wf["L"], wf["eps"], wf["link_seed"]))
@@ -282,6 +292,33 @@ def main():
                     ph["disconnected"][f"C_f[{d}]"] = float(Cf[y0, x0].real)
                     ph["disconnected"][f"C_full[{d}]"] = float(Cw[y0, x0].real)
             del tau_f, tau_w
+        if "nucleon" in parts:
+            t0 = time.perf_counter()
+            nb, nbs = dd.projection_basis(nctx, U64, kappa, nuc_pi, nuc_t, +1, nuc_v0, nuc_iter, pmx)
+            t1 = time.perf_counter()
+            log(f"nucleon: basis {t1 - t0:.1f}s")
+            xi, eta, nls = dd.nucleon_lines(nctx, U64, kappa, nuc_gbar, nuc_gstar, nuc_t, nb, nuc_x0, pmx)
+            t2 = time.perf_counter()
+            log(f"nucleon: lines {t2 - t1:.1f}s")
+            Bx = dd.baryon_blocks(nctx, xi)
+            By = dd.baryon_blocks(nctx, eta)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            log(f"nucleon: blocks {t3 - t2:.1f}s")
+            W1, W2 = dd.nucleon_contract(nctx, Bx, By)
+            t4 = time.perf_counter()
+            nslice = 1 + nuc_gstar[1]
+            flops = 96.0 * nuc_n ** 3 * L ** 3 * nslice  # complex GEMM of the blocks, 8 real flops per MAC
+            ph["nucleon"] = dict(ms=(t4 - t0) * 1e3, ms_basis=(t1 - t0) * 1e3, ms_lines=(t2 - t1) * 1e3,
+                                 ms_blocks=(t3 - t2) * 1e3, ms_contract=(t4 - t3) * 1e3, nvec=nuc_n,
+                                 block_slices=nslice, block_TFLOPs=flops / (t3 - t2) / 1e12,
+                                 basis_iters=nbs["iters"], line_iters=[q["iters"] for q in nls],
+                                 max_true_rel_resid=max(max(q["true_rel_resid"]) for q in nls))
+            if record:
+                Cn = (W1[:, 0] - W2[:, 0]) / L ** 3  # C_N^(f)(y0, x0 = 4), y0 = 24 + index
+                for y0 in (24, 28, 32, 40, 48):
+                    ph["nucleon"][f"C_f[{y0}]"] = float(Cn[y0 - 24].real)
+            del nb, xi, eta, Bx, By
         if "batched" in parts:
             t0 = time.perf_counter()
             bst = dd.block_solve_batched(bctx, bitems, pmx)
