@@ -298,11 +298,11 @@ def main():
             nb, nbs = dd.projection_basis(nctx, U64, kappa, nuc_pi, nuc_t, +1, nuc_v0, nuc_iter, pmx)
             t1 = time.perf_counter()
             log(f"nucleon: basis {t1 - t0:.1f}s")
-            xi, eta, nls = dd.nucleon_lines(nctx, U64, kappa, nuc_gbar, nuc_gstar, nuc_t, nb, nuc_x0, pmx)
+            nxi, neta, nls = dd.nucleon_lines(nctx, U64, kappa, nuc_gbar, nuc_gstar, nuc_t, nb, nuc_x0, pmx)
             t2 = time.perf_counter()
             log(f"nucleon: lines {t2 - t1:.1f}s")
-            Bx = dd.baryon_blocks(nctx, xi)
-            By = dd.baryon_blocks(nctx, eta)
+            Bx = dd.baryon_blocks(nctx, nxi)
+            By = dd.baryon_blocks(nctx, neta)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
             log(f"nucleon: blocks {t3 - t2:.1f}s")
@@ -323,7 +323,7 @@ def main():
                 Cn = (W1[:, 0] - W2[:, 0]) / L ** 3  # C_N^(f)(y0, x0 = 4), y0 = 24 + index
                 for y0 in (24, 28, 32, 40, 48):
                     ph["nucleon"][f"C_f[{y0}]"] = float(Cn[y0 - 24].real)
-            del nb, xi, eta, Bx, By
+            del nb, nxi, neta, Bx, By
         if "batched" in parts:
             t0 = time.perf_counter()
             bst = dd.block_solve_batched(bctx, bitems, pmx)
