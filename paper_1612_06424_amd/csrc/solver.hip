@@ -236,10 +236,10 @@ dd_status bicgstab_reliable(System& S, const cpx<double>* b, cpx<double>* x, con
             mask[j] = 0;
             if (done[j]) continue;
             const ColState& s = c->host_state[j];
-            if (s.breakdown == 2) {
-                *nonfinite = true;
-                break;
-            }
+            // A breakdown (an exact zero, or a non-finite alpha, omega or rho: the
+            // finalize kernel stops the segment before its solution is updated) takes
+            // a fresh start from the true residual of the last finite iterate; only a
+            // non-finite true residual is an error.
             // A low-precision recursion can lose bi-orthogonality and drift up or
             // stall; such a segment restarts (fresh shadow residual) from the true
             // residual: 100x above the last update, or 400 iterations with less
