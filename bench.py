@@ -298,7 +298,19 @@ def main():
             nb, nbs = dd.projection_basis(nctx, U64, kappa, nuc_pi, nuc_t, +1, nuc_v0, nuc_iter, pmx)
             t1 = time.perf_counter()
             log(f"nucleon: basis {t1 - t0:.1f}s")
-            nxi, neta, nls = dd.nucleon_lines(nctx, U64, kappa, nuc_gbar, nuc_gstar, nuc_t, nb, nuc_x0, pmx)
+            # the lines in calls of 24 vectors (two solves of 12 each), reporting as they go
+            parts_xi, parts_eta, nls = [], [], [dict(iters=0, true_rel_resid=[0.0]), dict(iters=0, true_rel_resid=[0.0])]
+            for a0 in range(0, nuc_n, 24):
+                xa, ea, sa = dd.nucleon_lines(nctx, U64, kappa, nuc_gbar, nuc_gstar, nuc_t, nb[a0:a0 + 24].contiguous(),
+                                              nuc_x0, pmx)
+                parts_xi.append(xa)
+                parts_eta.append(ea)
+                for q, r in zip(nls, sa):
+                    q["iters"] += r["iters"]
+                    q["true_rel_resid"] = [max(q["true_rel_resid"] + r["true_rel_resid"])]
+                log(f"nucleon: lines {a0 + 24}/{nuc_n} ({time.perf_counter() - t1:.1f}s)")
+            nxi, neta = torch.cat(parts_xi), torch.cat(parts_eta)
+            del parts_xi, parts_eta
             t2 = time.perf_counter()
             log(f"nucleon: lines {t2 - t1:.1f}s")
             Bx = dd.baryon_blocks(nctx, nxi)
@@ -309,7 +321,8 @@ def main():
             W1, W2 = dd.nucleon_contract(nctx, Bx, By)
             t4 = time.perf_counter()
             nslice = 1 + nuc_gstar[1]
-            flops = 96.0 * nuc_n ** 3 * L ** 3 * nslice  # complex GEMM of the blocks, 8 real flops per MAC
+            # complex GEMM of the blocks over the pairs i <= j, 8 real flops per multiply-add
+            flops = 96.0 * (nuc_n * (nuc_n + 1) // 2) * nuc_n * L ** 3 * nslice
             ph["nucleon"] = dict(ms=(t4 - t0) * 1e3, ms_basis=(t1 - t0) * 1e3, ms_lines=(t2 - t1) * 1e3,
                                  ms_blocks=(t3 - t2) * 1e3, ms_contract=(t4 - t3) * 1e3, nvec=nuc_n,
                                  block_slices=nslice, block_TFLOPs=flops / (t3 - t2) / 1e12,
@@ -319,6 +332,8 @@ def main():
             tf = flops / (t3 - t2) / 1e12
             ph["nucleon"]["block_roofline"] = dict(bound="mfma", achieved=round(tf, 2), peak=FP64_PEAK_TFLOPS,
                                                    unit="TFLOP/s", frac=round(tf / FP64_PEAK_TFLOPS, 4))
+            if record and not args.no_cpu_baseline:
+                ph["nucleon"]["block_cpu_baseline"] = nucleon_cpu_baseline()
             if record:
                 Cn = (W1[:, 0] - W2[:, 0]) / L ** 3  # C_N^(f)(y0, x0 = 4), y0 = 24 + index
                 for y0 in (24, 28, 32, 40, 48):
@@ -451,6 +466,29 @@ def cpu_baseline(T, L, bc, kappa, w):
     return {"value": round(gbs, 2), "unit": "GB/s", "cores": O.threads(), "kind": "oracle",
             "sample": f"oracle D apply, whole 64x32^3 lattice, FP64, {ncol} columns one at a time, "
                       f"{reps} times ({dt:.1f} s)"}
+
+
+def nucleon_cpu_baseline():
+    """The oracle's baryon blocks (Eq. 25), as they stand, on a bounded sample of the nucleon
+    block workload: 8 Gaussian vectors on one 16^3 slice (about 10 s of host time), scaled to
+    TFLOP/s with the GPU's executed flop count for the same sample (96 P n L^3, P = n(n+1)/2)."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    from paper_1612_06424_amd.inputs import gaussian_field
+
+    n, Ls = 8, 16
+    s = gaussian_field(Ls ** 3, n, 9)
+    t0 = time.perf_counter()
+    O.baryon_blocks(Ls, s)
+    dt = time.perf_counter() - t0
+    flops = 96.0 * (n * (n + 1) // 2) * n * Ls ** 3
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle baryon blocks (numpy einsum, FP64), {n} vectors on one {Ls}^3 slice ({dt:.1f} s)"}
 
 
 if __name__ == "__main__":

@@ -14,11 +14,13 @@
 // Blocks per slice are a dense contraction over the sites x and colours c:
 //   B[(k, alpha)][(i, j)] = sum_{x, c} E_c[(i, j)](x) s_k^c_alpha(x),
 //   E_c = eps^{abc} sum_{beta, gamma} s_i^a_beta (C gamma5)_{beta gamma} s_j^b_gamma,
-// an (N_m^2 x 3 X) by (3 X x 4 N_m) matrix product per chunk of X sites.  The
-// diquarks E (a hand-written kernel, HBM-bound) and the packed quark matrix are
-// written per chunk, and the product runs as one FP64 complex GEMM (rocBLAS,
-// matrix cores) accumulating into the slice's blocks.  About N_m flops per byte
-// of E, so the product, not the diquarks, bounds the time.
+// a (P x 3 X) by (3 X x 4 N_m) matrix product per chunk of X sites, over the
+// P = N_m (N_m + 1) / 2 pairs i <= j only: B is symmetric in (i, j) (C gamma5 and
+// eps are both antisymmetric).  The diquarks E (a hand-written kernel,
+// HBM-bound) and the packed quark matrix are written per chunk, the product runs
+// as one FP64 complex GEMM (rocBLAS, matrix cores) accumulating into the
+// slice's packed blocks, and a last kernel writes both (i, j) and (j, i).  About
+// N_m / 2 flops per byte of E, so the product, not the diquarks, bounds the time.
 //
 // Basis: chiral, component = spin * 3 + colour; gamma_0 = [[0, -1], [-1, 0]]
 // (2 x 2 blocks), gamma5 = diag(1, 1, -1, -1), C = gamma_0 gamma_2 (C gamma_mu
@@ -64,13 +66,25 @@ __global__ __launch_bounds__(kNB) void k_pack_quarks(int n, long long nsite, lon
     Sp[(size_t)q * 3 * X + (size_t)c * X + x] = s[((size_t)k * 12 + al * 3 + c) * nsite + off + x];
 }
 
+// row p of the packed pairs i <= j, p = i n - i (i - 1) / 2 + (j - i)
+__device__ inline long long pair_start(int i, int n) { return (long long)i * n - (long long)i * (i - 1) / 2; }
+__device__ inline void pair_of(long long p, int n, int& i, int& j) {
+    const double d = 2.0 * n + 1.0;
+    int a = (int)((d - sqrt(d * d - 8.0 * (double)p)) * 0.5);
+    a = max(0, min(a, n - 1));
+    while (a > 0 && pair_start(a, n) > p) a--;
+    while (a < n - 1 && pair_start(a + 1, n) <= p) a++;
+    i = a;
+    j = a + (int)(p - pair_start(a, n));
+}
+
 // diquark of the colour pair (a, b): sum_{beta, gamma} s_i^a_beta (C gamma5)_{beta gamma} s_j^b_gamma
 __device__ inline cpx<double> diquark(const cpx<double>* si, const cpx<double>* sj, int a, int b) {
     // (C gamma5): (0,1) = -1, (1,0) = +1, (2,3) = -1, (3,2) = +1
     return si[3 + a] * sj[b] - si[a] * sj[3 + b] + si[9 + a] * sj[6 + b] - si[6 + a] * sj[9 + b];
 }
 
-// E (column-major, n^2 x 3X): row i n + j, column c X + x  <-  eps^{abc} diquark(a, b) at site off + x
+// E (column-major, P x 3X): row p(i, j), column c X + x  <-  eps^{abc} diquark(a, b) at site off + x
 __global__ __launch_bounds__(kNB) void k_diquarks(int n, long long nsite, long long off, int X,
                                                   const cpx<double>* __restrict__ s, cpx<double>* __restrict__ E) {
     __shared__ cpx<double> sq[kXT][kMaxN][12];
@@ -82,9 +96,10 @@ __global__ __launch_bounds__(kNB) void k_diquarks(int n, long long nsite, long l
         sq[xt][k][comp] = x < X ? s[((size_t)k * 12 + comp) * nsite + off + x] : cpx<double>{0.0, 0.0};
     }
     __syncthreads();
-    const size_t M = (size_t)n * n;
-    for (int r = threadIdx.x; r < n * n; r += kNB) {
-        const int i = r / n, j = r % n;
+    const size_t M = (size_t)n * (n + 1) / 2;
+    for (int r = threadIdx.x; r < (int)M; r += kNB) {
+        int i, j;
+        pair_of(r, n, i, j);
 #pragma unroll
         for (int xt = 0; xt < kXT; xt++) {
             const int x = x0 + xt;
@@ -97,6 +112,18 @@ __global__ __launch_bounds__(kNB) void k_diquarks(int n, long long nsite, long l
             E[r + (size_t)(2 * X + x) * M] = diquark(si, sj, 0, 1) - diquark(si, sj, 1, 0);
         }
     }
+}
+
+// B[t][k][al][i][j] = Bp[t][(4 k + al) P + p(min(i, j), max(i, j))]
+__global__ __launch_bounds__(kNB) void k_unpack_blocks(int n, size_t P, const cpx<double>* __restrict__ Bp,
+                                                       cpx<double>* __restrict__ B) {
+    const size_t f = (size_t)blockIdx.x * kNB + threadIdx.x;
+    const size_t n2 = (size_t)n * n;
+    if (f >= 4 * n2 * n) return;
+    const int j = (int)(f % n), i = (int)((f / n) % n);
+    const size_t q = f / n2;  // 4 k + al
+    const int a = min(i, j), b = max(i, j);
+    B[f] = Bp[q * P + (size_t)(pair_start(a, n) + (b - a))];
 }
 
 // P1[k][al][i][j] = B[k][al][j][i],  P2[k][al][i][j] = B[j][al][k][i]  (one slice, n^3 4 entries)
@@ -262,20 +289,21 @@ dd_status nucleon_lines(dd_ctx* c, const cpx<double>* U, double kappa, const dd_
 dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<double>* B) {
     const int L3 = c->lat.L * c->lat.L * c->lat.L;
     const long long nsite = (long long)nt * L3;
-    const size_t M = (size_t)n * n;
+    const size_t M = (size_t)n * (n + 1) / 2;  // pairs i <= j
     // sites per chunk: the diquarks of a chunk stay below 2 GiB
     int X = (int)std::min<size_t>((size_t)L3, std::max<size_t>(64, ((size_t)1 << 31) / (M * 3 * sizeof(cpx<double>))));
     if (const char* env = std::getenv("DD_BLOCK_CHUNK")) X = std::max(1, std::min(X, std::atoi(env)));  // tests
     dd_status e = DD_OK;
-    cpx<double>* E = (cpx<double>*)workspace(c, W_DISC2, M * 3 * X * sizeof(cpx<double>), &e);
+    cpx<double>* E = (cpx<double>*)workspace(c, W_DISC2, (M * 3 * X + M * 4 * n) * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
+    cpx<double>* Bp = E + M * 3 * X;  // the packed blocks of one slice
     cpx<double>* Sp = (cpx<double>*)workspace(c, W_DISC3, (size_t)3 * X * 4 * n * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
     rocblas_handle h = blas_handle(c, &e);
     if (h == nullptr) return e;
     const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    const size_t nfull = (size_t)4 * n * n * n;
     for (int t = 0; t < nt; t++) {
-        cpx<double>* Bt = B + (size_t)t * 4 * n * M;
         for (int x0 = 0; x0 < L3; x0 += X) {
             const int xc = std::min(X, L3 - x0);
             const long long off = (long long)t * L3 + x0;
@@ -284,14 +312,16 @@ dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<doub
             hipLaunchKernelGGL(k_diquarks, dim3((unsigned)((xc + kXT - 1) / kXT)), dim3(kNB), 0, c->stream, n, nsite,
                                off, xc, s, E);
             DD_HIP(c, hipGetLastError());
-            // Bt (n^2 x 4n, column-major) (+)= E (n^2 x 3 xc) Sp (3 xc x 4n)
+            // Bp (P x 4n, column-major) (+)= E (P x 3 xc) Sp (3 xc x 4n)
             const rocblas_status bs = rocblas_zgemm(
                 h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)M, 4 * n, 3 * xc, &one,
                 (const rocblas_double_complex*)E, (rocblas_int)M, (const rocblas_double_complex*)Sp, 3 * xc,
-                x0 == 0 ? &zero : &one, (rocblas_double_complex*)Bt, (rocblas_int)M);
+                x0 == 0 ? &zero : &one, (rocblas_double_complex*)Bp, (rocblas_int)M);
             if (bs != rocblas_status_success)
                 return fail(c, DD_ERR_HIP, std::string("rocblas_zgemm failed: ") + rocblas_status_to_string(bs));
         }
+        hipLaunchKernelGGL(k_unpack_blocks, dim3((unsigned)((nfull + kNB - 1) / kNB)), dim3(kNB), 0, c->stream, n, M,
+                           Bp, B + (size_t)t * nfull);
     }
     DD_HIP(c, hipGetLastError());
     return DD_OK;
