@@ -121,7 +121,8 @@ struct StencilSched {
     int tc = 8;
     int remap = 0;
     int kc = 1;       // columns per thread (even-odd half hop)
-    int blocked = 0;  // tiles as 4 x 4 (y, z) bricks of x rows (even-odd half hop)
+    int blocked = 0;  // even-odd half hop tile flags: bit 0 tiles as 4 x 4 (y, z) bricks of x rows,
+                      // bit 1 the time chunks of a tile in adjacent workgroups
 };
 
 struct TimedLaunch {

@@ -41,18 +41,25 @@ __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R
     if (live == 0) return;  // uniform over the workgroup
     const int nblk = (int)gridDim.x / ngrp;
     const int ntile = ((g.L3 >> 1) + NT - 1) / NT;
+    const int nchunk = nblk / ntile;
+    // bit 1 of the tile flags: the time chunks of one tile are adjacent workgroups (the
+    // slice either side of a chunk, which its neighbour chunks read too, stays in L2);
+    // otherwise the tiles of one chunk are
+    const bool chunk_major = (blocked & 2) != 0;
+    const int tile = chunk_major ? blk / nchunk : blk % ntile;
+    const int chunk = chunk_major ? blk % nchunk : blk / ntile;
+    const int bricks = blocked & 1;
     const size_t off = (size_t)col0 * 12 * (size_t)(g.nsite >> 1);
     double* slot = partial + ((size_t)col0 * nblk + blk) * 3;
     if constexpr (KC == 1)
         eo_sweep_tile<R, DAG, EPI, NT, SELF>(g, U, a_self, c_hop, p_out, in + off,
                                              self != nullptr ? self + off : nullptr, out + off,
-                                             aux != nullptr ? aux + off : nullptr, blk % ntile, blk / ntile, tc_len,
-                                             blocked, slot);
+                                             aux != nullptr ? aux + off : nullptr, tile, chunk, tc_len, bricks, slot);
     else
         eo_sweep_cols<R, DAG, EPI, NT, SELF, KC, REC>(g, U, a_self, c_hop, p_out, in + off,
                                                       self != nullptr ? self + off : nullptr, out + off,
-                                                      aux != nullptr ? aux + off : nullptr, live, blk % ntile,
-                                                      blk / ntile, tc_len, blocked, slot, (size_t)nblk);
+                                                      aux != nullptr ? aux + off : nullptr, live, tile, chunk, tc_len,
+                                                      bricks, slot, (size_t)nblk);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -191,7 +198,8 @@ void launch_eo_kc(hipStream_t s, int kc, bool rec, int epi, dim3 grid, const Geo
 
 // out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
 // time chunks of tc slices, kc columns per thread (eo_kc_ok), workgroups
-// optionally in XCD-contiguous ranges, tiles as rows or bricks (pair_site).
+// optionally in XCD-contiguous ranges; tile flags `blocked`: bit 0 tiles as
+// bricks (pair_site) rather than rows, bit 1 the chunks of a tile adjacent.
 // U: the checkerboard links; U12 (nullable): the same links as two rows each,
 // which launches with kc > 1 read instead.
 template <typename R>
@@ -199,7 +207,7 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, 
                    int p_out, int dag, int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux,
                    int ncol, int tc, int kc, int remap, int blocked, double* partial, const ColState* st) {
     if (!eo_kc_ok<R>(kc, ncol)) kc = 1;
-    if (g.L % 4 != 0) blocked = 0;
+    if (g.L % 4 != 0) blocked &= ~1;
     const bool rec = U12 != nullptr && kc > 1;
     if (rec) U = U12;
     const dim3 grid((unsigned)(eo_blocks(g, tc) * (ncol / kc)));
@@ -269,7 +277,8 @@ struct EOSystem : System {
 // Launch shape of the half-hop sweep for one precision: timed on the Schur
 // operator of this geometry and column count at first use (chunks of 1, 2,
 // 4, 8 slices, workgroups in hardware order or XCD-contiguous ranges, 1 or 2
-// columns per thread where allowed, row or brick tiles), cached in the
+// columns per thread where allowed, row or brick tiles, tiles or chunks
+// adjacent), cached in the
 // context like the stencil shapes; small fields take 4 slices, no remap, one
 // column, row tiles, untimed.
 template <typename R>
@@ -294,8 +303,9 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, const cpx<R>* UR1
             for (int t : {1, 2, 4, 8})
                 for (int rm = 0; rm < 2; rm++)
                     for (int kc : {1, 2})
-                        for (int bl = 0; bl < 2; bl++) {
-                            if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol) || (bl && g.L % 4 != 0)) continue;
+                        for (int bl = 0; bl < 4; bl++) {
+                            if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol) || ((bl & 1) && g.L % 4 != 0)) continue;
+                            if ((bl & 2) && (g.nt + t - 1) / t < 2) continue;  // one chunk: the same order
                             StencilSched sc = best;
                             sc.tc = t;
                             sc.remap = rm;

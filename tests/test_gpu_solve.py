@@ -242,8 +242,9 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     """The XCD remap of the half hop only moves work between workgroups: mixed
     solves give bitwise the same solution.  Columns per thread (the kernel is
     compiled once per count, and the compiler may contract multiply-adds
-    differently in each), the chunk length and the tile shape (both regroup the
-    partial sums) change the rounding only: the solutions agree to 1e-8 with the same
+    differently in each), the chunk length, the tile shape and the order of tiles
+    and chunks over the workgroups (all regroup the partial sums) change the
+    rounding only: the solutions agree to 1e-8 with the same
     iteration counts within a few.  Gaussian and point sources stop at
     different iterations, so stopped columns share workgroups with running
     ones, whose launches must leave the stopped columns' vectors as they were
@@ -261,8 +262,9 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
     tail = f"12:{L}:{T}:{dom[1]}:0"
     xs, its = [], []
+    # bl: tile flags, bit 0 brick tiles, bit 1 the time chunks of a tile in adjacent workgroups
     for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 2, 0), (4, 1, 2, 0), (2, 0, 1, 1),
-                              (4, 1, 2, 1)]:
+                              (4, 1, 2, 1), (2, 1, 1, 2), (2, 1, 2, 2), (1, 0, 2, 3), (2, 1, 2, 3)]:
         path = tmp_path / f"shapes_{tc}_{remap}_{kc}_{bl}.txt"
         path.write_text(f"eo:0:{tail} 256 {tc} {remap} 1 {bl}\neo:1:{tail} 256 {tc} {remap} {kc} {bl}\n")
         monkeypatch.setenv("DD_TUNE_CACHE", str(path))
