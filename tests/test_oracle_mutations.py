@@ -2,17 +2,22 @@
 
 Each case plants one mistake in a copy of the oracle's C source (a flipped sign, a
 dropped factor, a transposed or misplaced link, a wrong index), builds it, points the
-oracle at the copy and requires that at least one of the named pins fails.  Nothing
-here touches the GPU library.
+oracle at the copy and requires that at least one of the named pins fails.  The Python
+cases do the same for one function of the oracle's Python face (rebuilt from its
+source with the mistake, for that test only).  Nothing here touches the GPU library.
 """
+import inspect
 import os
 import subprocess
 
 import pytest
 
 import oracle as O
+import test_oracle_disconnected as TD
 import test_oracle_force as TF
+import test_oracle_nucleon as TN
 import test_oracle_operator as TO
+import test_oracle_projection as TP
 import test_oracle_solve as TS
 
 MUTATIONS = {
@@ -73,3 +78,45 @@ def test_planted_mistake_is_caught(name, tmp_path):
         assert caught > 0, f"planted mistake '{name}' passed every pin"
     finally:
         O.restore_library(prev)
+
+
+# (function, text, replacement, pins)
+PY_MUTATIONS = {
+    "trace without gamma5": ("disconnected_traces", "gamma5(e), dom=dom", "e, dom=dom",
+                             [lambda: TD.test_probing_sources_give_the_exact_trace(-1, None)]),
+    "hop term normalisation": ("hop_power", "out = out - 2.0 * kappa * apply_dirac(",
+                               "out = out - kappa * apply_dirac(",
+                               [lambda: TD.test_probing_sources_give_the_exact_trace(-1, None)]),
+    "trace on the wrong slice": ("disconnected_traces", "tau[:, (t0 + k) % T] = prod[:, k]",
+                                 "tau[:, (t0 + k + 1) % T] = prod[:, k]",
+                                 [lambda: TD.test_probing_sources_give_the_exact_trace(-1, [(3, 2), (1, 2)])]),
+    "frontier spin projector sign": ("hop_spin_projector", "(np.eye(4) + sign * g0) / 2", "(np.eye(4) - sign * g0) / 2",
+                                     [lambda: TP.test_complete_basis_is_no_approximation(-1)]),
+    "projection on the wrong slice": ("_project_slices", "k = (t - t0) % T", "k = (t - t0 + 1) % T",
+                                      [TP.test_projected_chain_vs_dense]),
+    "charge conjugation gamma_0 only": ("charge_conjugation", "return g[0] @ g[2]", "return g[0]",
+                                        [TN.test_block_symmetry_colour_singlet_spin_covariance]),
+    "second nucleon contraction with the first one's order": (
+        "nucleon_factorized", '"xkija,ab,yijkb->yx"', '"xjika,ab,yijkb->yx"',
+        [lambda: TN.test_blocks_equal_the_three_propagator_contraction(5)]),
+    "xi not conjugated": ("nucleon_lines", "xi = np.conj(gamma5(z))", "xi = gamma5(z)",
+                          [lambda: TN.test_blocks_equal_the_three_propagator_contraction(5)]),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
+def test_planted_python_mistake_is_caught(name, monkeypatch):
+    fn, old, new, pins = PY_MUTATIONS[name]
+    src = inspect.getsource(getattr(O, fn))
+    assert src.count(old) == 1, f"mutation anchor not found once: {name}"
+    scope = {}
+    exec(compile(src.replace(old, new), f"<mutant {fn}>", "exec"), O.__dict__, scope)
+    monkeypatch.setattr(O, fn, scope[fn])
+    caught = 0
+    for pin in pins:
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught > 0, f"planted mistake '{name}' passed every pin"
