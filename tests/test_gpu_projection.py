@@ -171,3 +171,39 @@ def test_projection_errors(setup):
             ctx._h, Ud.data_ptr(), KAPPA, srcarr, darr, 2, 0, n, (C.c_int * n)(*ts), (C.c_int * n)(*nv),
             (C.c_void_p * n)(*[phi.data_ptr()] * n), C.byref(params), S.data_ptr(), None, None)
         assert st == dd.DD_ERR_ARG, (ts, nv)
+
+
+def test_basis_at_the_64x32_slab():
+    """24 vectors, one inverse iteration, on the bench's slab [8, 24) of the 64x32^3 workload
+    (slice 15, forward): Phi is orthonormal and spin-projected, and spans the same space as
+    (1 + gamma_0)/2 of D_Pi^-1 V0 on slice 15, built here from plain block solves of the raw
+    start vectors (orthonormalising V0 first does not change that span)."""
+    from paper_1612_06424_amd.inputs import WORKLOADS
+    dd = lib()
+    w = WORKLOADS["64x32^3"]
+    Tw, Lw, kappa = w["T"], w["L"], w["kappa"]
+    L3w = Lw ** 3
+    step("projection basis 64x32^3 slab")
+    U = dd.pack_links(random_links(Tw, Lw, w["eps"], w["link_seed"]))
+    ctx = dd.Context(Tw, Lw, w["bc"])
+    pi, t, n = (8, 16), 15, 24
+    g = torch.Generator(device="cuda")
+    g.manual_seed(830)
+    v0 = torch.randn((n, 12, pi[1] * L3w), dtype=torch.complex128, device="cuda", generator=g)
+    p = dd.solver_params(tol=1e-12, max_iter=20000, prec=dd.DD_FP64, solver=dd.DD_CGNR)
+    phi, stats = dd.projection_basis(ctx, U, kappa, pi, t, +1, v0, 1, p)
+    P = phi.reshape(n, -1)
+    G = P.conj() @ P.T
+    assert (G - torch.eye(n, dtype=G.dtype, device=G.device)).abs().max().item() < 1e-12
+    assert (phi[:, :6] + phi[:, 6:]).abs().max().item() < 1e-13   # (1 + gamma_0)/2: lower = -upper
+    k = t - pi[0]
+    W = torch.empty((n, 12, L3w), dtype=torch.complex128, device="cuda")
+    for a0 in range(0, n, 12):
+        x, _ = dd.block_solve(ctx, U, kappa, v0[a0:a0 + 12].contiguous(), pi, p)
+        xs = x[:, :, k * L3w:(k + 1) * L3w]
+        up = 0.5 * (xs[:, :6] - xs[:, 6:])
+        W[a0:a0 + 12, :6] = up
+        W[a0:a0 + 12, 6:] = -up
+    Wm = W.reshape(n, -1)
+    rest = Wm - (Wm @ P.conj().T) @ P
+    assert (torch.linalg.vector_norm(rest) / torch.linalg.vector_norm(Wm)).item() < 1e-9
