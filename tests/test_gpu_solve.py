@@ -387,3 +387,39 @@ def test_solves_and_factorised_at_64x32():
             r = r - b
         rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
         assert rel <= 4 * w["tol"], (k, rel)
+
+
+def test_force_at_32x16():
+    """The bench's force workload (32x16^3, Dirichlet time, one Gaussian field): the link
+    force from the adjoint solve against a central difference of the action along
+    U + h i X U, X a random hermitian traceless field on every link (FP64 solves at tol
+    1e-12, h = 1e-4); PyTorch's complex convention makes the derivative
+    Re sum conj(grad_U) i X U."""
+    from paper_1612_06424_amd.inputs import WORKLOADS
+    dd = lib()
+    w = WORKLOADS["force-32x16^3"]
+    T, L, kappa = w["T"], w["L"], w["kappa"]
+    V = T * L ** 3
+    step("force 32x16^3")
+    U0 = dd.pack_links(random_links(T, L, w["eps"], w["link_seed"]))
+    phi = dd.pack_field(gaussian_field(V, 1, w["phi_seed"]))
+    ctx = dd.Context(T, L, w["bc"])
+    p = dd.solver_params(tol=1e-12, max_iter=20000, prec=dd.DD_FP64, solver=dd.DD_CGNR)
+    Ug = U0.clone().requires_grad_(True)
+    S = dd.DomainActionFn.apply(Ug, phi, ctx, kappa, None, p)
+    S.backward()
+    g = Ug.grad
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w["fd_seed"])
+    A = torch.randn((V, 4, 3, 3), dtype=torch.complex128, device="cuda", generator=gen)
+    X = 0.5 * (A + A.conj().transpose(-1, -2))
+    X = X - torch.diagonal(X, dim1=-2, dim2=-1).sum(-1)[..., None, None] / 3 * torch.eye(3, device="cuda")
+    Un = U0.permute(2, 0, 1).reshape(V, 4, 3, 3)
+    dU = (1j * (X @ Un)).reshape(V, 4, 9).permute(1, 2, 0).contiguous()
+    pred = (g.conj() * dU).real.sum().item()
+    h = 1e-4
+    Sp, _, _, _ = dd.domain_action(ctx, (U0 + h * dU).contiguous(), kappa, phi, None, p)
+    Sm, _, _, _ = dd.domain_action(ctx, (U0 - h * dU).contiguous(), kappa, phi, None, p)
+    fd = (Sp - Sm) / (2 * h)
+    assert abs(pred) > 1e-6 * abs(S.item())
+    assert abs(fd - pred) <= 1e-6 * abs(pred), (fd, pred)
