@@ -337,7 +337,8 @@ def test_even_odd_adjoint_and_fallback():
 
 def test_solves_and_factorised_at_64x32():
     """The bench's configuration (64x32^3, eps 0.15, kappa 0.135, 12 point sources at the
-    origin): the slab solves on [0, 16) in FP64 and mixed precision leave a true residual
+    origin; the pion correlator against a plain sum of |S|^2 per slice): the slab solves on
+    [0, 16) in FP64 and mixed precision leave a true residual
     b - D_Lambda x within tol, checked with the full-operator stencil (not the even-odd path
     that solved), and agree with each other; every slab of the four-slab factorised
     propagator satisfies its equation of the chain, D_Lk psi_k = eta on the source slab and
@@ -370,6 +371,10 @@ def test_solves_and_factorised_at_64x32():
     doms = w["domains"]
     p = dd.solver_params(tol=w["tol"], max_iter=20000, prec=dd.DD_MIXED, solver=dd.DD_CGNR)
     Sf, _, _ = dd.factorized_propagator(ctx, U, kappa, w["sources"][0], doms, p)
+    # the pion correlator of it (source slice 0) against a plain sum of |S|^2 per slice
+    C = dd.pion_correlator(ctx, Sf, 0)
+    Cref = (Sf.real ** 2 + Sf.imag ** 2).reshape(144, T, L3).sum(dim=(0, 2)).cpu().numpy()
+    assert np.abs(C - Cref).max() < 1e-12 * Cref.max()
     psi = [Sf[:, :, t0 * L3:(t0 + nt) * L3].contiguous() for t0, nt in doms]
     del Sf
     feeds = {0: [], 1: [0], 3: [0], 2: [1, 3]}
