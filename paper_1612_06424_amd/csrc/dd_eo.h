@@ -284,7 +284,8 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
 // its stores go through a buffer resource of size 0 otherwise, which drops
 // them without a branch.  REC: Ueo holds only the first two rows of every link
 // (Ueo12[mu][k < 6][parity][nsite / 2]) and the third is rebuilt (bload_link_r).
-template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC>
+// NTS: the output stores are non-temporal.
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC, bool NTS = false>
 __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
                                               int p_out, const cpx<R>* __restrict__ in,
                                               const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
@@ -423,7 +424,8 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
                     cpx<R> q = mk<R>(0, 0);
                     if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
                     if (EPI == EPI_RESID) r = q - r;
-                    bstore<R>(ro[k], vo, (uint32_t)c * cs, r);
+                    if constexpr (NTS) bstore_nt<R>(ro[k], vo, (uint32_t)c * cs, r);
+                    else bstore<R>(ro[k], vo, (uint32_t)c * cs, r);
                     if (EPI == EPI_DOT_AUX) {
                         d[k][0] += (double)q.re * r.re + (double)q.im * r.im;
                         d[k][1] += (double)q.re * r.im - (double)q.im * r.re;

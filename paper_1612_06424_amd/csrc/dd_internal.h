@@ -122,7 +122,8 @@ struct StencilSched {
     int remap = 0;
     int kc = 1;       // columns per thread (even-odd half hop)
     int blocked = 0;  // even-odd half hop tile flags: bit 0 tiles as 4 x 4 (y, z) bricks of x rows,
-                      // bit 1 the time chunks of a tile in adjacent workgroups
+                      // bit 1 the time chunks of a tile in adjacent workgroups, bit 2 non-temporal
+                      // output stores (two columns per thread)
 };
 
 struct TimedLaunch {

@@ -103,6 +103,18 @@ template <>
 __device__ __forceinline__ void bstore<float>(rsrc_t r, uint32_t voff, uint32_t soff, cpx<float> v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
 }
+// The same stores marked non-temporal (cache-policy bit nt), for outputs the launch
+// does not read again.
+template <typename R>
+__device__ __forceinline__ void bstore_nt(rsrc_t r, uint32_t voff, uint32_t soff, cpx<R> v);
+template <>
+__device__ __forceinline__ void bstore_nt<double>(rsrc_t r, uint32_t voff, uint32_t soff, cpx<double> v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)voff, (int)soff, 2);
+}
+template <>
+__device__ __forceinline__ void bstore_nt<float>(rsrc_t r, uint32_t voff, uint32_t soff, cpx<float> v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 2);
+}
 
 // spinor of local site s from a field resource with component stride cs (bytes)
 template <typename R>

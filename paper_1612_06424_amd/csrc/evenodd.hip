@@ -23,14 +23,12 @@ namespace {
 // Workgroup -> (group of KC columns fastest, tile of NT pairs of a slice, chunk
 // of tc_len slices); partial slot of (col, block) = col * nblk + block.  ncol is
 // a multiple of KC.  REC: U holds two rows per link (KC > 1 only).
-template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC>
-__global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self,
-                                                             R c_hop, int p_out, const cpx<R>* __restrict__ in,
-                                                             const cpx<R>* __restrict__ self,
-                                                             cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
-                                                             int ncol, int tc_len, int remap, int blocked,
-                                                             double* __restrict__ partial,
-                                                             const ColState* __restrict__ st) {
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC, bool NTS>
+__device__ __forceinline__ void eo_hop_body(const Geo& g, const cpx<R>* __restrict__ U, R a_self, R c_hop, int p_out,
+                                            const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ self,
+                                            cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux, int ncol,
+                                            int tc_len, int remap, int blocked, double* __restrict__ partial,
+                                            const ColState* __restrict__ st) {
     const int lb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int ngrp = ncol / KC;
     const int col0 = (lb % ngrp) * KC, blk = lb / ngrp;
@@ -56,10 +54,35 @@ __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R
                                              self != nullptr ? self + off : nullptr, out + off,
                                              aux != nullptr ? aux + off : nullptr, tile, chunk, tc_len, bricks, slot);
     else
-        eo_sweep_cols<R, DAG, EPI, NT, SELF, KC, REC>(g, U, a_self, c_hop, p_out, in + off,
+        eo_sweep_cols<R, DAG, EPI, NT, SELF, KC, REC, NTS>(g, U, a_self, c_hop, p_out, in + off,
                                                       self != nullptr ? self + off : nullptr, out + off,
                                                       aux != nullptr ? aux + off : nullptr, live, tile, chunk, tc_len,
                                                       bricks, slot, (size_t)nblk);
+}
+
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC>
+__global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop(Geo g, const cpx<R>* __restrict__ U, R a_self,
+                                                             R c_hop, int p_out, const cpx<R>* __restrict__ in,
+                                                             const cpx<R>* __restrict__ self,
+                                                             cpx<R>* __restrict__ out, const cpx<R>* __restrict__ aux,
+                                                             int ncol, int tc_len, int remap, int blocked,
+                                                             double* __restrict__ partial,
+                                                             const ColState* __restrict__ st) {
+    eo_hop_body<R, DAG, EPI, NT, SELF, KC, REC, false>(g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc_len,
+                                                       remap, blocked, partial, st);
+}
+
+// The same half hop with non-temporal output stores (KC > 1).
+template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC>
+__global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop_nt(Geo g, const cpx<R>* __restrict__ U, R a_self,
+                                                                R c_hop, int p_out, const cpx<R>* __restrict__ in,
+                                                                const cpx<R>* __restrict__ self,
+                                                                cpx<R>* __restrict__ out,
+                                                                const cpx<R>* __restrict__ aux, int ncol, int tc_len,
+                                                                int remap, int blocked, double* __restrict__ partial,
+                                                                const ColState* __restrict__ st) {
+    eo_hop_body<R, DAG, EPI, NT, SELF, KC, REC, true>(g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc_len,
+                                                      remap, blocked, partial, st);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -150,14 +173,18 @@ constexpr int kEoNT = 256;
 // workgroups per column: tiles of kEoNT pairs per slice x chunks of tc slices
 int eo_blocks(const Geo& g, int tc) { return (((g.L3 >> 1) + kEoNT - 1) / kEoNT) * ((g.nt + tc - 1) / tc); }
 
-template <typename R, int DAG, bool SELF, int KC, bool REC>
+template <typename R, int DAG, bool SELF, int KC, bool REC, bool NTS>
 void launch_eo_epi(hipStream_t s, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self, R c_hop, int p_out,
                    const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol, int tc,
                    int remap, int blocked, double* partial, const ColState* st) {
     const dim3 block(kEoNT);
-#define DD_EO_CASE(E)                                                                                            \
-    hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF, KC, REC>), grid, block, 0, s, g, U, a_self, c_hop, p_out, \
-                       in, self, out, aux, ncol, tc, remap, blocked, partial, st)
+#define DD_EO_CASE(E)                                                                                              \
+    if constexpr (NTS)                                                                                             \
+        hipLaunchKernelGGL((k_eo_hop_nt<R, DAG, E, kEoNT, SELF, KC, REC>), grid, block, 0, s, g, U, a_self, c_hop, \
+                           p_out, in, self, out, aux, ncol, tc, remap, blocked, partial, st);                      \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_eo_hop<R, DAG, E, kEoNT, SELF, KC, REC>), grid, block, 0, s, g, U, a_self, c_hop,    \
+                           p_out, in, self, out, aux, ncol, tc, remap, blocked, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EO_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_EO_CASE(EPI_DOT_AUX); break;
@@ -179,27 +206,33 @@ bool eo_kc_ok(int kc, int ncol) {
 }
 
 template <typename R, int D, bool SF>
-void launch_eo_kc(hipStream_t s, int kc, bool rec, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R a_self,
-                  R c_hop, int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux, int ncol,
-                  int tc, int remap, int blocked, double* partial, const ColState* st) {
-#define DD_EO_KC(K, REC)                                                                                         \
-    launch_eo_epi<R, D, SF, K, REC>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, \
-                                    blocked, partial, st)
+void launch_eo_kc(hipStream_t s, int kc, bool rec, bool nts, int epi, dim3 grid, const Geo& g, const cpx<R>* U,
+                  R a_self, R c_hop, int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux,
+                  int ncol, int tc, int remap, int blocked, double* partial, const ColState* st) {
+#define DD_EO_KC(K, REC, NTS)                                                                                          \
+    launch_eo_epi<R, D, SF, K, REC, NTS>(s, epi, grid, g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc, remap, \
+                                         blocked, partial, st)
     if constexpr (sizeof(R) == 4) {
         if (kc == 2) {
-            if (rec) DD_EO_KC(2, true);
-            else DD_EO_KC(2, false);
+            if (rec) {
+                if (nts) DD_EO_KC(2, true, true);
+                else DD_EO_KC(2, true, false);
+            } else {
+                if (nts) DD_EO_KC(2, false, true);
+                else DD_EO_KC(2, false, false);
+            }
             return;
         }
     }
-    DD_EO_KC(1, false);
+    DD_EO_KC(1, false, false);
 #undef DD_EO_KC
 }
 
 // out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
 // time chunks of tc slices, kc columns per thread (eo_kc_ok), workgroups
 // optionally in XCD-contiguous ranges; tile flags `blocked`: bit 0 tiles as
-// bricks (pair_site) rather than rows, bit 1 the chunks of a tile adjacent.
+// bricks (pair_site) rather than rows, bit 1 the chunks of a tile adjacent,
+// bit 2 non-temporal output stores (k_eo_hop_nt; FP32 with kc > 1 only).
 // U: the checkerboard links; U12 (nullable): the same links as two rows each,
 // which launches with kc > 1 read instead.
 template <typename R>
@@ -208,14 +241,16 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, 
                    int ncol, int tc, int kc, int remap, int blocked, double* partial, const ColState* st) {
     if (!eo_kc_ok<R>(kc, ncol)) kc = 1;
     if (g.L % 4 != 0) blocked &= ~1;
+    const bool nts = (blocked & 4) && kc > 1;
+    blocked &= 3;
     const bool rec = U12 != nullptr && kc > 1;
     if (rec) U = U12;
     const dim3 grid((unsigned)(eo_blocks(g, tc) * (ncol / kc)));
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_EO_LAUNCH(D, SF)                                                                                           \
-    launch_eo_kc<R, D, SF>(c->stream, kc, rec, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, aux, \
-                           ncol, tc, remap, blocked, partial, st)
+    launch_eo_kc<R, D, SF>(c->stream, kc, rec, nts, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, \
+                           aux, ncol, tc, remap, blocked, partial, st)
     const bool sf = self != nullptr && a_self != 0;
     if (dag) {
         if (sf) DD_EO_LAUNCH(1, true);
@@ -233,7 +268,7 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, 
         const double extra = (a_self != 0 || epi == EPI_TS ? 24.0 : 0.0) +
                              (epi == EPI_DOT_AUX || epi == EPI_RESID ? 24.0 : 0.0);
         const double bytes = nh * ((48.0 + extra) * ncol + (rec ? 96.0 : 144.0)) * sizeof(R);
-        const std::string name = std::string("k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+        const std::string name = std::string(nts ? "k_eo_hop_nt<" : "k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
                                  std::to_string(kEoNT) + (sf ? ", true, " : ", false, ") + std::to_string(kc) +
                                  (rec ? ", true>" : ", false>");
@@ -278,7 +313,7 @@ struct EOSystem : System {
 // operator of this geometry and column count at first use (chunks of 1, 2,
 // 4, 8 slices, workgroups in hardware order or XCD-contiguous ranges, 1 or 2
 // columns per thread where allowed, row or brick tiles, tiles or chunks
-// adjacent), cached in the
+// adjacent, plain or non-temporal output stores with two columns), cached in the
 // context like the stencil shapes; small fields take 4 slices, no remap, one
 // column, row tiles, untimed.
 template <typename R>
@@ -303,8 +338,9 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, const cpx<R>* UR1
             for (int t : {1, 2, 4, 8})
                 for (int rm = 0; rm < 2; rm++)
                     for (int kc : {1, 2})
-                        for (int bl = 0; bl < 4; bl++) {
+                        for (int bl = 0; bl < 8; bl++) {
                             if (t > g.nt || !eo_kc_ok<R>(kc, S.ncol) || ((bl & 1) && g.L % 4 != 0)) continue;
+                            if ((bl & 4) && kc == 1) continue;  // non-temporal stores: kc > 1 only
                             if ((bl & 2) && (g.nt + t - 1) / t < 2) continue;  // one chunk: the same order
                             StencilSched sc = best;
                             sc.tc = t;

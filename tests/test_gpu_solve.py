@@ -239,8 +239,9 @@ def test_even_odd_matches_full_operator(prec, solver, T, L, bc, dom):
 
 @pytest.mark.parametrize("solver", [0, 1])
 def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
-    """The XCD remap of the half hop only moves work between workgroups: mixed
-    solves give bitwise the same solution.  Columns per thread (the kernel is
+    """The XCD remap of the half hop only moves work between workgroups, and
+    non-temporal output stores only change a cache policy: mixed solves give
+    bitwise the same solution.  Columns per thread (the kernel is
     compiled once per count, and the compiler may contract multiply-adds
     differently in each), the chunk length, the tile shape and the order of tiles
     and chunks over the workgroups (all regroup the partial sums) change the
@@ -262,9 +263,11 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=solver)
     tail = f"12:{L}:{T}:{dom[1]}:0"
     xs, its = [], []
-    # bl: tile flags, bit 0 brick tiles, bit 1 the time chunks of a tile in adjacent workgroups
+    # bl: tile flags, bit 0 brick tiles, bit 1 the time chunks of a tile in adjacent workgroups,
+    # bit 2 non-temporal output stores (two columns per thread)
     for tc, remap, kc, bl in [(2, 0, 1, 0), (2, 1, 1, 0), (2, 0, 2, 0), (2, 1, 2, 0), (4, 1, 2, 0), (2, 0, 1, 1),
-                              (4, 1, 2, 1), (2, 1, 1, 2), (2, 1, 2, 2), (1, 0, 2, 3), (2, 1, 2, 3)]:
+                              (4, 1, 2, 1), (2, 1, 1, 2), (2, 1, 2, 2), (1, 0, 2, 3), (2, 1, 2, 3), (2, 1, 2, 4),
+                              (2, 1, 2, 7)]:
         path = tmp_path / f"shapes_{tc}_{remap}_{kc}_{bl}.txt"
         path.write_text(f"eo:0:{tail} 256 {tc} {remap} 1 {bl}\neo:1:{tail} 256 {tc} {remap} {kc} {bl}\n")
         monkeypatch.setenv("DD_TUNE_CACHE", str(path))
@@ -274,6 +277,8 @@ def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
         xs.append(x)
         its.append(stats["iters"])
     assert torch.equal(xs[1], xs[0])
+    # non-temporal stores change a cache policy, nothing in the arithmetic
+    assert torch.equal(xs[11], xs[3]) and torch.equal(xs[12], xs[10])
     for x, it in zip(xs[2:], its[2:]):
         assert relerr(dd.unpack_field(x), dd.unpack_field(xs[0])) < 1e-8
         assert abs(it - its[0]) <= 4
