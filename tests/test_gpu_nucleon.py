@@ -31,7 +31,8 @@ def _blocks_to_dev(B):
     return torch.as_tensor(np.ascontiguousarray(B.transpose(0, 3, 4, 1, 2))).to("cuda")
 
 
-@pytest.mark.parametrize("n,nt,L,chunk", [(5, 3, 4, None), (13, 2, 4, None), (13, 2, 4, 24), (7, 1, 6, 50)])
+@pytest.mark.parametrize("n,nt,L,chunk", [(1, 2, 4, None), (5, 3, 4, None), (13, 2, 4, None), (13, 2, 4, 24),
+                                         (7, 1, 6, 50)])
 def test_baryon_blocks_vs_oracle(n, nt, L, chunk):
     dd = lib()
     step(f"baryon blocks n={n} nt={nt} L={L} chunk={chunk}")
@@ -150,3 +151,32 @@ def test_sampled_blocks_at_the_32_cubed_slice():
         want = np.einsum("abc,rax,rs,sbx,cx->", EPS, q[i], cg5, q[j], q[k, al], optimize=True)
         got = Bh[k, al, i, j].item()
         assert abs(got - want) < 1e-12 * np.sqrt(6 * 16 * L3) * 4, (i, j, k, al, got, want)
+
+
+def test_the_maximum_vector_count():
+    """256 vectors (the largest basis): blocks on one 4^3 slice sampled against sums from the
+    definition (the pair index reaches 256 * 257 / 2 - 1 and every (i, j) order is unpacked),
+    and the contraction of random 256-vector blocks against the oracle."""
+    dd = lib()
+    step("nucleon 256 vectors")
+    L, n = 4, 256
+    L3 = L ** 3
+    ctx = dd.Context(8, L, -1)
+    s = gaussian_field(L3, n, 4500)
+    B = dd.baryon_blocks(ctx, dd.pack_field(s))[0].cpu().numpy()   # [k][alpha][i][j]
+    q = s.reshape(n, L3, 4, 3)
+    cg5 = O.charge_conjugation() @ O.gamma_matrices()[4]
+    rng = np.random.default_rng(4501)
+    idx = [tuple(int(v) for v in rng.integers(0, n, 3)) + (int(rng.integers(0, 4)),) for _ in range(16)]
+    idx += [(0, n - 1, n - 1, 3), (n - 1, n - 1, 0, 0), (n - 1, 0, n - 2, 1), (n - 2, n - 1, 7, 2)]
+    for i, j, k, al in idx:
+        want = np.einsum("abc,xra,rs,xsb,xc->", EPS, q[i], cg5, q[j], q[k, :, al, :], optimize=True)
+        assert abs(B[k, al, i, j] - want) < 1e-12 * max(1.0, abs(want)) * 10, (i, j, k, al)
+    assert np.abs(B - B.transpose(0, 1, 3, 2)).max() < 1e-12 * np.abs(B).max()
+    del B
+    Bx = rng.standard_normal((1, n, n, n, 4)) + 1j * rng.standard_normal((1, n, n, n, 4))
+    By = rng.standard_normal((1, n, n, n, 4)) + 1j * rng.standard_normal((1, n, n, n, 4))
+    W1r, W2r, _ = O.nucleon_factorized(L, Bx, By)
+    W1, W2 = dd.nucleon_contract(ctx, _blocks_to_dev(Bx), _blocks_to_dev(By))
+    scale = max(np.abs(W1r).max(), np.abs(W2r).max())
+    assert np.abs(W1 - W1r).max() < 1e-11 * scale and np.abs(W2 - W2r).max() < 1e-11 * scale
