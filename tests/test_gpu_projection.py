@@ -207,3 +207,23 @@ def test_basis_at_the_64x32_slab():
     Wm = W.reshape(n, -1)
     rest = Wm - (Wm @ P.conj().T) @ P
     assert (torch.linalg.vector_norm(rest) / torch.linalg.vector_norm(Wm)).item() < 1e-9
+
+
+@pytest.mark.parametrize("nvec", [1, 256])
+def test_basis_sizes_one_and_maximum(nvec):
+    """The extremes of the basis size on a 4^3 slice (6 L^3 = 384 directions): one vector,
+    and 256, the most the library takes (single-workgroup Cholesky factor, the combine
+    kernel's matrix in LDS at its limit); projectors against the oracle's (FP64)."""
+    dd = lib()
+    step(f"projection basis nvec={nvec}")
+    Tb, Lb = 8, 4
+    U = random_links(Tb, Lb, 0.3, 840)
+    v0 = gaussian_field(3 * Lb ** 3, nvec, 841)
+    ref, _ = O.projection_basis(U, KAPPA, Tb, Lb, -1, (2, 3), 3, +1, v0, 1, tol=1e-13)
+    ctx = dd.Context(Tb, Lb, -1)
+    phi, _ = dd.projection_basis(ctx, dd.pack_links(U), KAPPA, (2, 3), 3, +1, dd.pack_field(v0), 1,
+                                 _params(dd, "fp64"))
+    got = _from_dev(phi)
+    G = got.reshape(nvec, -1).conj() @ got.reshape(nvec, -1).T
+    assert np.abs(G - np.eye(nvec)).max() < 1e-12
+    assert relerr(_projector(got), _projector(ref)) < 1e-10
