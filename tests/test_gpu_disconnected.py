@@ -127,3 +127,20 @@ def test_hop_identity_on_the_64x32_workload():
     for t0, nt in doms:
         tot = tau8[:, t0:t0 + nt].sum(dim=1)
         assert (tot.imag.abs().max() / tot.abs().max()).item() < 1e-6
+
+
+def test_one_source_and_the_most_hop_powers():
+    """A single source, and 16 powers of kappa D_hop (the most the library takes), on two slabs
+    and the whole lattice against the oracle (FP64)."""
+    dd = lib()
+    T, L, bc, kappa = 16, 4, -1, 0.13
+    U = random_links(T, L, 0.3, 3100)
+    ctx = dd.Context(T, L, bc)
+    Ud = dd.pack_links(U)
+    p = _params(dd, "fp64")
+    for nsrc, n_hop, doms in ((1, 8, [(0, 9), (9, 7)]), (3, 16, [(0, 9), (9, 7)]), (1, 16, None)):
+        step(f"disconnected nsrc={nsrc} n_hop={n_hop} doms={doms}")
+        eta = gaussian_field(T * L ** 3, nsrc, 3101)
+        ref = O.disconnected_traces(U, kappa, T, L, bc, eta, doms, n_hop=n_hop, tol=1e-13, method=1)
+        tau, _ = dd.disconnected_traces(ctx, Ud, kappa, dd.pack_field(eta), doms, n_hop, p)
+        assert relerr(tau.cpu().numpy(), ref) < 1e-10
