@@ -35,3 +35,15 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_every_symbol():
     import paper_1612_06424_amd.dd as dd
     assert sorted(dd.EXPORTS) == declared_symbols()
+
+
+@pytest.mark.parametrize("compiler,std,lang", [("gcc", "c99", "c"), ("g++", "c++17", "c++")])
+def test_header_is_plain_c_and_cpp(compiler, std, lang):
+    """include/dd.h is a C header (the boundary takes no C++ or torch types): it compiles on
+    its own as C99 and as C++17 without warnings."""
+    import shutil
+    import subprocess
+    if shutil.which(compiler) is None:
+        pytest.skip(f"{compiler} not available")
+    hdr = os.path.join(ROOT, "include", "dd.h")
+    subprocess.check_call([compiler, "-fsyntax-only", f"-std={std}", "-Wall", "-Wextra", "-Werror", "-x", lang, hdr])
