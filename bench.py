@@ -261,6 +261,7 @@ def main():
             t0 = time.perf_counter()
             basis, pst = dd.projection_basis(ctx, U64, kappa, proj_pi, proj_t, +1, proj_v0, proj_iter, pmx)
             t1 = time.perf_counter()
+            log(f"projection: basis {t1 - t0:.1f}s")
             Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx,
                                                   projections={proj_t: basis})
             Cf = dd.pion_correlator(ctx, Sf, src[0])
@@ -280,6 +281,7 @@ def main():
             tau_f, dst = dd.disconnected_traces(ctx, U64, kappa, disc_eta, disc_doms, disc_hop, pmx)
             Cf = dd.disconnected_correlator(ctx, tau_f)
             t1 = time.perf_counter()
+            log(f"disconnected: domains {t1 - t0:.1f}s")
             tau_w, wst = dd.disconnected_traces(ctx, U64, kappa, disc_eta, None, disc_hop, pmx)
             Cw = dd.disconnected_correlator(ctx, tau_w)
             t2 = time.perf_counter()
