@@ -101,6 +101,19 @@ PY_MUTATIONS = {
         [lambda: TN.test_blocks_equal_the_three_propagator_contraction(5)]),
     "xi not conjugated": ("nucleon_lines", "xi = np.conj(gamma5(z))", "xi = gamma5(z)",
                           [lambda: TN.test_blocks_equal_the_three_propagator_contraction(5)]),
+    "frontier term added instead of subtracted": (
+        "factorized_propagator", "rhs -= block_apply(U, kappa, T, L, bc, dk, domains[j], hj)",
+        "rhs += block_apply(U, kappa, T, L, bc, dk, domains[j], hj)",
+        [lambda: TS.test_factorised_chain_vs_dense([(0, 4), (4, 4)], -1)]),
+    "chain fed from the source slab only": (
+        "factorized_propagator", "if dist[j] == dist[k] - 1:", "if dist[j] == 0:",
+        [lambda: TS.test_factorised_chain_vs_dense([(0, 2), (2, 2), (4, 2), (6, 2)], -1)]),
+    "overlap grown forward only": ("extended_domain", "return ((t0 - overlap) % T, nt + 2 * overlap)",
+                                   "return (t0 % T, nt + overlap)",
+                                   [lambda: TS.test_factorised_overlap_vs_dense([(0, 6), (6, 6)], 1, -1)]),
+    "overlap solution crossing from the extension": (
+        "factorized_propagator", "hop[k] = xe[:, a:b]", "hop[k] = xe[:, :b - a]",
+        [lambda: TS.test_factorised_overlap_vs_dense([(0, 6), (6, 6)], 2, -1)]),
 }
 
 

@@ -121,7 +121,8 @@ def test_block_inverse_schur_and_factorisation_identities():
                                      [(6, 3), (1, 3), (4, 2)]])
 @pytest.mark.parametrize("bc", [-1, 0])
 def test_factorised_chain_vs_dense(domains, bc):
-    """O7 chain against dense block products, including a ring of four slabs."""
+    """The factorised chain over several slabs (Eqs. 13-14 chained outward by block
+    distance) against dense block products, including a ring of four slabs."""
     T, L, kappa = 8, 2, 0.14
     if bc == 0 and domains[0][0] != 0:
         pytest.skip("open time edge: slabs must start at 0 for a chain")
