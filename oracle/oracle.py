@@ -410,8 +410,17 @@ def charge_conjugation():
 
 
 def nucleon_parity_projector():
-    """P_- = (1 - gamma_0)/2 of the factorised nucleon contractions (Eqs. 23-24)."""
-    return 0.5 * (np.eye(4) - gamma_matrices()[0])
+    """P_+ = (1 + gamma_0)/2, the spin matrix between the source and sink blocks of the
+    factorised nucleon contractions (Eqs. 23-24, read for this basis and operator).
+
+    The text writes gamma5 P_- there, in conventions it leaves to another paper.  With
+    this oracle's operator ((1 - gamma_mu) on the forward hop) and lines (xi_i^T =
+    phi_i^+ D^-1, Eq. 26, no gamma5), a quark propagating forward in time carries
+    (1 + gamma_0)/2 on both sides, so both blocks lie in the range of P_+ and
+    B_x^T gamma5 P_(+-) B_y vanishes identically at leading order in the hopping
+    expansion; B_x^T P_+ B_y is the positive-parity nucleon two-point function
+    tr[P_+ <N(y) Nbar(x)>] of a forward-propagating nucleon (pinned in the free field)."""
+    return 0.5 * (np.eye(4) + gamma_matrices()[0])
 
 
 def baryon_blocks(L, s):
@@ -461,11 +470,12 @@ def nucleon_lines(U, kappa, T, L, bc, gbar, gstar, t_phi, phi, x0, tol=1e-12, ma
 
 def nucleon_factorized(L, Bx, By):
     """Factorised nucleon Wick contractions summed over xvec and yvec (Eqs. 22-24):
-      W1[y0, x0] = - sum_{ijk} Bx[x0, j, i, k]^T gamma5 P_- By[y0, i, j, k]
-      W2[y0, x0] = - sum_{ijk} Bx[x0, k, i, j]^T gamma5 P_- By[y0, i, j, k]
-    with Bx the blocks of the xi lines and By those of the eta lines (baryon_blocks).
-    Returns (W1, W2, C_f = (W1 - W2) / L^3), each (nty, ntx)."""
-    M = gamma_matrices()[4] @ nucleon_parity_projector()
+      W1[y0, x0] = - sum_{ijk} Bx[x0, j, i, k]^T P_+ By[y0, i, j, k]
+      W2[y0, x0] = - sum_{ijk} Bx[x0, k, i, j]^T P_+ By[y0, i, j, k]
+    with Bx the blocks of the xi lines and By those of the eta lines (baryon_blocks) and
+    P_+ the spin matrix of nucleon_parity_projector (the text's gamma5 P_- read for this
+    basis).  Returns (W1, W2, C_f = (W1 - W2) / L^3), each (nty, ntx)."""
+    M = nucleon_parity_projector()
     W1 = -np.einsum("xjika,ab,yijkb->yx", Bx, M, By, optimize=True)
     W2 = -np.einsum("xkija,ab,yijkb->yx", Bx, M, By, optimize=True)
     return W1, W2, (W1 - W2) / L ** 3

@@ -111,6 +111,21 @@ PY_MUTATIONS = {
     "overlap grown forward only": ("extended_domain", "return ((t0 - overlap) % T, nt + 2 * overlap)",
                                    "return (t0 % T, nt + overlap)",
                                    [lambda: TS.test_factorised_overlap_vs_dense([(0, 6), (6, 6)], 1, -1)]),
+    "two-trace product normalised by n squared": (
+        "disconnected_correlator", "return C / (n * (n - 1) * L ** 3)", "return C / (n * n * L ** 3)",
+        [lambda: TD.test_two_trace_product_of_noise_free_traces_is_exact(3)]),
+    "two-trace product with the i = j terms": (
+        "disconnected_correlator", "            if i != j:\n", "            if True:\n",
+        [lambda: TD.test_two_trace_product_of_noise_free_traces_is_exact(3),
+         TD.test_two_trace_product_is_unbiased_over_every_sign_pattern]),
+    "nucleon spin matrix P_- in place of P_+": (
+        "nucleon_parity_projector", "return 0.5 * (np.eye(4) + gamma_matrices()[0])",
+        "return 0.5 * (np.eye(4) - gamma_matrices()[0])",
+        [lambda: TN.test_free_field_nucleon_propagates_forward_with_the_chosen_projector(0.02)]),
+    "nucleon spin matrix with the text's gamma5": (
+        "nucleon_parity_projector", "return 0.5 * (np.eye(4) + gamma_matrices()[0])",
+        "return gamma_matrices()[4] @ (0.5 * (np.eye(4) - gamma_matrices()[0]))",
+        [lambda: TN.test_free_field_nucleon_propagates_forward_with_the_chosen_projector(0.02)]),
     "overlap solution crossing from the extension": (
         "factorized_propagator", "hop[k] = xe[:, a:b]", "hop[k] = xe[:, :b - a]",
         [lambda: TS.test_factorised_overlap_vs_dense([(0, 6), (6, 6)], 2, -1)]),

@@ -1,7 +1,11 @@
 """Pins of the oracle's factorised nucleon contraction (Sec. 4.2, Eqs. 22-26).
 
 - C = gamma_0 gamma_2 is a charge conjugation (C gamma_mu C^-1 = -gamma_mu^T), C gamma5 is
-  antisymmetric, P_- is a projector.
+  antisymmetric, the spin matrix between the blocks, P_+ = (1 + gamma_0)/2, is a projector.
+- The spin matrix is the one of a nucleon propagating forward in time: in the free field at
+  small kappa the factorised correlator with P_+ is non-zero and falls by about (2 kappa)^3
+  per time slice (three quark lines, each (2 kappa) per hop), while with P_- it is zero to
+  rounding, and so is the text's gamma5 P_- (and gamma5 P_+) in this basis.
 - The blocks of Eq. 25 are symmetric in their first two quark fields (from the antisymmetry of
   C gamma5 and of eps), colour singlets (unchanged by an SU(3) rotation at every site) and
   transform as spinors under a Euclidean spin rotation S = exp(theta gamma_mu gamma_nu / 2).
@@ -10,7 +14,7 @@
   contractions at each site pair:
     W1 = eps^{abc} eps^{a'b'c'} (C g5)_{gd} (C g5)_{g'd'} M_{lm} S^{a'b}_{g'd} S^{b'a}_{d'g} S^{c'c}_{ml}
     W2 = eps^{abc} eps^{a'b'c'} (C g5)_{gd} (C g5)_{g'd'} M_{lm} S^{a'b}_{g'd} S^{b'c}_{d'l} S^{c'a}_{mg}
-  (M = gamma5 P_-).  Evaluated with S_f from the oracle's projected factorised propagator (its
+  (M = P_+).  Evaluated with S_f from the oracle's projected factorised propagator (its
   own pins tie it to dense block products) from point sources at every site of the source
   slice, they must equal the O(N_m^3) block path built from xi and eta.
 """
@@ -35,6 +39,7 @@ def test_charge_conjugation_and_projector():
     assert np.abs(cg5.T + cg5).max() < 1e-14
     P = O.nucleon_parity_projector()
     assert np.abs(P @ P - P).max() < 1e-14 and abs(np.trace(P) - 2) < 1e-14
+    assert np.abs(g[0] @ P - P).max() < 1e-14  # the range of (1 + gamma_0)/2
 
 
 def test_block_symmetry_colour_singlet_spin_covariance():
@@ -76,7 +81,7 @@ def test_blocks_equal_the_three_propagator_contraction(nvec):
     assert W1.shape == (4, 1)
     # the same from the projected factorised propagator, sources at every site of slice x0
     cg5 = O.charge_conjugation() @ O.gamma_matrices()[4]
-    M = O.gamma_matrices()[4] @ O.nucleon_parity_projector()
+    M = O.nucleon_parity_projector()
     P1 = np.zeros(4, dtype=complex)
     P2 = np.zeros(4, dtype=complex)
     for sp in range(L3):
@@ -94,3 +99,37 @@ def test_blocks_equal_the_three_propagator_contraction(nvec):
     assert np.abs(W1[:, 0] - P1).max() < 1e-9 * scale
     assert np.abs(W2[:, 0] - P2).max() < 1e-9 * np.abs(P2).max()
     assert np.abs(Cf[:, 0] - (P1 - P2) / L3).max() < 1e-9 * scale / L3
+
+
+def _free_chain_blocks(kappa):
+    """Blocks of the xi and eta lines in the free field (U = 1) on a 16 x 2^3 lattice with
+    Dirichlet time walls: Gbar = [0, 8), Gstar = [7, 16), lines cut on t_phi = 6, source
+    slice x0 = 2, 12 vectors from 2 inverse iterations on [4, 8)."""
+    T, L, bc = 16, 2, 0
+    U = np.zeros((T * L ** 3, 4, 3, 3), dtype=complex)
+    U[:] = np.eye(3)
+    v0 = gaussian_field(4 * L ** 3, 12, 64)
+    phi, _ = O.projection_basis(U, kappa, T, L, bc, (4, 4), 6, +1, v0, 2, tol=1e-14)
+    xi, eta = O.nucleon_lines(U, kappa, T, L, bc, (0, 8), (7, 9), 6, phi, 2, tol=1e-14)
+    return L, O.baryon_blocks(L, xi), O.baryon_blocks(L, eta)
+
+
+def _contract(L, Bx, By, M):
+    W1 = -np.einsum("xjika,ab,yijkb->yx", Bx, M, By, optimize=True)
+    W2 = -np.einsum("xkija,ab,yijkb->yx", Bx, M, By, optimize=True)
+    return ((W1 - W2) / L ** 3)[:, 0]
+
+
+@pytest.mark.parametrize("kappa", [0.02, 0.05])
+def test_free_field_nucleon_propagates_forward_with_the_chosen_projector(kappa):
+    L, Bx, By = _free_chain_blocks(kappa)
+    _, _, Cf = O.nucleon_factorized(L, Bx, By)
+    g = O.gamma_matrices()
+    scale = np.abs(Cf).max()
+    assert scale > 0 and np.all(np.abs(Cf) > 0)
+    # three quark lines, one power of 2 kappa per hop each: (2 kappa)^3 per slice at small kappa
+    ratio = np.abs(Cf[1:] / Cf[:-1])
+    assert np.all(ratio > 0.5 * (2 * kappa) ** 3) and np.all(ratio < 4 * (2 * kappa) ** 3), ratio
+    # the other parity projector, and the text's gamma5 P_-+, vanish at leading order
+    for M in (0.5 * (np.eye(4) - g[0]), g[4] @ (0.5 * (np.eye(4) - g[0])), g[4] @ (0.5 * (np.eye(4) + g[0]))):
+        assert np.abs(_contract(L, Bx, By, M)).max() < 1e-12 * scale
