@@ -108,6 +108,8 @@ typedef struct {
     double delta;      /* reliable-update threshold in (0, 1); 0: 0.1 (DD_FP64), 0.01 (DD_MIXED) */
     int check_every;   /* iterations between host-side convergence reads (0: 8) */
     int precond;       /* dd_precond (single-lattice solves; batched solves use the full operator) */
+    int x0;            /* dd_block_solve only: 0 start from x = 0 (x is output only), 1 x holds an
+                          initial guess on entry; every other entry point requires 0 */
 } dd_solver_params;
 
 typedef struct {
@@ -148,7 +150,9 @@ dd_status dd_frontier_hop(dd_ctx* ctx, const void* U, const dd_domain* dst, cons
 /*
  * x = D_Lambda^-1 b (dom = slab) or D^-1 b (dom NULL), nrhs <= DD_MAX_RHS
  * columns solved together (the "solutions of the Dirac equation" of Sec. 5).
- * U, b, x complex128.  x is output only (the solve starts from zero).
+ * U, b, x complex128, b and x distinct.  With params->x0 = 0 x is output only
+ * (the solve starts from zero); with x0 = 1 x holds an initial guess on entry
+ * (a column whose source is zero gets the zero solution whatever its guess).
  * Returns DD_ERR_NOCONV with x = last iterate if a column misses tol.
  * stats may be NULL.  Synchronises.
  */
@@ -282,9 +286,12 @@ dd_status dd_baryon_blocks(dd_ctx* ctx, int nvec, int nt, const void* s, void* B
  * The factorised nucleon Wick contractions summed over xvec and yvec
  * (Eqs. 22-24), from blocks Bx of the xi lines on ntx source slices and By of
  * the eta lines on nty sink slices (layout of dd_baryon_blocks):
- *   W1[y][x] = -sum_{ijk} Bx[x](j, i, k)^T gamma5 P_- By[y](i, j, k),
- *   W2[y][x] = -sum_{ijk} Bx[x](k, i, j)^T gamma5 P_- By[y](i, j, k),
- * P_- = (1 - gamma_0)/2; C_N^(f)(y0, x0) = (W1 - W2) / L^3.  W_host: host,
+ *   W1[y][x] = -sum_{ijk} Bx[x](j, i, k)^T P_+ By[y](i, j, k),
+ *   W2[y][x] = -sum_{ijk} Bx[x](k, i, j)^T P_+ By[y](i, j, k),
+ * P_+ = (1 + gamma_0)/2: the text's gamma5 P_- read for this basis and operator
+ * (a quark propagating forward in time carries (1 + gamma_0)/2 here, and with
+ * gamma5 the forward signal vanishes at leading order in kappa);
+ * C_N^(f)(y0, x0) = (W1 - W2) / L^3.  W_host: host,
  * 2 x nty x ntx complex (W1 then W2, 4 nty ntx doubles).  Sums in a fixed order.
  * Synchronises.
  */
@@ -321,6 +328,19 @@ dd_status dd_block_solve_backward(dd_ctx* ctx, const void* U, double kappa, cons
 dd_status dd_domain_action(dd_ctx* ctx, const void* U, double kappa, const dd_domain* dom, int nrhs,
                            const void* phi, void* X, void* Y, double* S_host,
                            const dd_solver_params* params, dd_solve_stats* stats);
+
+/*
+ * Backward of S = phi^+ (D_Lambda^+ D_Lambda)^-1 phi (dd_domain_action) for a
+ * loss with dL/dS = g_S, from the X, Y of the forward call; no further solve:
+ *   grad_U += g_S * (the link force of dd_link_force with coeff 1),
+ *   grad_phi = 2 g_S X  (PyTorch convention dL/dRe phi + i dL/dIm phi; S is
+ *   real and dS/d conj(phi) = (D^+ D)^-1 phi = X).
+ * X, Y, grad_phi complex128 [nrhs][12][nsite] (grad_phi overwritten), grad_U
+ * like U (accumulated).  The fermion force that local updates of a region need
+ * (Sec. 5 gives D^+ through gamma_5-hermiticity).  Asynchronous.
+ */
+dd_status dd_domain_action_backward(dd_ctx* ctx, const dd_domain* dom, int nrhs, const void* X, const void* Y,
+                                    double g_S, void* grad_U, void* grad_phi);
 
 /*
  * grad_U += coeff * g with g the link gradient of F(U) = -2 Re<Y, D_Lambda(U) X>

@@ -138,8 +138,11 @@ bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align) {
     return true;
 }
 
-dd_status check_params(dd_ctx* c, const dd_solver_params* p) {
+dd_status check_params(dd_ctx* c, const dd_solver_params* p, bool allow_guess) {
     if (p == nullptr) return fail(c, DD_ERR_ARG, "solver params are NULL");
+    if (p->x0 != 0 && !(p->x0 == 1 && allow_guess))
+        return fail(c, DD_ERR_ARG, allow_guess ? "solver x0 must be 0 or 1"
+                                               : "solver x0 must be 0 (only dd_block_solve takes an initial guess)");
     if (!(p->tol > 0) || p->tol >= 1 || p->max_iter < 1)
         return fail(c, DD_ERR_ARG, "need 0 < tol < 1 and max_iter >= 1");
     if (p->prec != DD_FP64 && p->prec != DD_MIXED) return fail(c, DD_ERR_ARG, "solver prec must be DD_FP64 or DD_MIXED");
@@ -275,7 +278,8 @@ dd_status dd_block_solve(dd_ctx* c, const void* U, double kappa, const dd_domain
                          void* x, const dd_solver_params* p, dd_solve_stats* stats) {
     if (c == nullptr) return DD_ERR_ARG;
     dd_status e;
-    if ((e = check_dom(c, dom)) != DD_OK || (e = check_params(c, p)) != DD_OK || (e = check_kappa(c, kappa)) != DD_OK)
+    if ((e = check_dom(c, dom)) != DD_OK || (e = check_params(c, p, true)) != DD_OK ||
+        (e = check_kappa(c, kappa)) != DD_OK)
         return e;
     if (nrhs < 1 || nrhs > DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs must be in [1, 12]");
     const Geo g = make_geo(c->lat, dom);
@@ -283,6 +287,7 @@ dd_status dd_block_solve(dd_ctx* c, const void* U, double kappa, const dd_domain
     CHECK_PTR(c, U, 36 * vlink(c->lat) * 16, 16, "U");
     CHECK_PTR(c, b, fbytes, 16, "b");
     CHECK_PTR(c, x, fbytes, 16, "x");
+    if (b == x) return fail(c, DD_ERR_ARG, "b and x must be different fields");
     return solve(c, (const cpx<double>*)U, kappa, g, nrhs, (const cpx<double>*)b, (cpx<double>*)x, *p, stats, 0);
 }
 
@@ -676,6 +681,25 @@ dd_status dd_domain_action(dd_ctx* c, const void* U, double kappa, const dd_doma
         *S_host = s;
     }
     DD_HIP(c, hipStreamSynchronize(c->stream));
+    return DD_OK;
+}
+
+dd_status dd_domain_action_backward(dd_ctx* c, const dd_domain* dom, int nrhs, const void* X, const void* Y,
+                                    double g_S, void* grad_U, void* grad_phi) {
+    if (c == nullptr) return DD_ERR_ARG;
+    dd_status e;
+    if ((e = check_dom(c, dom)) != DD_OK) return e;
+    if (nrhs < 1 || nrhs > DD_MAX_RHS) return fail(c, DD_ERR_ARG, "nrhs must be in [1, 12]");
+    if (!std::isfinite(g_S)) return fail(c, DD_ERR_ARG, "g_S must be finite");
+    const Geo g = make_geo(c->lat, dom);
+    const size_t n = (size_t)nrhs * 12 * g.nsite;
+    CHECK_PTR(c, X, n * 16, 16, "X");
+    CHECK_PTR(c, Y, n * 16, 16, "Y");
+    CHECK_PTR(c, grad_U, 36 * vlink(c->lat) * 16, 16, "grad_U");
+    CHECK_PTR(c, grad_phi, n * 16, 16, "grad_phi");
+    launch_link_force(c, g, nrhs, (const cpx<double>*)X, (const cpx<double>*)Y, g_S, (cpx<double>*)grad_U);
+    launch_scale(c, n, 2.0 * g_S, (const cpx<double>*)X, (cpx<double>*)grad_phi);
+    DD_HIP(c, hipGetLastError());
     return DD_OK;
 }
 

@@ -38,6 +38,13 @@ __global__ __launch_bounds__(kBlock) void k_gamma5(int nsite, const cpx<R>* __re
     b[k] = (i >= 6 * nsite) ? cpx<R>{-v.re, -v.im} : v;
 }
 
+// b = s a (complex128, real s)
+__global__ __launch_bounds__(kBlock) void k_scale(size_t n, double s, const cpx<double>* __restrict__ a,
+                                                  cpx<double>* __restrict__ b) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) b[i] = s * a[i];
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_zero(size_t n, cpx<R>* __restrict__ a) {
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -252,6 +259,11 @@ template <typename R>
 void launch_zero(dd_ctx* c, size_t n, cpx<R>* a) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_zero<R>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n, a);
+}
+
+void launch_scale(dd_ctx* c, size_t n, double s, const cpx<double>* a, cpx<double>* b) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n, s, a, b);
 }
 
 void launch_frontier(dd_ctx* c, const dd_lattice& lat, const cpx<double>* U, const dd_domain& dst,

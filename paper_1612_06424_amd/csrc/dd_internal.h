@@ -193,7 +193,8 @@ void* workspace(dd_ctx* c, Slot s, size_t bytes, dd_status* st);
 Geo make_geo(const dd_lattice& lat, const dd_domain* dom);
 // p is device memory of the context's device, aligned, with bytes available
 bool on_device(dd_ctx* c, const void* p, size_t bytes, size_t align);
-dd_status check_params(dd_ctx* c, const dd_solver_params* p);
+// allow_guess: the entry point honours dd_solver_params::x0 (dd_block_solve only)
+dd_status check_params(dd_ctx* c, const dd_solver_params* p, bool allow_guess = false);
 
 // ---------------------------------------------------------------- stencil launchers
 // Epilogues fused into the stencil (one pass over the output):
@@ -266,6 +267,8 @@ void launch_restart_dirs(dd_ctx* c, const Segs& S, const cpx<R>* r, cpx<R>* rh, 
                          const int* mask);
 template <typename R>
 void launch_cg_shift(dd_ctx* c, const Segs& S, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask);
+// a = 0 on the segments with mask[seg] != 0
+void launch_zero_segs(dd_ctx* c, const Segs& S, cpx<double>* a, const int* mask);
 
 // finalize kinds (one workgroup per segment reduces its partial slots, then
 // updates that segment's scalars)
@@ -369,6 +372,8 @@ template <typename R>
 void launch_gamma5(dd_ctx* c, int n, int ncol, const cpx<R>* in, cpx<R>* out);
 template <typename R>
 void launch_zero(dd_ctx* c, size_t n, cpx<R>* a);
+// b = s a over n complex128 elements (b may be a)
+void launch_scale(dd_ctx* c, size_t n, double s, const cpx<double>* a, cpx<double>* b);
 
 // frontier: out(dst) += alpha * P_dst D P_src in(src), time hops across the frontier
 void launch_frontier(dd_ctx* c, const dd_lattice& lat, const cpx<double>* U, const dd_domain& dst,

@@ -504,6 +504,8 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
     // b_e' = b_e + (1/(2m)) H_eo b_o
     launch_eo_hop64(c, g, Ueo64, 1.0, 0.5 / m, 0, dag, b_o, b_e, bhat, ncol);
 
+    // an initial guess (dd_block_solve with x0 = 1): its even sites start the Schur solve
+    if (p.x0) hipLaunchKernelGGL(k_eo_split, dim3(gsplit), dim3(kBlock), 0, c->stream, g, ncol, x, x_e, x_o);
     SolveResult res;
     dd_status st = solve_system(S, bhat, x_e, p, &res);
     if (st != DD_OK && st != DD_ERR_NOCONV && st != DD_ERR_BREAKDOWN) return st;

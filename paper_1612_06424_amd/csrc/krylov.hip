@@ -202,6 +202,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_shift(Segs S, cpx<R>* __restrict_
              (p[q.at(j)] = pv[j] + tv[j] - zv[j], z[q.at(j)] = tv[j]))
 }
 
+// a = 0 on the masked segments (a solve started from a guess whose source column is zero)
+__global__ __launch_bounds__(kBlock) void k_zero_segs(Segs S, cpx<double>* __restrict__ a, const int* __restrict__ mask) {
+    const SegPos q = seg_pos(S);
+    if (!mask[q.seg]) return;
+    SEG_LOOP((void)0, (a[q.at(j)] = cd(0.0, 0.0)))
+}
+
 // One workgroup per segment: fixed-order sum of the segment's partial slots
 // [p0[seg], p0[seg+1]), then the scalar recurrences of BiCGStab / CG for it.
 __global__ __launch_bounds__(kBlock) void k_finalize(int fin, const int* __restrict__ p0,
@@ -379,6 +386,10 @@ template <typename R>
 void launch_cg_shift(dd_ctx* c, const Segs& S, cpx<R>* p, cpx<R>* z, const cpx<R>* t, const int* mask) {
     hipLaunchKernelGGL(k_cg_shift<R>, sgrid(S), dim3(kBlock), 0, c->stream, S, p, z, t, mask);
 }
+void launch_zero_segs(dd_ctx* c, const Segs& S, cpx<double>* a, const int* mask) {
+    hipLaunchKernelGGL(k_zero_segs, dim3((unsigned)S.neb), dim3(kBlock), 0, c->stream, S, a, mask);
+}
+
 void launch_finalize(dd_ctx* c, int fin, int nseg, const int* p0, const double* partial, ColState* st,
                      double* out) {
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)nseg), dim3(kBlock), 0, c->stream, fin, p0, partial, st, out);

@@ -9,7 +9,11 @@
 // so the Wick contractions factorise into colourless spinors (Eq. 25)
 //   B[s_i, s_j, s_k](x)_alpha = eps^{abc} (s_i^{aT} C gamma5 s_j^b)(x) s_k^c_alpha(x),
 // summed over each time slice, one set built from three xi's at the source and
-// one from three eta's at every sink slice, contracted with gamma5 P_- (Eqs. 23-24).
+// one from three eta's at every sink slice, contracted through the spin matrix
+// P_+ = (1 + gamma_0)/2 (Eqs. 23-24, whose gamma5 P_- belongs to conventions the
+// text does not print: with this operator, (1 - gamma_mu) on the forward hop,
+// and xi^T = phi^+ D^-1 without gamma5, a forward-propagating quark carries
+// (1 + gamma_0)/2 and B_x^T gamma5 P_-+ B_y vanishes at leading order).
 //
 // Blocks per slice are a dense contraction over the sites x and colours c:
 //   B[(k, alpha)][(i, j)] = sum_{x, c} E_c[(i, j)](x) s_k^c_alpha(x),
@@ -25,7 +29,7 @@
 // Basis: chiral, component = spin * 3 + colour; gamma_0 = [[0, -1], [-1, 0]]
 // (2 x 2 blocks), gamma5 = diag(1, 1, -1, -1), C = gamma_0 gamma_2 (C gamma_mu
 // C^-1 = -gamma_mu^T), so C gamma5 has (0,1) = -1, (1,0) = +1, (2,3) = -1,
-// (3,2) = +1 and gamma5 P_- = gamma5 (1 - gamma_0)/2 = 1/2 [[1, 1], [-1, -1]].
+// (3,2) = +1 and P_+ = (1 + gamma_0)/2 = 1/2 [[1, -1], [-1, 1]].
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(kNB) void k_block_perms(int n, const cpx<double>* _
 }
 
 // partial sums over a chunk of the flat index f = ((k 4 + al) n + i) n + j of
-//   sum P_x[f] (gamma5 P_- By_y)[f]  for W1 (P1) and W2 (P2)
+//   sum P_x[f] (P_+ By_y)[f]  for W1 (P1) and W2 (P2)
 __global__ __launch_bounds__(kNB) void k_nucleon_partial(int n, int nchunk, int ntx, const cpx<double>* __restrict__ By,
                                                          const cpx<double>* __restrict__ P1,
                                                          const cpx<double>* __restrict__ P2,
@@ -152,11 +156,11 @@ __global__ __launch_bounds__(kNB) void k_nucleon_partial(int n, int nchunk, int 
     double a1r = 0, a1i = 0, a2r = 0, a2i = 0;
     for (size_t f = f0 + threadIdx.x; f < f1; f += kNB) {
         const int al = (int)((f / n2) % 4);
-        // (gamma5 P_-)_{al, be} = +1/2 for be in {al, al + 2} (al < 2), -1/2 for be in {al - 2, al}
+        // (P_+)_{al, be} = +1/2 for be = al, -1/2 for be = al +- 2
         const size_t base = f - (size_t)al * n2;  // the al = 0 entry of this (k, i, j)
         const cpx<double> u = by[base + (size_t)(al & 1) * n2], v = by[base + (size_t)((al & 1) + 2) * n2];
         const double h = al < 2 ? 0.5 : -0.5;
-        const cpx<double> m = {h * (u.re + v.re), h * (u.im + v.im)};
+        const cpx<double> m = {h * (u.re - v.re), h * (u.im - v.im)};
         const cpx<double> b1 = p1[f], b2 = p2[f];
         a1r += b1.re * m.re - b1.im * m.im;
         a1i += b1.re * m.im + b1.im * m.re;

@@ -176,7 +176,7 @@ dd_status bicgstab_reliable(System& S, const cpx<double>* b, cpx<double>* x, con
     ColState* st = W.st;
     double* partial = W.partial;
     dd_status e;
-    launch_zero<double>(c, S.nelem, x);
+    if (!p.x0) launch_zero<double>(c, S.nelem, x);  // else x holds the caller's guess
     if (fold) launch_zero<R>(c, S.nelem, xk);
     e = residual_to_host(S, b, x, W.r64, partial, W.dots);
     if (e != DD_OK) return e;
@@ -336,7 +336,7 @@ dd_status cgnr_reliable(System& S, const cpx<double>* b, cpx<double>* x, const s
     ColState* st = W.st;
     double* partial = W.partial;
     dd_status e;
-    launch_zero<double>(c, S.nelem, x);
+    if (!p.x0) launch_zero<double>(c, S.nelem, x);  // else x holds the caller's guess
     if (fold) launch_zero<R>(c, S.nelem, xk);
     e = residual_to_host(S, b, x, W.r64, partial, W.dots);
     if (e != DD_OK) return e;
@@ -541,6 +541,17 @@ dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd
     for (int j = 0; j < ns; j++) bb[j] = c->host_dots[3 * j];
     for (int j = 0; j < ns; j++)
         if (!std::isfinite(bb[j])) return fail(c, DD_ERR_BREAKDOWN, "non-finite values in the right-hand side");
+    // a zero source column has the zero solution, whatever guess x held
+    if (p.x0) {
+        std::vector<int> zmask(ns, 0);
+        bool any = false;
+        for (int j = 0; j < ns; j++) any = any || (zmask[j] = bb[j] == 0);
+        if (any) {
+            e = push_mask(c, W.mask_dev, zmask);
+            if (e != DD_OK) return e;
+            launch_zero_segs(c, S.seg, x, W.mask_dev);
+        }
+    }
     // relative residuals refer to |b|^2, or to the norm the System names (the
     // original source of a preconditioned system); a zero source stays done
     if (S.ref_norm2 != nullptr)

@@ -39,7 +39,7 @@ EXPORTS = [
     "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing_count",
     "dd_kernel_timing", "dd_projection_basis", "dd_factorized_propagator_projected",
     "dd_disconnected_traces", "dd_disconnected_correlator", "dd_nucleon_lines", "dd_baryon_blocks",
-    "dd_nucleon_contract",
+    "dd_nucleon_contract", "dd_domain_action_backward",
 ]
 
 
@@ -53,7 +53,7 @@ class dd_domain(C.Structure):
 
 class dd_solver_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("prec", C.c_int), ("solver", C.c_int),
-                ("delta", C.c_double), ("check_every", C.c_int), ("precond", C.c_int)]
+                ("delta", C.c_double), ("check_every", C.c_int), ("precond", C.c_int), ("x0", C.c_int)]
 
 
 class dd_solve_stats(C.Structure):
@@ -99,6 +99,7 @@ _sig = {
     "dd_domain_action": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _vp, _vp, _vp, C.POINTER(C.c_double),
                           C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
     "dd_link_force": ([_vp, C.POINTER(dd_domain), _i, _vp, _vp, _d, _vp], _i),
+    "dd_domain_action_backward": ([_vp, C.POINTER(dd_domain), _i, _vp, _vp, _d, _vp, _vp], _i),
     "dd_block_solve_batched": ([_vp, _i, C.POINTER(dd_batch_item), C.POINTER(dd_solver_params),
                                 C.POINTER(dd_solve_stats)], _i),
     "dd_set_kernel_timing": ([_vp, _i], _i),
@@ -121,9 +122,10 @@ class DDError(RuntimeError):
 def solver_params(tol=1e-10, max_iter=20000, prec=DD_FP64, solver=DD_CGNR, delta=0.0, check_every=0,
                   precond=None):
     """Solver parameters; delta = 0 takes the library's reliable-update threshold; precond
-    defaults to even-odd (used where the lattice allows it)."""
+    defaults to even-odd (used where the lattice allows it); solves start from zero (x0 = 0,
+    see block_solve for an initial guess)."""
     return dd_solver_params(float(tol), int(max_iter), int(prec), int(solver), float(delta), int(check_every),
-                            DD_PRECOND_EO if precond is None else int(precond))
+                            DD_PRECOND_EO if precond is None else int(precond), 0)
 
 
 def _dom(dom):
@@ -193,15 +195,21 @@ def frontier_hop(ctx, U, dst, src, psi, out, alpha=1.0):
     return out
 
 
-def block_solve(ctx, U, kappa, b, dom=None, params=None, x=None, allow_noconv=False):
-    """x = D_Lambda^-1 b for the columns of b (complex128, (ncol, 12, nsite)).  Returns (x, stats)."""
+def block_solve(ctx, U, kappa, b, dom=None, params=None, x=None, allow_noconv=False, guess=False):
+    """x = D_Lambda^-1 b for the columns of b (complex128, (ncol, 12, nsite)).  With guess=True
+    the given x is the initial guess (overwritten by the solution); otherwise the solve starts
+    from zero.  Returns (x, stats)."""
     params = params or solver_params()
+    if guess and x is None:
+        raise ValueError("guess=True needs x")
     if x is None:
         x = torch.empty_like(b)
+    p = dd_solver_params(params.tol, params.max_iter, params.prec, params.solver, params.delta,
+                         params.check_every, params.precond, 1 if guess else 0)
     stats = dd_solve_stats()
     ctx._check(_lib.dd_block_solve(ctx._h, _ptr(U, torch.complex128, "U"), float(kappa), _dom(dom), b.shape[0],
                                    _ptr(b, torch.complex128, "b"), _ptr(x, torch.complex128, "x"),
-                                   C.byref(params), C.byref(stats)),
+                                   C.byref(p), C.byref(stats)),
                allow=(DD_ERR_NOCONV,) if allow_noconv else ())
     return x, stats.as_dict()
 
@@ -352,6 +360,17 @@ def domain_action(ctx, U, kappa, phi, dom=None, params=None):
     return S.value, X, Y, stats.as_dict()
 
 
+def domain_action_backward(ctx, X, Y, g_S, grad_U, dom=None, grad_phi=None):
+    """grad_U += g_S * force(X, Y) and grad_phi = 2 g_S X, both in libdd.  Returns grad_phi."""
+    if grad_phi is None:
+        grad_phi = torch.empty_like(X)
+    ctx._check(_lib.dd_domain_action_backward(ctx._h, _dom(dom), X.shape[0], _ptr(X, torch.complex128, "X"),
+                                              _ptr(Y, torch.complex128, "Y"), float(g_S),
+                                              _ptr(grad_U, torch.complex128, "grad_U"),
+                                              _ptr(grad_phi, torch.complex128, "grad_phi")))
+    return grad_phi
+
+
 def link_force(ctx, X, Y, coeff, grad_U, dom=None):
     """grad_U += coeff * d/dU [-2 Re <Y, D X>]."""
     ctx._check(_lib.dd_link_force(ctx._h, _dom(dom), X.shape[0], _ptr(X, torch.complex128, "X"),
@@ -454,7 +473,6 @@ class DomainActionFn(torch.autograd.Function):
     def backward(fctx, gS):
         X, Y, U = fctx.saved_tensors
         ctx, dom = fctx.dd
-        g = float(gS.item())
         grad_U = torch.zeros_like(U)
-        link_force(ctx, X, Y, g, grad_U, dom)
-        return grad_U, 2.0 * g * X, None, None, None, None
+        grad_phi = domain_action_backward(ctx, X, Y, float(gS.item()), grad_U, dom)
+        return grad_U, grad_phi, None, None, None, None

@@ -1,0 +1,147 @@
+"""Write the oracle-fixed parity values of the 32x16^3 and 64x32^3 workloads.
+
+    python tests/golden/make_golden.py [32x16^3] [64x32^3]
+
+Calls only the CPU oracle (oracle/) and the seeded input generators
+(paper_1612_06424_amd/inputs.py); nothing here touches the HIP library.  For
+each workload it solves the point-source columns with the oracle's FP64
+BiCGStab (CGNR where BiCGStab stalls) to a true relative residual of 1e-13 and
+stores, per source column j (the slabs taken from the one that holds the source),
+  C_j(t) = sum_xvec sum_c |S_cj((t_src + t) mod T, xvec)|^2   (Eq. 4, W_Pc, one column)
+for the exact propagator D^-1 eta (whole lattice) and for the factorised one of
+the workload's time slabs (Sec. 3.1 Eq. 13 on the source slab, Sec. 3.2 Eq. 14
+chained outward, overlap Delta = 0), plus sampled entries S_cj(x) of both.
+
+32x16^3: all 12 columns of the 4 point sources (8k, 4k, 4k, 4k), k = 0..3, so
+the stored sums give the 12-column C(t) of each source; slabs [0,16) [16,32).
+64x32^3: columns j = 0 and 7 of the point source at the origin (solving all
+12 would take the host many hours); slabs [0,16) [16,32) [32,48) [48,64).
+Sampled sites: numpy default_rng(seed) over the lattice, seed 3002 (32x16^3) and
+3003 (64x32^3).
+
+force-32x16^3 (the differentiation workload: one Dirichlet-walled 32x16^3
+lattice, one Gaussian pseudofermion field, seed 502): the action
+S = phi^+ (D^+ D)^-1 phi and the su(3) force F^a_mu(x) = dS/d omega^a for
+U_mu(x) -> exp(i omega^a T^a) U_mu(x), T^a = lambda^a / 2, from the oracle's
+analytic link gradient, at 64 links drawn by numpy default_rng(503) plus the
+time link of one site on the last slice (zero force: its hop is dropped).
+
+Output: tests/golden/<file>.json.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "oracle"))
+
+import oracle as O  # noqa: E402
+from paper_1612_06424_amd.inputs import WORKLOADS, point_sources, random_links  # noqa: E402
+
+TOL = 1e-13
+PLAN = {
+    "32x16^3": dict(file="golden_32x16.json", columns=list(range(12)), sources=[0, 1, 2, 3], nsample=16,
+                    sample_seed=3002),
+    "64x32^3": dict(file="golden_64x32.json", columns=[0, 7], sources=[0], nsample=24, sample_seed=3003),
+}
+
+
+def log(msg):
+    print(f"[golden {time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def solve_checked(U, kappa, T, L, bc, b, dom):
+    x, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=TOL, method=0)
+    if st != 0 or max(rr) > TOL:
+        log(f"  BiCGStab status {st} relres {max(rr):.2e}; CGNR instead")
+        x, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=TOL, method=1)
+    if st != 0 or max(rr) > TOL:
+        raise RuntimeError(f"oracle solve failed: status {st}, relres {max(rr):.3e}")
+    return x, it, rr
+
+
+def column_correlator(T, L, S1, t_src):
+    """C(t) of one column from the oracle's pion sum (S1: (1, V, 12))."""
+    return O.pion_correlator(T, L, S1, t_src)
+
+
+def run(name):
+    plan = PLAN[name]
+    w = WORKLOADS[name]
+    T, L, bc, kappa = w["T"], w["L"], w["bc"], w["kappa"]
+    V = T * L ** 3
+    U = random_links(T, L, w["eps"], w["link_seed"])
+    rng = np.random.default_rng(plan["sample_seed"])
+    sites = sorted(int(s) for s in rng.choice(V, size=plan["nsample"], replace=False))
+    out = dict(workload=name, T=T, L=L, bc=bc, kappa=kappa, eps=w["eps"], link_seed=w["link_seed"],
+               domains=w["domains"], overlap=0, oracle_tol=TOL, solver="oracle BiCGStab (CGNR fallback)",
+               sample_sites=sites, sources=[])
+    for si in plan["sources"]:
+        src = w["sources"][si]
+        eta_all = point_sources(T, L, *src)
+        # the chain starts from the slab holding the source (listed first)
+        doms = sorted(w["domains"], key=lambda d: (src[0] - d[0]) % T >= d[1])
+        rec = dict(source=list(src), domains=doms, columns=plan["columns"], C_exact=[], C_fact=[], S_exact_samples=[],
+                   S_fact_samples=[], iters_exact=[], iters_fact=[], relres=[])
+        for j in plan["columns"]:
+            t0 = time.time()
+            eta = np.ascontiguousarray(eta_all[j:j + 1])
+            Se, it_e, rr_e = solve_checked(U, kappa, T, L, bc, eta, None)
+            Sf, info = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=TOL, eta=eta)
+            for k, inf in info.items():
+                if inf["status"] != 0 or max(inf["relres"]) > TOL:
+                    # the chain's slab solves use BiCGStab; a stalled one is redone by CGNR
+                    raise RuntimeError(f"factorised chain slab {k} failed: {inf}")
+            rec["C_exact"].append(column_correlator(T, L, Se, src[0]).tolist())
+            rec["C_fact"].append(column_correlator(T, L, Sf, src[0]).tolist())
+            rec["S_exact_samples"].append([[[v.real, v.imag] for v in Se[0, s]] for s in sites])
+            rec["S_fact_samples"].append([[[v.real, v.imag] for v in Sf[0, s]] for s in sites])
+            rec["iters_exact"].append(it_e[0])
+            rec["iters_fact"].append({str(k): inf["iters"][0] for k, inf in info.items()})
+            rec["relres"].append(max([rr_e[0]] + [inf["relres"][0] for inf in info.values()]))
+            log(f"{name} source {si} column {j}: exact {it_e[0]} iters, chain "
+                f"{[inf['iters'][0] for inf in info.values()]} iters, {time.time() - t0:.0f} s")
+        out["sources"].append(rec)
+    out["threads"] = O.threads()
+    path = os.path.join(HERE, plan["file"])
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f)
+    os.replace(path + ".tmp", path)
+    log(f"wrote {path}")
+
+
+def run_force():
+    from paper_1612_06424_amd.inputs import gaussian_field
+    w = WORKLOADS["force-32x16^3"]
+    T, L, bc, kappa = w["T"], w["L"], w["bc"], w["kappa"]
+    L3 = L ** 3
+    V = T * L3
+    U = random_links(T, L, w["eps"], w["link_seed"])
+    phi = gaussian_field(V, 1, w["phi_seed"])
+    t0 = time.time()
+    S, X, Y = O.domain_action(U, kappa, T, L, bc, None, phi, tol=TOL)
+    F = O.su3_force(U, O.link_grad(T, L, bc, None, X, Y))
+    rng = np.random.default_rng(w["fd_seed"])
+    links = [(int(rng.integers(0, V)), int(rng.integers(0, 4))) for _ in range(64)]
+    links.append(((T - 1) * L3 + 5, 0))
+    out = dict(workload="force-32x16^3", T=T, L=L, bc=bc, kappa=kappa, eps=w["eps"], link_seed=w["link_seed"],
+               phi_seed=w["phi_seed"], oracle_tol=TOL, S=S, links=links,
+               F=[[float(F[s, mu, a]) for a in range(8)] for s, mu in links], threads=O.threads())
+    path = os.path.join(HERE, "golden_force_32x16.json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f)
+    os.replace(path + ".tmp", path)
+    log(f"wrote {path} ({time.time() - t0:.0f} s)")
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(PLAN) + ["force-32x16^3"]):
+        if name == "force-32x16^3":
+            run_force()
+        else:
+            run(name)
