@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "dd_eo.h"
+#include "dd_eo_lds.h"
 
 namespace dd {
 
@@ -83,6 +84,18 @@ __global__ __launch_bounds__(NT, eo_waves<R>()) void k_eo_hop_nt(Geo g, const cp
                                                                 const ColState* __restrict__ st) {
     eo_hop_body<R, DAG, EPI, NT, SELF, KC, REC, true>(g, U, a_self, c_hop, p_out, in, self, out, aux, ncol, tc_len,
                                                       remap, blocked, partial, st);
+}
+
+// The LDS-tile form of the half hop (dd_eo_lds.h): one slice of a brick of rows per
+// workgroup, cpw columns per workgroup, links of two rows each (SU(3)).
+template <typename R, int DAG, int EPI, bool SELF, int LH, bool NTS>
+__global__ __launch_bounds__(kLdsNT, 1) void k_eo_lds(Geo g, const cpx<R>* __restrict__ U12, R a_self, R c_hop,
+                                                     int p_out, const cpx<R>* __restrict__ in,
+                                                     const cpx<R>* __restrict__ self, cpx<R>* __restrict__ out,
+                                                     const cpx<R>* __restrict__ aux, int ncol, int cpw, int remap,
+                                                     double* __restrict__ partial, const ColState* __restrict__ st) {
+    eo_lds_body<R, DAG, EPI, SELF, LH, NTS>(g, U12, a_self, c_hop, p_out, in, self, out, aux, ncol, cpw, remap,
+                                            partial, st);
 }
 
 // full field [ncol][12][nsite] <-> even / odd half fields [ncol][12][nsite / 2]
@@ -228,6 +241,38 @@ void launch_eo_kc(hipStream_t s, int kc, bool rec, bool nts, int epi, dim3 grid,
 #undef DD_EO_KC
 }
 
+// The LDS-tile form applies to FP32 fields with L = 32 or 16 whose links are SU(3)
+// (two rows each).
+template <typename R>
+bool eo_lds_ok(const Geo& g, const void* U12) {
+    return sizeof(R) == 4 && U12 != nullptr && (g.L == 32 || g.L == 16);
+}
+
+template <typename R, int D, bool SF, int LH>
+void launch_eo_lds_lh(hipStream_t s, int epi, bool nts, dim3 grid, const Geo& g, const cpx<R>* U12, R a_self,
+                      R c_hop, int p_out, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux,
+                      int ncol, int cpw, int remap, double* partial, const ColState* st) {
+    const dim3 block(kLdsNT);
+#define DD_LDS_CASE(E)                                                                                              \
+    if (nts)                                                                                                        \
+        hipLaunchKernelGGL((k_eo_lds<R, D, E, SF, LH, true>), grid, block, 0, s, g, U12, a_self, c_hop, p_out, in, \
+                           self, out, aux, ncol, cpw, remap, partial, st);                                          \
+    else                                                                                                            \
+        hipLaunchKernelGGL((k_eo_lds<R, D, E, SF, LH, false>), grid, block, 0, s, g, U12, a_self, c_hop, p_out, in, \
+                           self, out, aux, ncol, cpw, remap, partial, st)
+    if constexpr (!SF) {
+        DD_LDS_CASE(EPI_STORE);  // the first half of the Schur operator
+    } else {
+        switch (epi) {
+            case EPI_STORE: DD_LDS_CASE(EPI_STORE); break;
+            case EPI_DOT_AUX: DD_LDS_CASE(EPI_DOT_AUX); break;
+            case EPI_TS: DD_LDS_CASE(EPI_TS); break;
+            default: DD_LDS_CASE(EPI_NORM); break;
+        }
+    }
+#undef DD_LDS_CASE
+}
+
 // out = a_self * self + c_hop * H_{p_out, 1 - p_out} in, for ncol half-field columns,
 // time chunks of tc slices, kc columns per thread (eo_kc_ok), workgroups
 // optionally in XCD-contiguous ranges; tile flags `blocked`: bit 0 tiles as
@@ -235,10 +280,53 @@ void launch_eo_kc(hipStream_t s, int kc, bool rec, bool nts, int epi, dim3 grid,
 // bit 2 non-temporal output stores (k_eo_hop_nt; FP32 with kc > 1 only).
 // U: the checkerboard links; U12 (nullable): the same links as two rows each,
 // which launches with kc > 1 read instead.
+//
+// Tile flag bit 3 selects the LDS-tile form (eo_lds_ok; one slice per workgroup, so
+// its partial slots are those of tc = 1) with kc columns per workgroup and bit 2
+// for non-temporal stores; where it does not apply the time sweep runs instead.
 template <typename R>
 void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, double a_self, double c_hop,
                    int p_out, int dag, int epi, const cpx<R>* in, const cpx<R>* self, cpx<R>* out, const cpx<R>* aux,
                    int ncol, int tc, int kc, int remap, int blocked, double* partial, const ColState* st) {
+    const bool sf = self != nullptr && a_self != 0;
+    if constexpr (sizeof(R) == 4)
+    if ((blocked & 8) && eo_lds_ok<R>(g, U12) && !(epi == EPI_RESID) && (sf || epi == EPI_STORE)) {
+        const int cpw = std::max(1, std::min(kc, ncol));
+        const bool nts = (blocked & 4) != 0;
+        const int ntile = ((g.L3 >> 1) + kLdsNT - 1) / kLdsNT;
+        const dim3 grid((unsigned)(ntile * g.nt * ((ncol + cpw - 1) / cpw)));
+        hipEvent_t ev = nullptr;
+        if (c->timing) timing_begin(c, &ev);
+#define DD_LDS_LAUNCH(D, SF, LH)                                                                                    \
+    launch_eo_lds_lh<R, D, SF, LH>(c->stream, epi, nts, grid, g, U12, R(a_self), R(c_hop), p_out, in, self, out, aux, \
+                                   ncol, cpw, remap, partial, st)
+#define DD_LDS_LH(D, SF)                 \
+    if (g.L == 32) DD_LDS_LAUNCH(D, SF, 16); \
+    else DD_LDS_LAUNCH(D, SF, 8)
+        if (dag) {
+            if (sf) DD_LDS_LH(1, true);
+            else DD_LDS_LH(1, false);
+        } else {
+            if (sf) DD_LDS_LH(0, true);
+            else DD_LDS_LH(0, false);
+        }
+#undef DD_LDS_LH
+#undef DD_LDS_LAUNCH
+        if (c->timing) {
+            const double nh = (double)(g.nsite >> 1);
+            const double extra = (sf || epi == EPI_TS ? 24.0 : 0.0) + (epi == EPI_DOT_AUX ? 24.0 : 0.0);
+            const double bytes = nh * ((48.0 + extra) * ncol + 96.0) * sizeof(R);
+            const std::string name = std::string("k_eo_lds<float, ") + std::to_string(dag ? 1 : 0) + ", " +
+                                     std::to_string(epi) + (sf ? ", true, " : ", false, ") +
+                                     std::to_string(g.L / 2) + (nts ? ", true>" : ", false>");
+            timing_end(c, ev, name, bytes);
+        }
+        return;
+    }
+    if (blocked & 8) {  // the LDS form does not apply here: the time sweep of one slice per chunk
+        blocked = 0;
+        kc = 1;
+    }
     if (!eo_kc_ok<R>(kc, ncol)) kc = 1;
     if (g.L % 4 != 0) blocked &= ~1;
     const bool nts = (blocked & 4) && kc > 1;
@@ -251,7 +339,6 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, 
 #define DD_EO_LAUNCH(D, SF)                                                                                           \
     launch_eo_kc<R, D, SF>(c->stream, kc, rec, nts, epi, grid, g, U, R(a_self), R(c_hop), p_out, in, self, out, \
                            aux, ncol, tc, remap, blocked, partial, st)
-    const bool sf = self != nullptr && a_self != 0;
     if (dag) {
         if (sf) DD_EO_LAUNCH(1, true);
         else DD_EO_LAUNCH(1, false);
@@ -347,6 +434,31 @@ StencilSched eo_tune(dd_ctx* c, EOSystem& S, const cpx<R>* UR, const cpx<R>* UR1
                             sc.remap = rm;
                             sc.kc = kc;
                             sc.blocked = bl;
+                            for (int w = 0; w < 2; w++)
+                                S.schur<R>(UR, UR12, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                            (void)hipEventRecord(a, c->stream);
+                            for (int r = 0; r < 3; r++)
+                                S.schur<R>(UR, UR12, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
+                            (void)hipEventRecord(b, c->stream);
+                            (void)hipEventSynchronize(b);
+                            float ms = 0;
+                            (void)hipEventElapsedTime(&ms, a, b);
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                best = sc;
+                            }
+                        }
+            // the LDS-tile form: columns per workgroup, XCD remap, store form
+            if (eo_lds_ok<R>(g, UR12))
+                for (int cpw : {12, 6, 4, 3, 2, 1})
+                    for (int rm = 0; rm < 2; rm++)
+                        for (int nts = 0; nts < 2; nts++) {
+                            if (cpw > S.ncol) continue;
+                            StencilSched sc = best;
+                            sc.tc = 1;
+                            sc.remap = rm;
+                            sc.kc = cpw;
+                            sc.blocked = 8 | (nts ? 4 : 0);
                             for (int w = 0; w < 2; w++)
                                 S.schur<R>(UR, UR12, tmp, sc, 0, EPI_STORE, in, out, nullptr, nullptr, nullptr);
                             (void)hipEventRecord(a, c->stream);
