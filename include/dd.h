@@ -307,6 +307,19 @@ dd_status dd_nucleon_contract(dd_ctx* ctx, int nvec, int ntx, const void* Bx, in
 dd_status dd_pion_correlator(dd_ctx* ctx, const void* S, int ncol, int t_src, double* C_host);
 
 /*
+ * dd_pion_correlator for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bitwise, with their partial sums in a
+ * static device array of 2^18 doubles (2 MiB, one per GPU, held until the
+ * process ends) instead of the context's workspace.  No allocation of any kind.
+ * Limit: 36 T ncol + T <= 2^18 (e.g. T = 64 with 48 columns); larger requests
+ * return DD_ERR_ARG.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (different contexts, streams or threads) race.
+ * Synchronises.
+ */
+dd_status dd_pion_correlator_noalloc(dd_ctx* ctx, const void* S, int ncol, int t_src, double* C_host);
+
+/*
  * Adjoint of x = D_Lambda^-1 b for a real loss with gradient grad_x
  * (PyTorch convention g = dL/dRe + i dL/dIm): solves D_Lambda^+ lambda = grad_x
  * (one extra solve, through gamma_5-hermiticity) and returns grad_b = lambda

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -156,6 +157,34 @@ dd_status check_params(dd_ctx* c, const dd_solver_params* p, bool allow_guess) {
 
 using namespace dd;
 
+// ---------------------------------------------------------------- allocation-free scratch
+// A file-scope device array that serves dd_pion_correlator_noalloc as its partial-sum and
+// result scratch, so that call needs no allocation (each GPU the library runs on holds
+// its own copy until the process ends).  Host code never uses the array's name as an
+// address: dd_create looks up its device address once per device (with that device
+// current) and every later use goes through that pointer.
+namespace {
+constexpr size_t kScratchDoubles = (size_t)1 << 18;  // 2 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// the device address of `scratch` on device dev (current), looked up on first use
+dd_status resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return DD_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] != nullptr) return DD_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+        (void)hipGetLastError();
+        return DD_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = (double*)ptr;
+    return DD_OK;
+}
+}  // namespace
+
 #define CHECK_PTR(c, p, bytes, align, name)                                                         \
     do {                                                                                             \
         if (!on_device(c, p, bytes, align))                                                          \
@@ -201,6 +230,10 @@ dd_status dd_create(const dd_lattice* lat, void* stream, dd_ctx** out) {
         return DD_ERR_HIP;
     }
     c->ws.resize(W_NSLOTS);
+    if (resolve_scratch(c->device) != DD_OK) {
+        delete c;
+        return DD_ERR_HIP;
+    }
     tune_cache_load(c);
     *out = c;
     return DD_OK;
@@ -616,6 +649,27 @@ dd_status dd_pion_correlator(dd_ctx* c, const void* S, int ncol, int t_src, doub
     launch_pion(c, c->lat, ncol, (const cpx<double>*)S, t_src, partial, Cd);
     DD_HIP(c, hipGetLastError());
     DD_HIP(c, hipMemcpyAsync(C_host, Cd, sizeof(double) * c->lat.T, hipMemcpyDeviceToHost, c->stream));
+    DD_HIP(c, hipStreamSynchronize(c->stream));
+    return DD_OK;
+}
+
+dd_status dd_pion_correlator_noalloc(dd_ctx* c, const void* S, int ncol, int t_src, double* C_host) {
+    if (c == nullptr) return DD_ERR_ARG;
+    if (ncol < 1 || ncol > 4 * DD_MAX_RHS) return fail(c, DD_ERR_ARG, "ncol out of range");
+    if (t_src < 0 || t_src >= c->lat.T) return fail(c, DD_ERR_ARG, "t_src outside [0, T)");
+    if (C_host == nullptr) return fail(c, DD_ERR_ARG, "C_host is NULL");
+    const size_t V = vlink(c->lat);
+    CHECK_PTR(c, S, (size_t)ncol * 12 * V * 16, 16, "S");
+    const size_t T = (size_t)c->lat.T;
+    const size_t npart = T * 12 * (size_t)ncol * 3;  // the pion kernels' partial sums, then C
+    if (npart + T > kScratchDoubles)
+        return fail(c, DD_ERR_ARG, "dd_pion_correlator_noalloc: 36 T ncol + T = " + std::to_string(npart + T) +
+                                       " doubles exceed the static scratch of " + std::to_string(kScratchDoubles));
+    double* base = c->device >= 0 && c->device < kMaxDevices ? g_scratch_ptr[c->device] : nullptr;
+    if (base == nullptr) return fail(c, DD_ERR_HIP, "static scratch not resolved for this device");
+    launch_pion(c, c->lat, ncol, (const cpx<double>*)S, t_src, base, base + npart);
+    DD_HIP(c, hipGetLastError());
+    DD_HIP(c, hipMemcpyAsync(C_host, base + npart, sizeof(double) * T, hipMemcpyDeviceToHost, c->stream));
     DD_HIP(c, hipStreamSynchronize(c->stream));
     return DD_OK;
 }

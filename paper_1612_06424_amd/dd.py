@@ -39,7 +39,7 @@ EXPORTS = [
     "dd_link_force", "dd_block_solve_batched", "dd_set_kernel_timing", "dd_kernel_timing_count",
     "dd_kernel_timing", "dd_projection_basis", "dd_factorized_propagator_projected",
     "dd_disconnected_traces", "dd_disconnected_correlator", "dd_nucleon_lines", "dd_baryon_blocks",
-    "dd_nucleon_contract", "dd_domain_action_backward",
+    "dd_nucleon_contract", "dd_domain_action_backward", "dd_pion_correlator_noalloc",
 ]
 
 
@@ -87,6 +87,7 @@ _sig = {
     "dd_projection_basis": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _i, _i, _i, _vp, _vp,
                              C.POINTER(dd_solver_params), C.POINTER(dd_solve_stats)], _i),
     "dd_pion_correlator": ([_vp, _vp, _i, _i, C.POINTER(C.c_double)], _i),
+    "dd_pion_correlator_noalloc": ([_vp, _vp, _i, _i, C.POINTER(C.c_double)], _i),
     "dd_disconnected_traces": ([_vp, _vp, _d, C.POINTER(dd_domain), _i, _i, _vp, _i, C.POINTER(dd_solver_params),
                                 _vp, C.POINTER(dd_solve_stats)], _i),
     "dd_disconnected_correlator": ([_vp, _i, _vp, C.POINTER(C.c_double)], _i),
@@ -265,6 +266,13 @@ def pion_correlator(ctx, S, t_src):
     """C(t), t = 0..T-1, as a numpy float64 array."""
     out = (C.c_double * ctx.T)()
     ctx._check(_lib.dd_pion_correlator(ctx._h, _ptr(S, torch.complex128, "S"), S.shape[0], int(t_src), out))
+    return np.array(list(out))
+
+
+def pion_correlator_noalloc(ctx, S, t_src):
+    """pion_correlator through the allocation-free entry point (static device scratch)."""
+    out = (C.c_double * ctx.T)()
+    ctx._check(_lib.dd_pion_correlator_noalloc(ctx._h, _ptr(S, torch.complex128, "S"), S.shape[0], int(t_src), out))
     return np.array(list(out))
 
 
