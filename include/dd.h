@@ -411,8 +411,11 @@ dd_status dd_block_solve_batched(dd_ctx* ctx, int n, const dd_batch_item* items,
  * instance, e.g. "k_dslash<float, 1, 4, 128>" (real type, dagger, fused
  * epilogue, work-group size).  For each instance dd_kernel_timing returns the
  * summed milliseconds, the launch count and the summed algorithmic bytes
- *     V * ((48 + e) * ncol + 72) * sizeof(real)   per launch,
- * with e = 24 for the epilogues that read one more field.  index runs over
+ *     V * ((48 + e) * ncol * f + 72) * sizeof(real)   per launch,
+ * with e = 24 for the epilogues that read one more field and f the share of
+ * the launch's columns that are live (inside solves the share the host saw
+ * active when it launched; the workgroups of a stopped column return at once;
+ * 1 elsewhere).  index runs over
  * [0, count) from dd_kernel_timing_count, in first-launch order; name
  * receives at most name_len - 1 characters and a terminating zero.  Reading
  * the counters waits for the context stream.

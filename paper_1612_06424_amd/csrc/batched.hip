@@ -279,7 +279,7 @@ struct BatchSystem : System {
                 sites += d.g.nsite;
             }
             const double extra = (epi == EPI_DOT_AUX || epi == EPI_RESID) ? 24.0 : 0.0;
-            const double bytes = ((48.0 + extra) * sites_cols + 72.0 * sites) * sizeof(R);
+            const double bytes = ((48.0 + extra) * sites_cols * c->bill_frac + 72.0 * sites) * sizeof(R);
             const std::string name = std::string("k_bdslash<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                      std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
                                      std::to_string(L.sc.nt) + ">";
@@ -342,7 +342,7 @@ struct BatchEOSystem : System {
                     s += (double)(d.g.nsite >> 1);
                 }
                 const double extra = (half ? 24.0 : 0.0) + (e == EPI_DOT_AUX || e == EPI_RESID ? 24.0 : 0.0);
-                const double bytes = ((48.0 + extra) * sc + (rec ? 96.0 : 144.0) * s) * sizeof(R);
+                const double bytes = ((48.0 + extra) * sc * c->bill_frac + (rec ? 96.0 : 144.0) * s) * sizeof(R);
                 const std::string name = std::string("k_beo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                          std::to_string(dag ? 1 : 0) + ", " + std::to_string(e) + ", " +
                                          (half ? "true, " : "false, ") + std::to_string(k) +

@@ -164,6 +164,10 @@ struct dd_ctx {
     int host_n = 0;
     // rocBLAS handle of the nucleon block products (created on first use)
     void* blas = nullptr;
+    // fraction of a launch's columns whose spinor bytes the kernel timing bills: solvers set
+    // it to the share of columns active when they launch (a stopped column's workgroups
+    // return at once); 1 outside solves
+    double bill_frac = 1.0;
 };
 
 namespace dd {

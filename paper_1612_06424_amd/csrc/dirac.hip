@@ -100,7 +100,7 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
 #undef DD_NT_CASE
     if (c->timing) {
         const double extra = (epi == EPI_DOT_AUX || epi == EPI_RESID) ? 24.0 : 0.0;
-        const double bytes = (double)g.nsite * ((48.0 + extra) * ncol + 72.0) * sizeof(R);
+        const double bytes = (double)g.nsite * ((48.0 + extra) * ncol * c->bill_frac + 72.0) * sizeof(R);
         const std::string name = std::string("k_dslash<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
                                  std::to_string(sc.nt) + ">";

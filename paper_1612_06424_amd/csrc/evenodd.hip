@@ -315,7 +315,7 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, 
         if (c->timing) {
             const double nh = (double)(g.nsite >> 1);
             const double extra = (sf || epi == EPI_TS ? 24.0 : 0.0) + (epi == EPI_DOT_AUX ? 24.0 : 0.0);
-            const double bytes = nh * ((48.0 + extra) * ncol + 96.0) * sizeof(R);
+            const double bytes = nh * ((48.0 + extra) * ncol * c->bill_frac + 96.0) * sizeof(R);
             const std::string name = std::string("k_eo_lds<float, ") + std::to_string(dag ? 1 : 0) + ", " +
                                      std::to_string(epi) + (sf ? ", true, " : ", false, ") +
                                      std::to_string(g.L / 2) + (nts ? ", true>" : ", false>");
@@ -354,7 +354,7 @@ void launch_eo_hop(dd_ctx* c, const Geo& g, const cpx<R>* U, const cpx<R>* U12, 
         const double nh = (double)(g.nsite >> 1);
         const double extra = (a_self != 0 || epi == EPI_TS ? 24.0 : 0.0) +
                              (epi == EPI_DOT_AUX || epi == EPI_RESID ? 24.0 : 0.0);
-        const double bytes = nh * ((48.0 + extra) * ncol + (rec ? 96.0 : 144.0)) * sizeof(R);
+        const double bytes = nh * ((48.0 + extra) * ncol * c->bill_frac + (rec ? 96.0 : 144.0)) * sizeof(R);
         const std::string name = std::string(nts ? "k_eo_hop_nt<" : "k_eo_hop<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
                                  std::to_string(kEoNT) + (sf ? ", true, " : ", false, ") + std::to_string(kc) +

@@ -72,6 +72,15 @@ dd_status push_state(dd_ctx* c, ColState* dev, int n) {
 
 void reset_host_state(dd_ctx* c, int n) { std::memset(c->host_state, 0, sizeof(ColState) * n); }
 
+// Kernel timing bills the columns the host mirror shows active (exact for the masked
+// launches of the reliable updates; for a round of inner iterations the share at its start,
+// so a column that stops inside a round is billed until the round ends).
+void bill_active(dd_ctx* c, int ns) {
+    int n = 0;
+    for (int j = 0; j < ns; j++) n += c->host_state[j].active != 0;
+    c->bill_frac = ns > 0 ? (double)n / ns : 1.0;
+}
+
 // Copy a per-segment mask from (pageable) host memory and wait for the copy.
 dd_status push_mask(dd_ctx* c, int* dev, const std::vector<int>& mask) {
     DD_HIP(c, hipMemcpyAsync(dev, mask.data(), sizeof(int) * mask.size(), hipMemcpyHostToDevice, c->stream));
@@ -95,6 +104,7 @@ dd_status norms_to_host(System& S, const cpx<R>* a, double* partial, double* dot
 dd_status residual_to_host(System& S, const cpx<double>* b, const cpx<double>* x, cpx<double>* r,
                            double* partial, double* dots) {
     dd_ctx* c = S.c;
+    c->bill_frac = 1.0;  // every column
     S.apply64(0, EPI_RESID, x, r, b, partial, nullptr);
     launch_finalize(c, FIN_STORE, S.nseg, S.sp0[0], partial, nullptr, dots);
     DD_HIP(c, hipGetLastError());
@@ -226,6 +236,7 @@ dd_status bicgstab_reliable(System& S, const cpx<double>* b, cpx<double>* x, con
     static const bool dbg = std::getenv("DD_DEBUG") != nullptr;
     while (ndone < ns && total < p.max_iter) {
         const int k = std::min(check_every, p.max_iter - total);
+        bill_active(c, ns);
         e = rounds.run(k, iteration);
         if (e != DD_OK) return e;
         e = pull_state(c, st, ns);
@@ -366,6 +377,7 @@ dd_status cgnr_reliable(System& S, const cpx<double>* b, cpx<double>* x, const s
         launch_set_resid<R>(c, S.seg, W.r64, r, W.mask_dev);
         e = push_state(c, st, ns);
         if (e != DD_OK) return e;
+        bill_active(c, ns);
         S.apply(1, EPI_NORM, r, z, (const cpx<R>*)nullptr, partial, st);
         launch_finalize(c, FIN_CG_ZZ, ns, S.sp0[kind], partial, st, nullptr);
         launch_copy_segs<R>(c, S.seg, z, pp, st);
@@ -382,6 +394,7 @@ dd_status cgnr_reliable(System& S, const cpx<double>* b, cpx<double>* x, const s
     };
     while (ndone < ns && total < p.max_iter) {
         const int k = std::min(check_every, p.max_iter - total);
+        bill_active(c, ns);
         e = rounds.run(k, iteration);
         if (e != DD_OK) return e;
         e = pull_state(c, st, ns);
@@ -440,6 +453,7 @@ dd_status cgnr_reliable(System& S, const cpx<double>* b, cpx<double>* x, const s
         launch_set_resid<R>(c, S.seg, W.r64, r, W.mask_dev);
         e = push_state(c, st, ns);
         if (e != DD_OK) return e;
+        bill_active(c, ns);
         S.apply(1, EPI_NORM, r, tz, (const cpx<R>*)nullptr, partial, st);
         launch_finalize(c, FIN_CG_ZZ, ns, S.sp0[kind], partial, st, nullptr);
         launch_cg_shift<R>(c, S.seg, pp, z, tz, W.mask_dev);
@@ -578,6 +592,7 @@ dd_status solve_system(System& S, const cpx<double>* b, cpx<double>* x, const dd
         e = p.solver == DD_BICGSTAB ? bicgstab_reliable<double>(S, b, x, bb, p, delta, w, nullptr, W, res, &nonfinite)
                                     : cgnr_reliable<double>(S, b, x, bb, p, delta, w, nullptr, W, res, &nonfinite);
     }
+    c->bill_frac = 1.0;
     if (e != DD_OK) return e;
 
     // whatever the exit, x holds the full correction: report the true residuals

@@ -143,6 +143,40 @@ def test_factorised_overlap_vs_oracle(case, prec):
     assert all(max(st["true_rel_resid"]) <= p.tol for st in stats[:len(doms)])
 
 
+@pytest.mark.parametrize("dlt", [4, 6])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_factorised_thick_overlap_vs_oracle(dlt, prec):
+    """Thick overlap regions (Delta = 4 and 6 on a ring of four 8-slice slabs of a 32 x 4^3
+    lattice: the extended slabs span 16 and 20 slices) against the oracle; the correction to
+    the exact correlator just past the first frontier then shrinks with Delta (Sec. 3.2 Eq. 15;
+    kappa below the free critical value so that the fall-off shows on a lattice this small)."""
+    dd = lib()
+    step(f"factorised thick overlap {dlt} {prec}")
+    T, L, kappa, bc = 32, 4, 0.115, -1
+    doms, src = [(0, 8), (8, 8), (16, 8), (24, 8)], (3, 1, 2, 0)
+    U = random_links(T, L, 0.3, 2450)
+    Sf_ref, _ = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=1e-13, overlap=dlt)
+    ctx = dd.Context(T, L, bc)
+    p = dd.solver_params(tol=1e-13 if prec == "fp64" else 1e-10,
+                         prec=dd.DD_FP64 if prec == "fp64" else dd.DD_MIXED)
+    Ud = dd.pack_links(U)
+    Sf, Se, stats = dd.factorized_propagator(ctx, Ud, kappa, src, doms, p, overlap=dlt, exact=True)
+    bar = 1e-10 if prec == "fp64" else 1e-6
+    assert relerr(dd.unpack_field(Sf), Sf_ref) < bar
+    C = dd.pion_correlator(ctx, Sf, src[0])
+    Cr = O.pion_correlator(T, L, Sf_ref, src[0])
+    assert np.abs(C - Cr).max() / Cr.max() < bar
+    if prec == "fp64":
+        # the correction on the first slice across the frontier falls with Delta (the oracle
+        # gives 1e-5, 1e-7, 2e-9 relative for Delta = 2, 4, 6; slices further on carry the
+        # truncation of the chain over four slabs as well, which Delta does not change)
+        S0, _, _ = dd.factorized_propagator(ctx, Ud, kappa, src, doms, p, overlap=dlt - 2)
+        Ce = dd.pion_correlator(ctx, Se, src[0])
+        C0 = dd.pion_correlator(ctx, S0, src[0])
+        t = 8 - src[0]  # slice 8
+        assert abs(Ce[t] - C[t]) < 0.1 * abs(Ce[t] - C0[t]), (Ce[t], C[t], C0[t])
+
+
 def test_factorised_overlap_errors():
     dd = lib()
     step("factorised overlap errors")
