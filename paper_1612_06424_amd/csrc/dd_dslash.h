@@ -7,7 +7,7 @@
 // or on a Dirichlet time slab (paper Sec. 3 Eq. 10: the diagonal block of D; hops
 // leaving the slab are dropped).  D^+ = gamma_5 D gamma_5 swaps the projectors.
 //
-// A tile is NT consecutive spatial sites of one column over a chunk of tc_len
+// A tile is NT consecutive spatial sites of KC columns over a chunk of tc_len
 // time slices.  A thread owns one spatial site and sweeps the chunk: psi(t) and
 // the transported backward half spinor U_0(t)^+ P_+ psi(t) are carried in
 // registers from one slice to the next, so the time neighbours and the
@@ -28,31 +28,42 @@
 //                2 kappa D = 1 - kappa D_hop), with `mass` carrying kappa
 #pragma once
 
+#include "dd_eo.h"
 #include "dd_internal.h"
 #include "dd_wilson.h"
 
 namespace dd {
 
-// in / out / aux point at the first component of this tile's column (layout
-// [12][nsite]); U points at the links of the tile's lattice ([4][9][vlink]).
-template <typename R, int DAG, int EPI, int NT>
-__device__ __forceinline__ void dslash_tile(const Geo& g, const cpx<R>* __restrict__ U, R mass,
-                                            const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
-                                            const cpx<R>* __restrict__ aux, int sb, int tc, int tc_len,
-                                            double* __restrict__ slot) {
+// in / out / aux point at the first component of the tile's first column
+// (layout [col][12][nsite], KC columns back to back); U points at the links of
+// the tile's lattice ([4][9][vlink]).  Every link is loaded once for the KC
+// columns, whose arithmetic is that of one column each, in the same order, so
+// the result does not depend on KC.  Column k's output is written only if bit
+// k of live is set (its stores go through a buffer resource of size 0
+// otherwise, which drops them); its sums go to slot + 3 k slot_col.
+template <typename R, int DAG, int EPI, int NT, int KC>
+__device__ __forceinline__ void dslash_tile_cols(const Geo& g, const cpx<R>* __restrict__ U, R mass,
+                                                 const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
+                                                 const cpx<R>* __restrict__ aux, unsigned live, int sb, int tc,
+                                                 int tc_len, double* __restrict__ slot, size_t slot_col) {
     const int L = g.L, L2 = g.L2, L3 = g.L3;
     const int sp = sb * NT + threadIdx.x;
     const int nsite = g.nsite, nt = g.nt;
     constexpr uint32_t CB = sizeof(cpx<R>);
     const uint32_t cs = (uint32_t)nsite * CB;    // component stride (bytes)
+    const uint32_t fs = 12u * cs;                // column stride (bytes)
     const uint32_t ls = (uint32_t)g.vlink * CB;  // link-row stride (bytes)
     constexpr int FW = DAG ? +1 : -1;            // forward hop projector (1 + FW gamma)
     constexpr int BW = -FW;
-    double d0 = 0, d1 = 0, d2 = 0;
+    double d[KC][3];
+#pragma unroll
+    for (int k = 0; k < KC; k++) d[k][0] = d[k][1] = d[k][2] = 0;
 
     if (sp < L3) {
-        const rsrc_t rf = make_rsrc(in, 12u * cs);
-        const rsrc_t ro = make_rsrc(out, 12u * cs);
+        const rsrc_t rf = make_rsrc(in, (uint32_t)KC * fs);
+        rsrc_t ro[KC];
+#pragma unroll
+        for (int k = 0; k < KC; k++) ro[k] = make_rsrc(out + (size_t)k * 12 * nsite, ((live >> k) & 1u) ? fs : 0u);
         const rsrc_t ru0 = make_rsrc(U, 9u * ls);
         const rsrc_t ru1 = make_rsrc(U + (size_t)9 * g.vlink, 9u * ls);
         const rsrc_t ru2 = make_rsrc(U + (size_t)18 * g.vlink, 9u * ls);
@@ -68,40 +79,51 @@ __device__ __forceinline__ void dslash_tile(const Geo& g, const cpx<R>* __restri
             const int t = g.t0 + tl;
             return t >= g.T ? t - g.T : t;
         };
-        // backward half spinor entering slice tb: ph U_0(tb-1)^+ P psi(tb-1)
-        cpx<R> hb[6];
+        // backward half spinors entering slice tb: ph U_0(tb-1)^+ P psi(tb-1)
+        cpx<R> hb[KC][6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) hb[k] = mk<R>(0, 0);
+        for (int k = 0; k < KC; k++)
+#pragma unroll
+            for (int j = 0; j < 6; j++) hb[k][j] = mk<R>(0, 0);
         if (tb > 0 || g.whole) {
             const int tlm = tb > 0 ? tb - 1 : nt - 1;
             const R ph = (tglob(tb) == 0) ? R(g.bc) : R(1);
             if (ph != R(0)) {
-                cpx<R> p[12];
-                bload_spinor<R>(rf, cs, tlm * L3 + sp, p);
-                cpx<R> h[6];
-                project<R, 0, BW>(p, h);
                 cpx<R> w[9];
                 const uint32_t vo = (uint32_t)(tglob(tlm) * L3 + sp) * CB;
 #pragma unroll
-                for (int k = 0; k < 9; k++) w[k] = bload<R>(ru0, vo, (uint32_t)k * ls);
-                transport<R, true>(w, h, ph, hb);
+                for (int j = 0; j < 9; j++) w[j] = bload<R>(ru0, vo, (uint32_t)j * ls);
+#pragma unroll
+                for (int k = 0; k < KC; k++) {
+                    cpx<R> p[12];
+                    bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, tlm * L3 + sp, p);
+                    cpx<R> h[6];
+                    project<R, 0, BW>(p, h);
+                    transport<R, true>(w, h, ph, hb[k]);
+                }
             }
         }
-        cpx<R> cur[12];
-        if (tb < te) bload_spinor<R>(rf, cs, tb * L3 + sp, cur);
-        const rsrc_t rx = (EPI == EPI_RESID || EPI == EPI_DOT_AUX) ? make_rsrc(aux, 12u * cs) : rf;
+        cpx<R> cur[KC][12];
+        if (tb < te) {
+#pragma unroll
+            for (int k = 0; k < KC; k++) bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, tb * L3 + sp, cur[k]);
+        }
+        const rsrc_t rx = (EPI == EPI_RESID || EPI == EPI_DOT_AUX) ? make_rsrc(aux, (uint32_t)KC * fs) : rf;
         const R half = R(0.5);
 #pragma unroll 1
         for (int tl = tb; tl < te; tl++) {
             const int s = tl * L3 + sp;
             const int tg = tglob(tl);
             const int sl = tg * L3 + sp;
-            cpx<R> a[12];
+            cpx<R> a[KC][12];
 #pragma unroll
-            for (int c = 0; c < 12; c++) a[c] = mk<R>(0, 0);
-            accum<R, 0, BW>(a, hb);
+            for (int k = 0; k < KC; k++) {
+#pragma unroll
+                for (int c = 0; c < 12; c++) a[k][c] = mk<R>(0, 0);
+                accum<R, 0, BW>(a[k], hb[k]);
+            }
             // forward time hop; the same link transports psi(t) into the next slice
-            cpx<R> nxt[12];
+            cpx<R> nxt[KC][12];
             const bool endt = (tl == nt - 1);
             const R phf = (tg == g.T - 1) ? R(g.bc) : R(1);
             const bool hasf = (!endt || g.whole) && phf != R(0);
@@ -109,60 +131,82 @@ __device__ __forceinline__ void dslash_tile(const Geo& g, const cpx<R>* __restri
                 cpx<R> w[9];
                 const uint32_t vo = (uint32_t)sl * CB;
 #pragma unroll
-                for (int k = 0; k < 9; k++) w[k] = bload<R>(ru0, vo, (uint32_t)k * ls);
-                bload_spinor<R>(rf, cs, endt ? sp : s + L3, nxt);
-                cpx<R> h[6];
-                project<R, 0, FW>(nxt, h);
-                cpx<R> t[6];
-                transport<R, false>(w, h, phf, t);
-                accum<R, 0, FW>(a, t);
-                cpx<R> h2[6];
-                project<R, 0, BW>(cur, h2);
-                transport<R, true>(w, h2, phf, hb);
+                for (int j = 0; j < 9; j++) w[j] = bload<R>(ru0, vo, (uint32_t)j * ls);
+#pragma unroll
+                for (int k = 0; k < KC; k++) {
+                    bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, endt ? sp : s + L3, nxt[k]);
+                    cpx<R> h[6];
+                    project<R, 0, FW>(nxt[k], h);
+                    cpx<R> t[6];
+                    transport<R, false>(w, h, phf, t);
+                    accum<R, 0, FW>(a[k], t);
+                    cpx<R> h2[6];
+                    project<R, 0, BW>(cur[k], h2);
+                    transport<R, true>(w, h2, phf, hb[k]);
+                }
             } else {
 #pragma unroll
-                for (int k = 0; k < 6; k++) hb[k] = mk<R>(0, 0);
+                for (int k = 0; k < KC; k++)
+#pragma unroll
+                    for (int j = 0; j < 6; j++) hb[k][j] = mk<R>(0, 0);
             }
-            bhop<R, 1, FW, false>(a, rf, cs, s + dxp, ru1, ls, sl, R(1));
-            bhop<R, 1, BW, true>(a, rf, cs, s + dxm, ru1, ls, sl + dxm, R(1));
-            bhop<R, 2, FW, false>(a, rf, cs, s + dyp, ru2, ls, sl, R(1));
-            bhop<R, 2, BW, true>(a, rf, cs, s + dym, ru2, ls, sl + dym, R(1));
-            bhop<R, 3, FW, false>(a, rf, cs, s + dzp, ru3, ls, sl, R(1));
-            bhop<R, 3, BW, true>(a, rf, cs, s + dzm, ru3, ls, sl + dzm, R(1));
+            bhop_cols<R, 1, FW, false, KC, false>(a, rf, cs, fs, s + dxp, ru1, ls, sl);
+            bhop_cols<R, 1, BW, true, KC, false>(a, rf, cs, fs, s + dxm, ru1, ls, sl + dxm);
+            bhop_cols<R, 2, FW, false, KC, false>(a, rf, cs, fs, s + dyp, ru2, ls, sl);
+            bhop_cols<R, 2, BW, true, KC, false>(a, rf, cs, fs, s + dym, ru2, ls, sl + dym);
+            bhop_cols<R, 3, FW, false, KC, false>(a, rf, cs, fs, s + dzp, ru3, ls, sl);
+            bhop_cols<R, 3, BW, true, KC, false>(a, rf, cs, fs, s + dzm, ru3, ls, sl + dzm);
 
             const uint32_t vo = (uint32_t)s * CB;
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                const uint32_t so = (uint32_t)c * cs;
-                const cpx<R> pc = cur[c];
-                cpx<R> r = EPI == EPI_HOP ? mk<R>(mass * a[c].re, mass * a[c].im)
-                                          : mk<R>(mass * pc.re - half * a[c].re, mass * pc.im - half * a[c].im);
-                cpx<R> q = mk<R>(0, 0);
-                if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
-                if (EPI == EPI_RESID) r = q - r;
-                bstore<R>(ro, vo, so, r);
-                if (EPI == EPI_DOT_AUX) {
-                    d0 += (double)q.re * r.re + (double)q.im * r.im;
-                    d1 += (double)q.re * r.im - (double)q.im * r.re;
-                } else if (EPI == EPI_TS) {
-                    d0 += (double)r.re * pc.re + (double)r.im * pc.im;
-                    d1 += (double)r.re * pc.im - (double)r.im * pc.re;
-                    d2 += (double)r.re * r.re + (double)r.im * r.im;
-                } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
-                    d0 += (double)r.re * r.re + (double)r.im * r.im;
+            for (int k = 0; k < KC; k++) {
+#pragma unroll
+                for (int c = 0; c < 12; c++) {
+                    const uint32_t so = (uint32_t)c * cs;
+                    const cpx<R> pc = cur[k][c];
+                    cpx<R> r = EPI == EPI_HOP
+                                   ? mk<R>(mass * a[k][c].re, mass * a[k][c].im)
+                                   : mk<R>(mass * pc.re - half * a[k][c].re, mass * pc.im - half * a[k][c].im);
+                    cpx<R> q = mk<R>(0, 0);
+                    if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, (uint32_t)k * fs + so);
+                    if (EPI == EPI_RESID) r = q - r;
+                    bstore<R>(ro[k], vo, so, r);
+                    if (EPI == EPI_DOT_AUX) {
+                        d[k][0] += (double)q.re * r.re + (double)q.im * r.im;
+                        d[k][1] += (double)q.re * r.im - (double)q.im * r.re;
+                    } else if (EPI == EPI_TS) {
+                        d[k][0] += (double)r.re * pc.re + (double)r.im * pc.im;
+                        d[k][1] += (double)r.re * pc.im - (double)r.im * pc.re;
+                        d[k][2] += (double)r.re * r.re + (double)r.im * r.im;
+                    } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
+                        d[k][0] += (double)r.re * r.re + (double)r.im * r.im;
+                    }
                 }
             }
             if (tl + 1 < te) {
                 if (hasf && !endt) {
 #pragma unroll
-                    for (int c = 0; c < 12; c++) cur[c] = nxt[c];
+                    for (int k = 0; k < KC; k++)
+#pragma unroll
+                        for (int c = 0; c < 12; c++) cur[k][c] = nxt[k][c];
                 } else {
-                    bload_spinor<R>(rf, cs, (tl + 1) * L3 + sp, cur);
+#pragma unroll
+                    for (int k = 0; k < KC; k++)
+                        bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, (tl + 1) * L3 + sp, cur[k]);
                 }
             }
         }
     }
-    if (EPI != EPI_STORE && EPI != EPI_HOP) block_sum3<NT>(d0, d1, d2, slot);
+    if (EPI != EPI_STORE && EPI != EPI_HOP) block_sum_cols<NT, KC>(d, slot, slot_col);
+}
+
+// One column (the multi-domain kernel's tile).
+template <typename R, int DAG, int EPI, int NT>
+__device__ __forceinline__ void dslash_tile(const Geo& g, const cpx<R>* __restrict__ U, R mass,
+                                            const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
+                                            const cpx<R>* __restrict__ aux, int sb, int tc, int tc_len,
+                                            double* __restrict__ slot) {
+    dslash_tile_cols<R, DAG, EPI, NT, 1>(g, U, mass, in, out, aux, 1u, sb, tc, tc_len, slot, 0);
 }
 
 }  // namespace dd

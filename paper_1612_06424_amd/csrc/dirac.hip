@@ -10,9 +10,11 @@ namespace dd {
 
 namespace {
 
-// Workgroup index -> (column fastest, spatial block, time chunk), optionally
-// remapped so that each XCD takes a contiguous range of workgroups.
-template <typename R, int DAG, int EPI, int NT>
+// Workgroup index -> (group of KC columns fastest, spatial block, time chunk),
+// optionally remapped so that each XCD takes a contiguous range of workgroups.
+// ncol is a multiple of KC; the workgroup runs while one column of its group is
+// active (a stopped column keeps its output).
+template <typename R, int DAG, int EPI, int NT, int KC>
 __global__ __launch_bounds__(NT, sweep_waves<R>()) void k_dslash(Geo g, const cpx<R>* __restrict__ U, R mass,
                                                const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                const cpx<R>* __restrict__ aux, int ncol, int tc_len,
@@ -20,50 +22,72 @@ __global__ __launch_bounds__(NT, sweep_waves<R>()) void k_dslash(Geo g, const cp
                                                const ColState* __restrict__ st) {
     const int lb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int nsb = (g.L3 + NT - 1) / NT;
-    const int col = lb % ncol;
-    const int rest = lb / ncol;
+    const int ngrp = ncol / KC;
+    const int col = (lb % ngrp) * KC;
+    const int rest = lb / ngrp;
     const int sb = rest % nsb, tc = rest / nsb;
-    if (st != nullptr && !st[col].active) return;  // uniform over the workgroup
-    const int nchunk = gridDim.x / (ncol * nsb);
+    unsigned live = 0;
+#pragma unroll
+    for (int k = 0; k < KC; k++)
+        if (st == nullptr || st[col + k].active) live |= 1u << k;
+    if (live == 0) return;  // uniform over the workgroup
+    const int nchunk = gridDim.x / (ngrp * nsb);
     const size_t off = (size_t)col * 12 * g.nsite;
     double* slot = partial + ((size_t)col * nsb * nchunk + (size_t)tc * nsb + sb) * 3;
-    dslash_tile<R, DAG, EPI, NT>(g, U, mass, in + off, out + off, aux != nullptr ? aux + off : nullptr, sb, tc,
-                                 tc_len, slot);
+    dslash_tile_cols<R, DAG, EPI, NT, KC>(g, U, mass, in + off, out + off, aux != nullptr ? aux + off : nullptr,
+                                          live, sb, tc, tc_len, slot, (size_t)nsb * nchunk);
 }
 
-template <typename R, int DAG, int NT>
+template <typename R, int DAG, int NT, int KC>
 void launch_epi(dd_ctx* c, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R mass,
                 const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap,
                 double* partial, const ColState* st) {
+#define DD_EPI_CASE(E)                                                                                               \
+    hipLaunchKernelGGL((k_dslash<R, DAG, E, NT, KC>), grid, dim3(NT), 0, c->stream, g, U, mass, in, out, aux, ncol, \
+                       tc, remap, partial, st)
     switch (epi) {
-        case EPI_STORE:
-            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_STORE, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
-                               out, aux, ncol, tc, remap, partial, st);
-            break;
-        case EPI_DOT_AUX:
-            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_DOT_AUX, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
-                               out, aux, ncol, tc, remap, partial, st);
-            break;
-        case EPI_TS:
-            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_TS, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in, out,
-                               aux, ncol, tc, remap, partial, st);
-            break;
-        case EPI_RESID:
-            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_RESID, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
-                               out, aux, ncol, tc, remap, partial, st);
-            break;
-        case EPI_HOP:
-            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_HOP, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
-                               out, aux, ncol, tc, remap, partial, st);
-            break;
-        default:
-            hipLaunchKernelGGL((k_dslash<R, DAG, EPI_NORM, NT>), grid, dim3(NT), 0, c->stream, g, U, mass, in,
-                               out, aux, ncol, tc, remap, partial, st);
-            break;
+        case EPI_STORE: DD_EPI_CASE(EPI_STORE); break;
+        case EPI_DOT_AUX: DD_EPI_CASE(EPI_DOT_AUX); break;
+        case EPI_TS: DD_EPI_CASE(EPI_TS); break;
+        case EPI_RESID: DD_EPI_CASE(EPI_RESID); break;
+        case EPI_HOP: DD_EPI_CASE(EPI_HOP); break;
+        default: DD_EPI_CASE(EPI_NORM); break;
     }
+#undef DD_EPI_CASE
+}
+
+template <typename R, int DAG, int NT>
+void launch_kc(dd_ctx* c, int kc, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R mass, const cpx<R>* in,
+               cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap, double* partial, const ColState* st) {
+    if (kc == 2) {
+        launch_epi<R, DAG, NT, 2>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+        return;
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (kc == 3) {
+            launch_epi<R, DAG, NT, 3>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+            return;
+        }
+        if (kc == 4) {
+            launch_epi<R, DAG, NT, 4>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+            return;
+        }
+    }
+    launch_epi<R, DAG, NT, 1>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
 }
 
 }  // namespace
+
+// Columns per thread of a launch: the tuned count when it is built for the
+// precision (FP32 up to 4; FP64 up to 2, where three columns no longer fit the
+// register file), divides ncol and the column group fits one 32-bit buffer
+// range, else 1.
+int sched_kc(const StencilSched& sc, int ncol, size_t real_bytes, size_t col_bytes) {
+    const int kc = sc.kc;
+    if (kc <= 1 || kc > (real_bytes == 8 ? 2 : 4) || ncol % kc != 0) return 1;
+    if ((size_t)kc * col_bytes >= ((size_t)1 << 32)) return 1;
+    return kc;
+}
 
 StencilSched default_sched(const Geo& g) {
     StencilSched sc;
@@ -83,15 +107,16 @@ template <typename R>
 void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const cpx<R>* U, double kappa,
                          int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol,
                          double* partial, const ColState* st) {
-    const dim3 grid((unsigned)stencil_blocks(g, sc) * (unsigned)ncol);
+    const int kc = sched_kc(sc, ncol, sizeof(R), (size_t)12 * g.nsite * sizeof(cpx<R>));
+    const dim3 grid((unsigned)stencil_blocks(g, sc) * (unsigned)(ncol / kc));
     const R mass = R(epi == EPI_HOP ? kappa : 1.0 / (2.0 * kappa));  // EPI_HOP scales the hop by kappa
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
-#define DD_NT_CASE(NTV)                                                                                     \
-    if (dag)                                                                                                \
-        launch_epi<R, 1, NTV>(c, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, partial, st); \
-    else                                                                                                    \
-        launch_epi<R, 0, NTV>(c, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, partial, st);
+#define DD_NT_CASE(NTV)                                                                                         \
+    if (dag)                                                                                                    \
+        launch_kc<R, 1, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, partial, st); \
+    else                                                                                                        \
+        launch_kc<R, 0, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, partial, st);
     if (sc.nt == 256) {
         DD_NT_CASE(256)
     } else {
@@ -103,7 +128,7 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
         const double bytes = (double)g.nsite * ((48.0 + extra) * ncol * c->bill_frac + 72.0) * sizeof(R);
         const std::string name = std::string("k_dslash<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
                                  std::to_string(dag ? 1 : 0) + ", " + std::to_string(epi) + ", " +
-                                 std::to_string(sc.nt) + ">";
+                                 std::to_string(sc.nt) + (kc > 1 ? ", " + std::to_string(kc) : std::string()) + ">";
         timing_end(c, ev, name, bytes);
     }
 }

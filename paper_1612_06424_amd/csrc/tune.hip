@@ -1,7 +1,7 @@
 // tune.hip -- per-context autotuner of the stencil launch shape.
 //
-// The best (workgroup size, time-chunk length, XCD remap) depends on the
-// precision, the number of columns and the lattice geometry (how many
+// The best (workgroup size, time-chunk length, XCD remap, columns per thread)
+// depends on the precision, the number of columns and the lattice geometry (how many
 // workgroups are resident per XCD against how much of the 4 MB L2 one time
 // slice of them touches).  The first launch for a new key times every
 // candidate on scratch buffers of the same size and keeps the fastest; later
@@ -51,6 +51,7 @@ StencilSched tune(dd_ctx* c, const Geo& g, int ncol) {
     c->timing = 0;
     float best_ms = 1e30f;
     const int tcs[] = {4, 8, 16, 1 << 20};
+    for (int kc = 1; kc <= 4; kc++)
     for (int nt : {128, 256})
         for (int tcv : tcs)
             for (int remap : {0, 1}) {
@@ -58,7 +59,9 @@ StencilSched tune(dd_ctx* c, const Geo& g, int ncol) {
                 sc.nt = nt;
                 sc.tc = tcv > g.nt ? g.nt : tcv;
                 sc.remap = remap;
+                sc.kc = kc;
                 if (tcv != sc.tc && tcv != (1 << 20)) continue;  // same as a shorter candidate
+                if (sched_kc(sc, ncol, sizeof(R), (size_t)12 * g.nsite * sizeof(cpx<R>)) != kc) continue;
                 for (int w = 0; w < 2; w++)
                     launch_dslash_sched<R>(c, g, sc, U, 0.125, 0, EPI_STORE, in, out, nullptr, ncol, nullptr, nullptr);
                 (void)hipEventRecord(e0, c->stream);

@@ -135,7 +135,8 @@ def test_batched_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
 def test_batched_96_domains_full_size():
     """The 96-domain workload (shapes 8x8^3 .. 16x16^3, own links and kappa, 12
     point sources each), mixed CGNR to 1e-10; sampled domains checked with the
-    oracle's operator, every domain with the library's own FP64 residual."""
+    oracle's operator, every domain with the library's own FP64 residual; a second
+    solve on the same inputs agrees with the first to 1e-9."""
     dd = lib()
     step("batched 96 domains")
     doms = batched_domains(96)
@@ -154,6 +155,19 @@ def test_batched_96_domains_full_size():
     p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED)
     stats = dd.block_solve_batched(ctx, items, p)
     assert all(max(s["true_rel_resid"]) <= 1e-10 for s in stats)
+    # the same solve again (tuned shape reused, graph captured anew).  Nearly always bitwise
+    # the first; rarely (a few first solves of a context in many) one domain differed at
+    # the 1e-11 level with equal iteration counts, cause not found.  The bar below is far
+    # above that and far below a launch that raced on the vectors (residuals of 1e-4).
+    first = [it["x"].clone() for it in items]
+    stats2 = dd.block_solve_batched(ctx, items, p)
+    assert all(max(s["true_rel_resid"]) <= 1e-10 for s in stats2)
+    same = 0
+    for k, (a, it) in enumerate(zip(first, items)):
+        same += int(torch.equal(a, it["x"]))
+        assert relerr(dd.unpack_field(a), dd.unpack_field(it["x"])) < 1e-9, k
+    print(f"[gpu-step] repeat: {same} of {len(items)} domains bitwise equal", flush=True)
+    assert max(abs(a["iters"] - b["iters"]) for a, b in zip(stats, stats2)) <= 2
     for k in (0, 17, 95):
         it, d = items[k], doms[k]
         x = dd.unpack_field(it["x"])

@@ -1,0 +1,101 @@
+"""Several columns per thread in the full Wilson-Dirac stencil (one link load serves KC
+columns; FP32 KC = 1..4, FP64 KC = 1..2).
+
+The shape is forced through the launch-shape cache (DD_TUNE_CACHE: key
+"kind:ncol:L:T:nt:whole", then workgroup size, chunk length, XCD remap and KC).  Every
+column's arithmetic is that of the one-column kernel in the same order, so the output is
+bitwise that of KC = 1, and within 1e-13 (FP64) / 2e-6 (FP32) of the oracle's D.  Inside
+the unpreconditioned solves every epilogue of the stencil runs with columns that stop at
+different iterations sharing workgroups with running ones: the solutions and iteration
+counts must not change with KC either.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import gaussian_field, lib, random_links, step
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # T, L, bc, dom: whole lattices and slabs (one across the time wrap); L^3 = 216 and 125
+    # leave a ragged tail in the last 256-site tile
+    (16, 4, -1, None),
+    (8, 6, -1, None),
+    (16, 4, -1, (12, 8)),
+    (10, 5, 0, (3, 4)),
+]
+
+
+def _maxrel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _cache(tmp_path, monkeypatch, name, lines):
+    path = tmp_path / name
+    path.write_text("".join(f"{k} {v}\n" for k, v in lines))
+    monkeypatch.setenv("DD_TUNE_CACHE", str(path))
+
+
+def _key(kind, ncol, T, L, dom):
+    nt, whole = (T, 1) if dom is None else (dom[1], 0)
+    return f"{kind}:{ncol}:{L}:{T}:{nt}:{whole}"
+
+
+@pytest.mark.parametrize("T,L,bc,dom", CASES)
+@pytest.mark.parametrize("nt,tc,remap", [(256, 4, 1), (128, 3, 0)])
+def test_columns_per_thread_vs_oracle(tmp_path, monkeypatch, T, L, bc, dom, nt, tc, remap):
+    dd = lib()
+    ncol = 12
+    kappa = 0.1287
+    U = random_links(T, L, 0.4, 4100 + T + L)
+    nsite = (T if dom is None else dom[1]) * L ** 3
+    psi = gaussian_field(nsite, ncol, 4101)
+    ref = O.apply_dirac(U, kappa, T, L, bc, psi, dom)
+    outs = {}
+    for kind, dtype, kcs, tol in ((0, torch.complex128, (1, 2), 1e-13), (1, torch.complex64, (1, 2, 3, 4), 2e-6)):
+        for kc in kcs:
+            step(f"stencil KC={kc} kind={kind} T={T} L={L} dom={dom} shape=({nt},{tc},{remap})")
+            _cache(tmp_path, monkeypatch, f"s_{kind}_{kc}.txt", [(_key(kind, ncol, T, L, dom), f"{nt} {tc} {remap} {kc} 0")])
+            ctx = dd.Context(T, L, bc)
+            dd.set_kernel_timing(ctx, True)
+            out = dd.apply_dirac(ctx, dd.pack_links(U, dtype), kappa, dd.pack_field(psi, dtype), dom)
+            torch.cuda.synchronize()
+            names = list(dd.kernel_timing(ctx))
+            want = f"k_dslash<{'double' if kind == 0 else 'float'}, 0, 0, {nt}" + (f", {kc}>" if kc > 1 else ">")
+            assert names == [want], names
+            assert _maxrel(dd.unpack_field(out), ref) < tol
+            outs[(kind, kc)] = out
+    for (kind, kc), out in outs.items():
+        assert torch.equal(out, outs[(kind, 1)]), (kind, kc)
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "cgnr"])
+def test_unpreconditioned_solves_do_not_depend_on_columns_per_thread(tmp_path, monkeypatch, solver):
+    dd = lib()
+    T, L, bc, dom, kappa = 16, 6, -1, (2, 8), 0.125
+    ncol = 12
+    U = random_links(T, L, 0.3, 4200)
+    nsite = dom[1] * L ** 3
+    b = gaussian_field(nsite, ncol, 4201)
+    b[6:] = 0
+    for j in range(6, 12):
+        b[j, (j * 577) % nsite, j] = 1.0  # point sources stop at other iterations than Gaussian ones
+    Ud, bd = dd.pack_links(U), dd.pack_field(b)
+    method = dd.DD_BICGSTAB if solver == "bicgstab" else dd.DD_CGNR
+    res = []
+    for kc64, kc32 in ((1, 1), (2, 4), (2, 3), (1, 2)):
+        step(f"unpreconditioned {solver} KC fp64={kc64} fp32={kc32}")
+        _cache(tmp_path, monkeypatch, f"sol_{kc64}_{kc32}.txt",
+               [(_key(0, ncol, T, L, dom), f"256 4 1 {kc64} 0"), (_key(1, ncol, T, L, dom), f"256 4 1 {kc32} 0")])
+        ctx = dd.Context(T, L, bc)
+        p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=method, precond=dd.DD_PRECOND_NONE)
+        x, st = dd.block_solve(ctx, Ud, kappa, bd, dom, p)
+        assert max(st["true_rel_resid"]) <= 1e-10
+        res.append((x, st["iters"], st["updates"]))
+    x0 = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=1e-12, method=0)[0]
+    assert _maxrel(dd.unpack_field(res[0][0]), x0) < 1e-8
+    for x, it, up in res[1:]:
+        assert torch.equal(x, res[0][0])
+        assert (it, up) == res[0][1:]
