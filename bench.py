@@ -45,14 +45,14 @@ def eo_iteration_bytes(nh, ncol, prec, method):
     of nh even (= odd) sites with ncol columns: every vector read or written once per kernel,
     every link once per half hop (stored as two rows, 12 reals, in the FP32 recursion of a mixed
     solve; 18 reals in FP64).  Per even site and column, in reals:
-      CGNR      4 half hops (in + out, + self in the two second halves) 240, x/r update 6 x 24,
-                p update 3 x 24: 456;
+      CGNR      4 half hops (in + out, + self in the two second halves) 240, r update 3 x 24,
+                x and p update 5 x 24: 432;
       BiCGStab  4 half hops with the <r^, v> (aux) and <t, s> epilogues 264, p update 4 x 24,
                 s update 3 x 24, x/r update 8 x 24: 624.
     The reliable updates (FP64 residuals every few tens of iterations) are not counted."""
     rb = 4 if prec == "mixed" else 8
     links = 96 if prec == "mixed" else 144
-    per_col = 456 if method == "cgnr" else 624
+    per_col = 432 if method == "cgnr" else 624
     return nh * (per_col * ncol + 4 * links) * rb
 
 

@@ -105,7 +105,7 @@ struct ColState {
     int active;                 // 1 while iterating
     int iters;                  // iterations done by this column
     int breakdown;              // 1: stalled (rho, <r^,v> or omega vanished), 2: non-finite
-    int pad;
+    int xdue;                   // CGNR: alpha p of the current iteration still to be added to x
 };
 
 // ------------------------------------------------------------------ context
@@ -255,10 +255,9 @@ template <typename R>
 void launch_bicg_xr(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* s,
                     const cpx<R>* t, const cpx<R>* rh, double* partial, const ColState* st);
 template <typename R>
-void launch_cg_xr(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* w,
-                  double* partial, const ColState* st);
+void launch_cg_r(dd_ctx* c, const Segs& S, cpx<R>* r, const cpx<R>* w, double* partial, const ColState* st);
 template <typename R>
-void launch_cg_p(dd_ctx* c, const Segs& S, cpx<R>* p, const cpx<R>* z, const ColState* st);
+void launch_cg_px(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* p, const cpx<R>* z, const ColState* st);
 template <typename R>
 void launch_norm2(dd_ctx* c, const Segs& S, const cpx<R>* a, double* partial);
 template <typename R>

@@ -4,7 +4,8 @@
 // lattice, or every column of every domain of a batch.  Segments are laid out
 // back to back in each work vector and may differ in length; every elementwise
 // workgroup covers kBlock * kElems consecutive elements of one segment (each
-// thread kElems of them, kBlock apart, so every load is coalesced), found
+// thread kElems of them in 16-byte units kBlock apart, so every load is
+// coalesced), found
 // through a workgroup -> segment table (Segs).  Columns whose ColState is inactive skip
 // their work; the reliable-update helpers are selected by a per-segment mask.
 //
@@ -27,135 +28,236 @@ __device__ inline cpx<R> scal(const double re, const double im, cpx<R> a) {
     return {R(re) * a.re - R(im) * a.im, R(re) * a.im + R(im) * a.re};
 }
 
-// This workgroup's segment, and the first of this thread's kElems elements
-// (element j of the thread is k + j * kBlock).
+// The unit a lane moves per access: one complex number in FP64 (16 bytes), two
+// consecutive ones in FP32 (16 bytes as well, so that a wavefront issues as few
+// address requests for FP32 vectors as for FP64 ones).  Segments start at even
+// elements and have even lengths (multiples of 12), so the pairs never straddle
+// two segments.
+template <typename R>
+struct Lane {
+    using T = cpx<R>;
+    static constexpr int P = 1;
+};
+struct alignas(16) c2f {
+    cpx<float> a, b;
+};
+template <>
+struct Lane<float> {
+    using T = c2f;
+    static constexpr int P = 2;
+};
+struct alignas(16) c2d {
+    cpx<double> a, b;
+};
+template <typename R>
+struct Wide {  // the FP64 counterpart of one lane unit of R
+    using T = cpx<double>;
+};
+template <>
+struct Wide<float> {
+    using T = c2d;
+};
+
+__device__ inline c2f operator+(c2f x, c2f y) { return {x.a + y.a, x.b + y.b}; }
+__device__ inline c2f operator-(c2f x, c2f y) { return {x.a - y.a, x.b - y.b}; }
+__device__ inline c2f operator*(float s, c2f x) { return {s * x.a, s * x.b}; }
+__device__ inline c2f scal(const double re, const double im, c2f x) { return {scal(re, im, x.a), scal(re, im, x.b)}; }
+template <typename R>
+__device__ inline cpx<R> zero_of(cpx<R>) { return {R(0), R(0)}; }
+__device__ inline c2f zero_of(c2f) { return {{0.f, 0.f}, {0.f, 0.f}}; }
+// sums of conj(h) r (re, im) and |r|^2 over the complex numbers of a unit
+template <typename R>
+__device__ inline void dot_acc(double& d0, double& d1, cpx<R> h, cpx<R> r) {
+    d0 += (double)h.re * r.re + (double)h.im * r.im;
+    d1 += (double)h.re * r.im - (double)h.im * r.re;
+}
+__device__ inline void dot_acc(double& d0, double& d1, c2f h, c2f r) {
+    dot_acc(d0, d1, h.a, r.a);
+    dot_acc(d0, d1, h.b, r.b);
+}
+template <typename R>
+__device__ inline void norm_acc(double& d, cpx<R> r) {
+    d += (double)r.re * r.re + (double)r.im * r.im;
+}
+__device__ inline void norm_acc(double& d, c2f r) {
+    norm_acc(d, r.a);
+    norm_acc(d, r.b);
+}
+// FP64 <-> Krylov precision
+template <typename R>
+__device__ inline cpx<R> narrow(cpx<double> v) { return {(R)v.re, (R)v.im}; }
+__device__ inline c2f narrow2(c2d v) { return {narrow<float>(v.a), narrow<float>(v.b)}; }
+__device__ inline cpx<double> widen_add(cpx<double> x, cpx<double> e) { return {x.re + e.re, x.im + e.im}; }
+__device__ inline cpx<double> widen_add(cpx<double> x, cpx<float> e) {
+    return {x.re + (double)e.re, x.im + (double)e.im};
+}
+__device__ inline c2d widen_add(c2d x, c2f e) { return {widen_add(x.a, e.a), widen_add(x.b, e.b)}; }
+
+// This workgroup's segment, and the first of this thread's units (unit j of the
+// thread is k + j * kBlock); P complex numbers per unit.
+template <int P>
 struct SegPos {
+    static constexpr int NE = kElems / P;  // units per thread
     int seg;
-    int i0;     // offset of the first element inside the segment
-    int len;    // segment length
-    size_t k;   // index of the first element in the work vectors
+    int i0;     // offset of the first unit inside the segment
+    int len;    // segment length in units
+    size_t k;   // index of the first unit in the work vectors
     __device__ bool live(int j) const { return i0 + j * kBlock < len; }
-    __device__ bool full() const { return i0 + (kElems - 1) * kBlock < len; }
+    __device__ bool full() const { return i0 + (NE - 1) * kBlock < len; }
     __device__ size_t at(int j) const { return k + (size_t)j * kBlock; }
 };
-__device__ inline SegPos seg_pos(const Segs& S) {
-    SegPos q;
+template <int P = 1>
+__device__ inline SegPos<P> seg_pos(const Segs& S) {
+    SegPos<P> q;
     q.seg = S.eseg[blockIdx.x];
-    q.i0 = ((int)blockIdx.x - S.eb0[q.seg]) * (kBlock * kElems) + (int)threadIdx.x;
-    q.len = S.len[q.seg];
-    q.k = (size_t)S.off[q.seg] + (size_t)q.i0;
+    q.i0 = ((int)blockIdx.x - S.eb0[q.seg]) * (kBlock * kElems / P) + (int)threadIdx.x;
+    q.len = S.len[q.seg] / P;
+    q.k = (size_t)(S.off[q.seg] / P) + (size_t)q.i0;
     return q;
 }
 
-// Elementwise kernels read all their inputs for the kElems elements first
-// (LD), then compute and store (OP), so that every load of a thread is in
-// flight at once; a workgroup at the end of a segment takes the checked path.
+// Elementwise kernels read all their inputs for the NE units first (LD), then
+// compute and store (OP), so that every load of a thread is in flight at once;
+// a workgroup at the end of a segment takes the checked path.
 #define SEG_LOOP(LD, OP)                                          \
     if (q.full()) {                                               \
-        _Pragma("unroll") for (int j = 0; j < kElems; j++) LD;    \
-        _Pragma("unroll") for (int j = 0; j < kElems; j++) OP;    \
+        _Pragma("unroll") for (int j = 0; j < NE; j++) LD;      \
+        _Pragma("unroll") for (int j = 0; j < NE; j++) OP;      \
     } else {                                                      \
-        for (int j = 0; j < kElems; j++)                          \
+        for (int j = 0; j < NE; j++)                            \
             if (q.live(j)) {                                      \
                 LD;                                               \
                 OP;                                               \
             }                                                     \
     }
 
+#define LANE_SETUP(R)                               \
+    using T = typename Lane<R>::T;                  \
+    constexpr int NE = kElems / Lane<R>::P;         \
+    const SegPos<Lane<R>::P> q = seg_pos<Lane<R>::P>(S)
+#define AS(T, ptr) reinterpret_cast<T*>(ptr)
+#define AS_C(T, ptr) reinterpret_cast<const T*>(ptr)
+
 // p = r + beta (p - omega v)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bicg_p(Segs S, const cpx<R>* __restrict__ r, cpx<R>* __restrict__ p,
-                                                   const cpx<R>* __restrict__ v, const ColState* __restrict__ st) {
-    const SegPos q = seg_pos(S);
+__global__ __launch_bounds__(kBlock) void k_bicg_p(Segs S, const cpx<R>* __restrict__ r_, cpx<R>* __restrict__ p_,
+                                                   const cpx<R>* __restrict__ v_, const ColState* __restrict__ st) {
+    LANE_SETUP(R);
     if (!st[q.seg].active) return;
     const ColState& s = st[q.seg];
-    cpx<R> rv[kElems], pv[kElems], vv[kElems];
+    const T* r = AS_C(T, r_);
+    T* p = AS(T, p_);
+    const T* v = AS_C(T, v_);
+    T rv[NE], pv[NE], vv[NE];
     SEG_LOOP((rv[j] = r[q.at(j)], pv[j] = p[q.at(j)], vv[j] = v[q.at(j)]),
              (p[q.at(j)] = rv[j] + scal(s.beta_re, s.beta_im, pv[j] - scal(s.omega_re, s.omega_im, vv[j]))))
 }
 
 // s = r - alpha v
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bicg_s(Segs S, const cpx<R>* __restrict__ r, const cpx<R>* __restrict__ v,
+__global__ __launch_bounds__(kBlock) void k_bicg_s(Segs S, const cpx<R>* __restrict__ r_, const cpx<R>* __restrict__ v_,
                                                    cpx<R>* __restrict__ s_, const ColState* __restrict__ st) {
-    const SegPos q = seg_pos(S);
+    LANE_SETUP(R);
     if (!st[q.seg].active) return;
     const ColState& s = st[q.seg];
-    cpx<R> rv[kElems], vv[kElems];
-    SEG_LOOP((rv[j] = r[q.at(j)], vv[j] = v[q.at(j)]), (s_[q.at(j)] = rv[j] - scal(s.alpha_re, s.alpha_im, vv[j])))
+    const T* r = AS_C(T, r_);
+    const T* v = AS_C(T, v_);
+    T* so = AS(T, s_);
+    T rv[NE], vv[NE];
+    SEG_LOOP((rv[j] = r[q.at(j)], vv[j] = v[q.at(j)]), (so[q.at(j)] = rv[j] - scal(s.alpha_re, s.alpha_im, vv[j])))
 }
 
 // x += alpha p + omega s; r = s - omega t; partials <r^, r>, |r|^2
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_bicg_xr(Segs S, cpx<R>* __restrict__ x, cpx<R>* __restrict__ r,
-                                                    const cpx<R>* __restrict__ p, const cpx<R>* __restrict__ s_,
-                                                    const cpx<R>* __restrict__ t, const cpx<R>* __restrict__ rh,
+__global__ __launch_bounds__(kBlock) void k_bicg_xr(Segs S, cpx<R>* __restrict__ x_, cpx<R>* __restrict__ r_,
+                                                    const cpx<R>* __restrict__ p_, const cpx<R>* __restrict__ s_,
+                                                    const cpx<R>* __restrict__ t_, const cpx<R>* __restrict__ rh_,
                                                     double* __restrict__ partial, const ColState* __restrict__ st) {
-    const SegPos q = seg_pos(S);
+    LANE_SETUP(R);
     if (!st[q.seg].active) return;  // uniform over the workgroup
     double d0 = 0, d1 = 0, d2 = 0;
     const ColState& s = st[q.seg];
-    cpx<R> xv[kElems], pv[kElems], sv[kElems], tv[kElems], hv[kElems];
-    SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)], sv[j] = s_[q.at(j)], tv[j] = t[q.at(j)], hv[j] = rh[q.at(j)]),
+    T* x = AS(T, x_);
+    T* r = AS(T, r_);
+    const T* p = AS_C(T, p_);
+    const T* sv_ = AS_C(T, s_);
+    const T* t = AS_C(T, t_);
+    const T* rh = AS_C(T, rh_);
+    T xv[NE], pv[NE], sv[NE], tv[NE], hv[NE];
+    SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)], sv[j] = sv_[q.at(j)], tv[j] = t[q.at(j)], hv[j] = rh[q.at(j)]),
              ({
                  x[q.at(j)] = xv[j] + scal(s.alpha_re, s.alpha_im, pv[j]) + scal(s.omega_re, s.omega_im, sv[j]);
-                 const cpx<R> rn = sv[j] - scal(s.omega_re, s.omega_im, tv[j]);
+                 const T rn = sv[j] - scal(s.omega_re, s.omega_im, tv[j]);
                  r[q.at(j)] = rn;
-                 d0 += (double)hv[j].re * rn.re + (double)hv[j].im * rn.im;
-                 d1 += (double)hv[j].re * rn.im - (double)hv[j].im * rn.re;
-                 d2 += (double)rn.re * rn.re + (double)rn.im * rn.im;
+                 dot_acc(d0, d1, hv[j], rn);
+                 norm_acc(d2, rn);
              }))
     block_sum3(d0, d1, d2, partial + (size_t)blockIdx.x * 3);
 }
 
-// CGNR: x += alpha p; r -= alpha w; partial |r|^2 (alpha real)
+// CGNR: r -= alpha w; partial |r|^2 (alpha real)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_xr(Segs S, cpx<R>* __restrict__ x, cpx<R>* __restrict__ r,
-                                                  const cpx<R>* __restrict__ p, const cpx<R>* __restrict__ w,
-                                                  double* __restrict__ partial, const ColState* __restrict__ st) {
-    const SegPos q = seg_pos(S);
+__global__ __launch_bounds__(kBlock) void k_cg_r(Segs S, cpx<R>* __restrict__ r_, const cpx<R>* __restrict__ w_,
+                                                 double* __restrict__ partial, const ColState* __restrict__ st) {
+    LANE_SETUP(R);
     if (!st[q.seg].active) return;
     double d0 = 0;
     const R a = R(st[q.seg].alpha_re);
-    cpx<R> xv[kElems], pv[kElems], rv[kElems], wv[kElems];
-    SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)], rv[j] = r[q.at(j)], wv[j] = w[q.at(j)]),
+    T* r = AS(T, r_);
+    const T* w = AS_C(T, w_);
+    T rv[NE], wv[NE];
+    SEG_LOOP((rv[j] = r[q.at(j)], wv[j] = w[q.at(j)]),
              ({
-                 x[q.at(j)] = xv[j] + a * pv[j];
-                 const cpx<R> rn = rv[j] - a * wv[j];
+                 const T rn = rv[j] - a * wv[j];
                  r[q.at(j)] = rn;
-                 d0 += (double)rn.re * rn.re + (double)rn.im * rn.im;
+                 norm_acc(d0, rn);
              }))
     block_sum3(d0, 0.0, 0.0, partial + (size_t)blockIdx.x * 3);
 }
 
-// CGNR: p = z + beta p (beta real)
+// CGNR, the end of an iteration: x += alpha p while that update is due (also for a
+// column that stopped in this iteration), then p = z + beta p for running columns
+// (alpha, beta real).  The x update waits until here so that p is read once.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_p(Segs S, cpx<R>* __restrict__ p, const cpx<R>* __restrict__ z,
-                                                 const ColState* __restrict__ st) {
-    const SegPos q = seg_pos(S);
-    if (!st[q.seg].active) return;
-    const R b = R(st[q.seg].beta_re);
-    cpx<R> zv[kElems], pv[kElems];
-    SEG_LOOP((zv[j] = z[q.at(j)], pv[j] = p[q.at(j)]), (p[q.at(j)] = zv[j] + b * pv[j]))
+__global__ __launch_bounds__(kBlock) void k_cg_px(Segs S, cpx<R>* __restrict__ x_, cpx<R>* __restrict__ p_,
+                                                  const cpx<R>* __restrict__ z_, const ColState* __restrict__ st) {
+    LANE_SETUP(R);
+    const ColState& s = st[q.seg];
+    const bool run = s.active != 0, due = s.xdue != 0;  // uniform over the workgroup
+    if (!run && !due) return;
+    const R a = R(s.alpha_re), b = R(s.beta_re);
+    T* x = AS(T, x_);
+    T* p = AS(T, p_);
+    const T* z = AS_C(T, z_);
+    T xv[NE], pv[NE], zv[NE];
+    if (run) {
+        SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)], zv[j] = z[q.at(j)]),
+                 (x[q.at(j)] = xv[j] + a * pv[j], p[q.at(j)] = zv[j] + b * pv[j]))
+    } else {
+        SEG_LOOP((xv[j] = x[q.at(j)], pv[j] = p[q.at(j)]), (x[q.at(j)] = xv[j] + a * pv[j]))
+    }
 }
 
 // partial |a|^2 of every segment
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_norm2(Segs S, const cpx<R>* __restrict__ a, double* __restrict__ partial) {
-    const SegPos q = seg_pos(S);
+__global__ __launch_bounds__(kBlock) void k_norm2(Segs S, const cpx<R>* __restrict__ a_, double* __restrict__ partial) {
+    LANE_SETUP(R);
     double d0 = 0;
-    cpx<R> v[kElems];
-    SEG_LOOP((v[j] = a[q.at(j)]), (d0 += (double)v[j].re * v[j].re + (double)v[j].im * v[j].im))
+    const T* a = AS_C(T, a_);
+    T v[NE];
+    SEG_LOOP((v[j] = a[q.at(j)]), norm_acc(d0, v[j]))
     block_sum3(d0, 0.0, 0.0, partial + (size_t)blockIdx.x * 3);
 }
 
 // b = a on the active segments
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_copy_segs(Segs S, const cpx<R>* __restrict__ a, cpx<R>* __restrict__ b,
+__global__ __launch_bounds__(kBlock) void k_copy_segs(Segs S, const cpx<R>* __restrict__ a_, cpx<R>* __restrict__ b_,
                                                       const ColState* __restrict__ st) {
-    const SegPos q = seg_pos(S);
+    LANE_SETUP(R);
     if (!st[q.seg].active) return;
-    cpx<R> v[kElems];
+    const T* a = AS_C(T, a_);
+    T* b = AS(T, b_);
+    T v[NE];
     SEG_LOOP((v[j] = a[q.at(j)]), (b[q.at(j)] = v[j]))
 }
 
@@ -163,48 +265,64 @@ __global__ __launch_bounds__(kBlock) void k_copy_segs(Segs S, const cpx<R>* __re
 //   x64 += xk; xk = 0        (xk in the Krylov precision)
 //   rk = (Rk) r64            (replace the recursive residual by the true one)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_fold_x(Segs S, cpx<double>* __restrict__ x, cpx<R>* __restrict__ xk,
+__global__ __launch_bounds__(kBlock) void k_fold_x(Segs S, cpx<double>* __restrict__ x_, cpx<R>* __restrict__ xk_,
                                                    const int* __restrict__ mask) {
-    const SegPos q = seg_pos(S);
+    LANE_SETUP(R);
     if (!mask[q.seg]) return;
-    cpx<R> e[kElems];
-    cpx<double> v[kElems];
-    SEG_LOOP((e[j] = xk[q.at(j)], v[j] = x[q.at(j)]),
-             (x[q.at(j)] = cd(v[j].re + (double)e[j].re, v[j].im + (double)e[j].im), xk[q.at(j)] = cpx<R>{R(0), R(0)}))
+    using W = typename Wide<R>::T;
+    W* x = AS(W, x_);
+    T* xk = AS(T, xk_);
+    T e[NE];
+    W v[NE];
+    SEG_LOOP((e[j] = xk[q.at(j)], v[j] = x[q.at(j)]), (x[q.at(j)] = widen_add(v[j], e[j]), xk[q.at(j)] = zero_of(e[j])))
 }
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_set_resid(Segs S, const cpx<double>* __restrict__ r64,
-                                                      cpx<R>* __restrict__ rk, const int* __restrict__ mask) {
-    const SegPos q = seg_pos(S);
+__global__ __launch_bounds__(kBlock) void k_set_resid(Segs S, const cpx<double>* __restrict__ r64_,
+                                                      cpx<R>* __restrict__ rk_, const int* __restrict__ mask) {
+    LANE_SETUP(R);
     if (!mask[q.seg]) return;
-    cpx<double> v[kElems];
-    SEG_LOOP((v[j] = r64[q.at(j)]), (rk[q.at(j)] = cpx<R>{(R)v[j].re, (R)v[j].im}))
+    using W = typename Wide<R>::T;
+    const W* r64 = AS_C(W, r64_);
+    T* rk = AS(T, rk_);
+    W v[NE];
+    if constexpr (Lane<R>::P == 2) {
+        SEG_LOOP((v[j] = r64[q.at(j)]), (rk[q.at(j)] = narrow2(v[j])))
+    } else {
+        SEG_LOOP((v[j] = r64[q.at(j)]), (rk[q.at(j)] = narrow<R>(v[j])))
+    }
 }
 // BiCGStab restart (mask == 2): fresh shadow residual r^ = r, directions cleared
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_restart_dirs(Segs S, const cpx<R>* __restrict__ r, cpx<R>* __restrict__ rh,
-                                                         cpx<R>* __restrict__ p, cpx<R>* __restrict__ v,
+__global__ __launch_bounds__(kBlock) void k_restart_dirs(Segs S, const cpx<R>* __restrict__ r_, cpx<R>* __restrict__ rh_,
+                                                         cpx<R>* __restrict__ p_, cpx<R>* __restrict__ v_,
                                                          const int* __restrict__ mask) {
-    const SegPos q = seg_pos(S);
+    LANE_SETUP(R);
     if (mask[q.seg] != 2) return;
-    cpx<R> v_[kElems];
-    SEG_LOOP((v_[j] = r[q.at(j)]),
-             (rh[q.at(j)] = v_[j], p[q.at(j)] = cpx<R>{R(0), R(0)}, v[q.at(j)] = cpx<R>{R(0), R(0)}))
+    const T* r = AS_C(T, r_);
+    T* rh = AS(T, rh_);
+    T* p = AS(T, p_);
+    T* v = AS(T, v_);
+    T w[NE];
+    SEG_LOOP((w[j] = r[q.at(j)]), (rh[q.at(j)] = w[j], p[q.at(j)] = zero_of(w[j]), v[q.at(j)] = zero_of(w[j])))
 }
 // CGNR reliable update: p += t - z; z = t
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_shift(Segs S, cpx<R>* __restrict__ p, cpx<R>* __restrict__ z,
-                                                     const cpx<R>* __restrict__ t, const int* __restrict__ mask) {
-    const SegPos q = seg_pos(S);
+__global__ __launch_bounds__(kBlock) void k_cg_shift(Segs S, cpx<R>* __restrict__ p_, cpx<R>* __restrict__ z_,
+                                                     const cpx<R>* __restrict__ t_, const int* __restrict__ mask) {
+    LANE_SETUP(R);
     if (!mask[q.seg]) return;
-    cpx<R> tv[kElems], pv[kElems], zv[kElems];
+    T* p = AS(T, p_);
+    T* z = AS(T, z_);
+    const T* t = AS_C(T, t_);
+    T tv[NE], pv[NE], zv[NE];
     SEG_LOOP((tv[j] = t[q.at(j)], pv[j] = p[q.at(j)], zv[j] = z[q.at(j)]),
              (p[q.at(j)] = pv[j] + tv[j] - zv[j], z[q.at(j)] = tv[j]))
 }
 
 // a = 0 on the masked segments (a solve started from a guess whose source column is zero)
 __global__ __launch_bounds__(kBlock) void k_zero_segs(Segs S, cpx<double>* __restrict__ a, const int* __restrict__ mask) {
-    const SegPos q = seg_pos(S);
+    constexpr int NE = kElems;
+    const SegPos<1> q = seg_pos<1>(S);
     if (!mask[q.seg]) return;
     SEG_LOOP((void)0, (a[q.at(j)] = cd(0.0, 0.0)))
 }
@@ -215,7 +333,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int fin, const int* __restr
                                                      const double* __restrict__ partial, ColState* __restrict__ st,
                                                      double* __restrict__ out) {
     const int seg = blockIdx.x;
-    if (fin != FIN_STORE && !st[seg].active) return;
+    if (fin != FIN_STORE && !st[seg].active) {
+        // a stopped column: its last x update (if any) was applied by k_cg_px
+        if (fin == FIN_CG_ALPHA && threadIdx.x == 0) st[seg].xdue = 0;
+        return;
+    }
     double d0 = 0, d1 = 0, d2 = 0;
     const int k0 = p0[seg], k1 = p0[seg + 1];
     for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) {
@@ -293,6 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int fin, const int* __restr
             break;
         }
         case FIN_CG_ALPHA: {
+            s.xdue = 0;  // the previous iteration's update was applied; due again once alpha is known
             if (!(d0 > 0) || !isfinite(d0)) {
                 s.breakdown = isfinite(d0) ? 1 : 2;
                 s.active = 0;
@@ -300,6 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int fin, const int* __restr
             }
             s.alpha_re = s.zz / d0;
             s.alpha_im = 0;
+            s.xdue = 1;
             break;
         }
         case FIN_CG_RR: {
@@ -334,6 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int fin, const int* __restr
 
 
 #undef SEG_LOOP
+#undef LANE_SETUP
+#undef AS
+#undef AS_C
 
 }  // namespace
 
@@ -353,13 +480,12 @@ void launch_bicg_xr(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* r, const cpx<R>
     hipLaunchKernelGGL(k_bicg_xr<R>, sgrid(S), dim3(kBlock), 0, c->stream, S, x, r, p, s, t, rh, partial, st);
 }
 template <typename R>
-void launch_cg_xr(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* r, const cpx<R>* p, const cpx<R>* w,
-                  double* partial, const ColState* st) {
-    hipLaunchKernelGGL(k_cg_xr<R>, sgrid(S), dim3(kBlock), 0, c->stream, S, x, r, p, w, partial, st);
+void launch_cg_r(dd_ctx* c, const Segs& S, cpx<R>* r, const cpx<R>* w, double* partial, const ColState* st) {
+    hipLaunchKernelGGL(k_cg_r<R>, sgrid(S), dim3(kBlock), 0, c->stream, S, r, w, partial, st);
 }
 template <typename R>
-void launch_cg_p(dd_ctx* c, const Segs& S, cpx<R>* p, const cpx<R>* z, const ColState* st) {
-    hipLaunchKernelGGL(k_cg_p<R>, sgrid(S), dim3(kBlock), 0, c->stream, S, p, z, st);
+void launch_cg_px(dd_ctx* c, const Segs& S, cpx<R>* x, cpx<R>* p, const cpx<R>* z, const ColState* st) {
+    hipLaunchKernelGGL(k_cg_px<R>, sgrid(S), dim3(kBlock), 0, c->stream, S, x, p, z, st);
 }
 template <typename R>
 void launch_norm2(dd_ctx* c, const Segs& S, const cpx<R>* a, double* partial) {
@@ -400,9 +526,8 @@ void launch_finalize(dd_ctx* c, int fin, int nseg, const int* p0, const double* 
     template void launch_bicg_s<R>(dd_ctx*, const Segs&, const cpx<R>*, const cpx<R>*, cpx<R>*, const ColState*); \
     template void launch_bicg_xr<R>(dd_ctx*, const Segs&, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*,       \
                                     const cpx<R>*, const cpx<R>*, double*, const ColState*);                   \
-    template void launch_cg_xr<R>(dd_ctx*, const Segs&, cpx<R>*, cpx<R>*, const cpx<R>*, const cpx<R>*, double*, \
-                                  const ColState*);                                                            \
-    template void launch_cg_p<R>(dd_ctx*, const Segs&, cpx<R>*, const cpx<R>*, const ColState*);               \
+    template void launch_cg_r<R>(dd_ctx*, const Segs&, cpx<R>*, const cpx<R>*, double*, const ColState*);       \
+    template void launch_cg_px<R>(dd_ctx*, const Segs&, cpx<R>*, cpx<R>*, const cpx<R>*, const ColState*);     \
     template void launch_norm2<R>(dd_ctx*, const Segs&, const cpx<R>*, double*);                               \
     template void launch_copy_segs<R>(dd_ctx*, const Segs&, const cpx<R>*, cpx<R>*, const ColState*);          \
     template void launch_fold_x<R>(dd_ctx*, const Segs&, cpx<double>*, cpx<R>*, const int*);                   \

@@ -386,11 +386,11 @@ dd_status cgnr_reliable(System& S, const cpx<double>* b, cpx<double>* x, const s
     auto iteration = [&]() {
         S.apply(0, EPI_NORM, pp, wv, (const cpx<R>*)nullptr, partial, st);
         launch_finalize(c, FIN_CG_ALPHA, ns, S.sp0[kind], partial, st, nullptr);
-        launch_cg_xr<R>(c, S.seg, xx, r, pp, wv, partial, st);
+        launch_cg_r<R>(c, S.seg, r, wv, partial, st);
         launch_finalize(c, FIN_CG_RR, ns, S.seg.eb0, partial, st, nullptr);
         S.apply(1, EPI_NORM, r, z, (const cpx<R>*)nullptr, partial, st);
         launch_finalize(c, FIN_CG_BETA, ns, S.sp0[kind], partial, st, nullptr);
-        launch_cg_p<R>(c, S.seg, pp, z, st);
+        launch_cg_px<R>(c, S.seg, xx, pp, z, st);  // x += alpha p (also as a column stops), p = z + beta p
     };
     while (ndone < ns && total < p.max_iter) {
         const int k = std::min(check_every, p.max_iter - total);
@@ -490,6 +490,9 @@ struct SingleSystem : System {
 
 dd_status SegLayout::upload(dd_ctx* c, Slot slot, System* S) {
     const int ns = (int)off.size();
+    // the vector kernels move FP32 fields two complex numbers at a time
+    for (int k = 0; k < ns; k++)
+        if ((off[k] & 1) != 0 || (len[k] & 1) != 0) return fail(c, DD_ERR_ARG, "segments must have even offsets and lengths");
     eb0.assign(ns + 1, 0);
     const int per = kBlock * kElems;  // elements per elementwise workgroup
     for (int k = 0; k < ns; k++) eb0[k + 1] = eb0[k] + (len[k] + per - 1) / per;

@@ -271,6 +271,33 @@ def test_even_odd_matches_full_operator(prec, solver, T, L, bc, dom):
     assert relerr(got[dd.DD_PRECOND_EO], got[dd.DD_PRECOND_NONE]) < 2 * bar
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+def test_cgnr_columns_stopping_inside_a_round_keep_their_last_update(precond):
+    """CGNR adds alpha p to x at the end of an iteration, together with the new search
+    direction; a column whose recursion stops in that iteration must still receive it.
+    One round of inner iterations covers the whole FP64 solve (check_every above the
+    iteration count), Gaussian and point sources stop at different iterations inside it,
+    and every true residual must then meet tol at the single reliable update (a lost
+    update would leave a residual of order alpha |M p| and force further rounds)."""
+    dd = lib()
+    step(f"CGNR stopping columns precond={precond}")
+    T, L, bc, dom, kappa = 16, 6, -1, (4, 8), 0.13
+    U = random_links(T, L, 0.3, 2900)
+    nsite = dom[1] * L ** 3
+    b = gaussian_field(nsite, 12, 2901)
+    b[6:] = 0
+    for j in range(6, 12):
+        b[j, (j * 379) % nsite, j] = 1.0
+    ctx = dd.Context(T, L, bc)
+    p = dd.solver_params(tol=1e-10, prec=dd.DD_FP64, solver=dd.DD_CGNR, check_every=5000, precond=precond)
+    x, st = dd.block_solve(ctx, dd.pack_links(U), kappa, dd.pack_field(b), dom, p)
+    assert st["updates"] == 1 and st["restarts"] == 0, st
+    assert max(st["true_rel_resid"]) <= 1e-10
+    ref, _, _, ost = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=1e-13, method=1)
+    assert ost == 0
+    assert relerr(dd.unpack_field(x), ref) < 1e-8
+
+
 @pytest.mark.parametrize("solver", [0, 1])
 def test_even_odd_launch_shapes_bitwise(solver, tmp_path, monkeypatch):
     """The XCD remap of the half hop only moves work between workgroups, and
