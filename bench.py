@@ -63,9 +63,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection,disconnected,nucleon "
-                    "(all = every part but projection, disconnected and nucleon, which take one to a few "
-                    "minutes a step)")
+    ap.add_argument("--parts", default="all", help="comma list of stencil,solve,fact,overlap,batched,force,projection,disconnected,nucleon,"
+                    "overlap_study (all = every part but projection, disconnected and nucleon, which take one to a "
+                    "few minutes a step; overlap_study runs once, after the timed steps, untimed)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (10 times), the reference that scales "
                          "the profiler's FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -123,7 +123,7 @@ def main():
     from paper_1612_06424_amd.inputs import WORKLOADS, batched_domains, gaussian_field, random_links
 
     parts = set(args.parts.split(",")) if args.parts != "all" else {"stencil", "solve", "fact", "overlap", "batched",
-                                                                     "force"}
+                                                                     "force", "overlap_study"}
     if args.no_batched:
         parts.discard("batched")
     torch.cuda.set_device(0)
@@ -478,9 +478,51 @@ def main():
         out["roofline"]["traffic"] = traffic
         out["roofline"]["traffic_over_algorithmic"] = round(traffic / max(db / max(dn, 1), 1), 3)
     out["parts"] = last
+    if "overlap_study" in parts:
+        out["overlap_study"] = overlap_study(dd, ctx, U64, w, pmx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(T, L, bc, kappa, w)
     print(json.dumps(out), flush=True)
+
+
+def overlap_study(dd, ctx, U64, w, params):
+    """The hierarchy of the factorised pion correlator in the overlap thickness Delta
+    (Sec. 3.2, Eqs. 14-15; the expansion of Sec. 6): on the 64x32^3 lattice, source slab
+    Gamma = [0, 24) and Gamma* = [24, 64), point source at x0 = (4, 0, 0, 0), the
+    factorised correlator C^(i) with Delta = 8, 12, 16 for i = 0, 1, 2, and the exact C.
+    Reported per slice t: C, C^(0), C^(1) - C^(0), C^(2) - C^(1) and C^(rest) = C - C^(2),
+    at kappa = 0.12 and 0.115 on the workload's links.  The workload's own kappa = 0.135
+    lies past the critical value of these smooth links: the propagator does not decay, the
+    factorised correlator exceeds the exact one by orders of magnitude at every Delta and the
+    solves take thousands of iterations (the study there took 108 s), so it stays out.
+    Untimed; mixed-precision solves to the workload's tol."""
+    src = (4, 0, 0, 0)
+    doms = [(0, 24), (24, 40)]
+    deltas = (8, 12, 16)
+    show = [4, 8, 16, 20, 24, 28, 32, 36, 40, 48, 56]
+    res = {"domains": [list(d) for d in doms], "source": list(src), "deltas": list(deltas), "t": show}
+    for kap in (0.12, 0.115):
+        t0 = time.perf_counter()
+        C = {}
+        iters = {}
+        for i, dl in enumerate(deltas):
+            Sf, Se, st = dd.factorized_propagator(ctx, U64, kap, src, doms, params, overlap=dl, exact=(i == 0))
+            C[dl] = dd.pion_correlator(ctx, Sf, src[0])
+            iters[dl] = [s["iters"] for s in st]
+            if Se is not None:
+                C["exact"] = dd.pion_correlator(ctx, Se, src[0])
+            del Sf, Se
+        Ce, C0, C1, C2 = C["exact"], C[8], C[12], C[16]
+        res[f"kappa={kap}"] = {
+            "ms": round((time.perf_counter() - t0) * 1e3, 1),
+            "solve_iters": {str(k): v for k, v in iters.items()},
+            "C": [float(Ce[t]) for t in show],
+            "C0": [float(C0[t]) for t in show],
+            "C1-C0": [float(C1[t] - C0[t]) for t in show],
+            "C2-C1": [float(C2[t] - C1[t]) for t in show],
+            "rest": [float(Ce[t] - C2[t]) for t in show],
+        }
+    return res
 
 
 def stencil_traffic(kernel):
