@@ -41,13 +41,28 @@ namespace dd {
 // the result does not depend on KC.  Column k's output is written only if bit
 // k of live is set (its stores go through a buffer resource of size 0
 // otherwise, which drops them); its sums go to slot + 3 k slot_col.
+// Site of thread tid of spatial tile sb: NT consecutive sites (whole x rows of z
+// planes), or (bricks = true, NT a multiple of L, see brick_rows) a brick of RY x RZ
+// whole x rows in (y, z), so that most y and z neighbours lie inside the tile; a
+// wavefront still reads whole consecutive rows.  Returns L3 for a thread past the end.
+__device__ __forceinline__ int tile_site(int sb, int tid, int NT, int L, int L3, bool bricks, int ry) {
+    if (!bricks) return min(sb * NT + tid, L3);
+    const int rows = NT / L, rz = rows / ry;
+    const int nby = L / ry;
+    const int by = sb % nby, bz = sb / nby;
+    const int r = tid / L, x = tid - r * L;
+    const int y = by * ry + r % ry, z = bz * rz + r / ry;
+    return (z * L + y) * L + x;
+}
+
 template <typename R, int DAG, int EPI, int NT, int KC>
 __device__ __forceinline__ void dslash_tile_cols(const Geo& g, const cpx<R>* __restrict__ U, R mass,
                                                  const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                  const cpx<R>* __restrict__ aux, unsigned live, int sb, int tc,
-                                                 int tc_len, double* __restrict__ slot, size_t slot_col) {
+                                                 int tc_len, double* __restrict__ slot, size_t slot_col,
+                                                 bool bricks = false, int ry = 1) {
     const int L = g.L, L2 = g.L2, L3 = g.L3;
-    const int sp = sb * NT + threadIdx.x;
+    const int sp = tile_site(sb, (int)threadIdx.x, NT, L, L3, bricks, ry);
     const int nsite = g.nsite, nt = g.nt;
     constexpr uint32_t CB = sizeof(cpx<R>);
     const uint32_t cs = (uint32_t)nsite * CB;    // component stride (bytes)

@@ -121,7 +121,7 @@ struct StencilSched {
     int tc = 8;
     int remap = 0;
     int kc = 1;       // columns per thread
-    int blocked = 0;  // even-odd half hop tile flags: bit 0 tiles as 4 x 4 (y, z) bricks of x rows,
+    int blocked = 0;  // tile flags: bit 0 tiles as (y, z) bricks of x rows (even-odd: 4 x 4),
                       // bit 1 the time chunks of a tile in adjacent workgroups, bit 2 non-temporal
                       // output stores (two columns per thread)
 };
@@ -227,6 +227,7 @@ void tune_cache_store(dd_ctx* c, const std::string& key, const StencilSched& sc)
 StencilSched default_sched(const Geo& g);
 int stencil_blocks(const Geo& g, const StencilSched& sc);
 int sched_kc(const StencilSched& sc, int ncol, size_t real_bytes, size_t col_bytes);
+int brick_rows(const Geo& g, int nt);
 template <typename R>
 void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const cpx<R>* U, double kappa,
                          int dag, int epi, const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol,

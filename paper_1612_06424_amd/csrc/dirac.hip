@@ -18,33 +18,39 @@ template <typename R, int DAG, int EPI, int NT, int KC>
 __global__ __launch_bounds__(NT, sweep_waves<R>()) void k_dslash(Geo g, const cpx<R>* __restrict__ U, R mass,
                                                const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                const cpx<R>* __restrict__ aux, int ncol, int tc_len,
-                                               int remap, double* __restrict__ partial,
+                                               int remap, int blocked, double* __restrict__ partial,
                                                const ColState* __restrict__ st) {
     const int lb = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int nsb = (g.L3 + NT - 1) / NT;
     const int ngrp = ncol / KC;
     const int col = (lb % ngrp) * KC;
     const int rest = lb / ngrp;
-    const int sb = rest % nsb, tc = rest / nsb;
+    const int nchunk = gridDim.x / (ngrp * nsb);
+    // tile flag bit 1: the time chunks of one tile in adjacent workgroups (the slices either side
+    // of a chunk, which the neighbouring chunks read too, are still in L2); otherwise the tiles
+    // of one chunk are adjacent
+    const bool chunk_major = (blocked & 2) != 0;
+    const int sb = chunk_major ? rest / nchunk : rest % nsb;
+    const int tc = chunk_major ? rest % nchunk : rest / nsb;
     unsigned live = 0;
 #pragma unroll
     for (int k = 0; k < KC; k++)
         if (st == nullptr || st[col + k].active) live |= 1u << k;
     if (live == 0) return;  // uniform over the workgroup
-    const int nchunk = gridDim.x / (ngrp * nsb);
     const size_t off = (size_t)col * 12 * g.nsite;
     double* slot = partial + ((size_t)col * nsb * nchunk + (size_t)tc * nsb + sb) * 3;
     dslash_tile_cols<R, DAG, EPI, NT, KC>(g, U, mass, in + off, out + off, aux != nullptr ? aux + off : nullptr,
-                                          live, sb, tc, tc_len, slot, (size_t)nsb * nchunk);
+                                          live, sb, tc, tc_len, slot, (size_t)nsb * nchunk, (blocked & 1) != 0,
+                                          blocked >> 8);
 }
 
 template <typename R, int DAG, int NT, int KC>
 void launch_epi(dd_ctx* c, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R mass,
-                const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap,
+                const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap, int blocked,
                 double* partial, const ColState* st) {
 #define DD_EPI_CASE(E)                                                                                               \
     hipLaunchKernelGGL((k_dslash<R, DAG, E, NT, KC>), grid, dim3(NT), 0, c->stream, g, U, mass, in, out, aux, ncol, \
-                       tc, remap, partial, st)
+                       tc, remap, blocked, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EPI_CASE(EPI_STORE); break;
         case EPI_DOT_AUX: DD_EPI_CASE(EPI_DOT_AUX); break;
@@ -58,22 +64,23 @@ void launch_epi(dd_ctx* c, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R 
 
 template <typename R, int DAG, int NT>
 void launch_kc(dd_ctx* c, int kc, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R mass, const cpx<R>* in,
-               cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap, double* partial, const ColState* st) {
+               cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap, int blocked, double* partial,
+               const ColState* st) {
     if (kc == 2) {
-        launch_epi<R, DAG, NT, 2>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+        launch_epi<R, DAG, NT, 2>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
         return;
     }
     if constexpr (sizeof(R) == 4) {
         if (kc == 3) {
-            launch_epi<R, DAG, NT, 3>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+            launch_epi<R, DAG, NT, 3>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
             return;
         }
         if (kc == 4) {
-            launch_epi<R, DAG, NT, 4>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+            launch_epi<R, DAG, NT, 4>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
             return;
         }
     }
-    launch_epi<R, DAG, NT, 1>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, partial, st);
+    launch_epi<R, DAG, NT, 1>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
 }
 
 }  // namespace
@@ -87,6 +94,20 @@ int sched_kc(const StencilSched& sc, int ncol, size_t real_bytes, size_t col_byt
     if (kc <= 1 || kc > (real_bytes == 8 ? 2 : 4) || ncol % kc != 0) return 1;
     if ((size_t)kc * col_bytes >= ((size_t)1 << 32)) return 1;
     return kc;
+}
+
+// y rows of a brick tile of nt sites (whole x rows, ry x nt / (L ry) rows in (y, z)), or 0
+// where bricks do not fit: nt a multiple of L, the rows split as evenly as possible with
+// ry <= 4, and both extents dividing L.
+int brick_rows(const Geo& g, int nt) {
+    const int L = g.L;
+    if (nt % L != 0) return 0;
+    const int rows = nt / L;
+    if (rows < 2) return 0;
+    const int ry = rows >= 16 ? 4 : (rows >= 4 ? (rows >= 8 ? 4 : 2) : rows);
+    const int rz = rows / ry;
+    if (ry * rz != rows || L % ry != 0 || L % rz != 0) return 0;
+    return ry;
 }
 
 StencilSched default_sched(const Geo& g) {
@@ -109,14 +130,18 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
                          double* partial, const ColState* st) {
     const int kc = sched_kc(sc, ncol, sizeof(R), (size_t)12 * g.nsite * sizeof(cpx<R>));
     const dim3 grid((unsigned)stencil_blocks(g, sc) * (unsigned)(ncol / kc));
+    // tile flags as the kernel reads them: bit 0 bricks (with the brick's y rows in bits 8+),
+    // bit 1 chunk-adjacent order
+    const int ry = brick_rows(g, sc.nt);
+    const int blk = ((sc.blocked & 1) && ry > 0 ? 1 | (ry << 8) : 0) | (sc.blocked & 2);
     const R mass = R(epi == EPI_HOP ? kappa : 1.0 / (2.0 * kappa));  // EPI_HOP scales the hop by kappa
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_NT_CASE(NTV)                                                                                         \
     if (dag)                                                                                                    \
-        launch_kc<R, 1, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, partial, st); \
+        launch_kc<R, 1, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, blk, partial, st); \
     else                                                                                                        \
-        launch_kc<R, 0, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, partial, st);
+        launch_kc<R, 0, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, blk, partial, st);
     if (sc.nt == 256) {
         DD_NT_CASE(256)
     } else {

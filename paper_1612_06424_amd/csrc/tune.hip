@@ -1,7 +1,8 @@
 // tune.hip -- per-context autotuner of the stencil launch shape.
 //
-// The best (workgroup size, time-chunk length, XCD remap, columns per thread)
-// depends on the precision, the number of columns and the lattice geometry (how many
+// The best (workgroup size, time-chunk length, XCD remap, columns per thread,
+// tile shape and order) depends on the precision, the number of columns and the
+// lattice geometry (how many
 // workgroups are resident per XCD against how much of the 4 MB L2 one time
 // slice of them touches).  The first launch for a new key times every
 // candidate on scratch buffers of the same size and keeps the fastest; later
@@ -54,14 +55,18 @@ StencilSched tune(dd_ctx* c, const Geo& g, int ncol) {
     for (int kc = 1; kc <= 4; kc++)
     for (int nt : {128, 256})
         for (int tcv : tcs)
-            for (int remap : {0, 1}) {
+            for (int remap : {0, 1})
+            for (int bl = 0; bl < 4; bl++) {
                 StencilSched sc;
                 sc.nt = nt;
                 sc.tc = tcv > g.nt ? g.nt : tcv;
                 sc.remap = remap;
                 sc.kc = kc;
+                sc.blocked = bl;
                 if (tcv != sc.tc && tcv != (1 << 20)) continue;  // same as a shorter candidate
                 if (sched_kc(sc, ncol, sizeof(R), (size_t)12 * g.nsite * sizeof(cpx<R>)) != kc) continue;
+                if ((bl & 1) && brick_rows(g, nt) == 0) continue;          // bricks do not fit
+                if ((bl & 2) && (g.nt + sc.tc - 1) / sc.tc < 2) continue;  // one chunk: the same order
                 for (int w = 0; w < 2; w++)
                     launch_dslash_sched<R>(c, g, sc, U, 0.125, 0, EPI_STORE, in, out, nullptr, ncol, nullptr, nullptr);
                 (void)hipEventRecord(e0, c->stream);

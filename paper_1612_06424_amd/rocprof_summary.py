@@ -8,6 +8,10 @@ DIR holds one rocprofv3 output directory per pass (csv format):
   write/       --pmc WRITE_SIZE  (stencil kernels)
   copy_fetch/  --pmc FETCH_SIZE  of bench.py --copy-calibration
   copy_write/  --pmc WRITE_SIZE  of bench.py --copy-calibration
+  units/       (optional) --pmc of the vector-memory unit counters TA_TA_BUSY_sum,
+               TA_ADDR_STALLED_BY_TC_CYCLES_sum, TCP_TCR_TCP_STALL_CYCLES_sum,
+               TCP_PENDING_STALL_CYCLES_sum, TCP_TOTAL_CACHE_ACCESSES_sum, SQ_INSTS_VMEM_RD,
+               GRBM_GUI_ACTIVE (stencil kernels)
 and writes DIR/summary.md (per-kernel durations, HBM bytes per launch from
 the counters scaled by the copy calibration) and DIR/stencil_traffic.json,
 which bench.py reads to fill roofline.traffic while the stencil sources are
@@ -66,6 +70,49 @@ def counters(d):
     return {k: (len(v[0]), v[1] / max(len(v[0]), 1)) for k, v in agg.items()}
 
 
+def counters_by_name(d):
+    """{kernel: {counter: mean value per dispatch}} of one --pmc pass with several counters."""
+    agg = collections.OrderedDict()
+    for r in _rows(os.path.join(d, "**", "*counter_collection.csv")):
+        k = short_name(r.get("Kernel_Name", "?"))
+        a = agg.setdefault(k, collections.OrderedDict())
+        c = a.setdefault(r.get("Counter_Name", "?"), [set(), 0.0])
+        c[0].add(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        c[1] += float(r.get("Counter_Value") or 0)
+    return {k: {c: v[1] / max(len(v[0]), 1) for c, v in cs.items()} | {"_n": max(len(v[0]) for v in cs.values())}
+            for k, cs in agg.items()}
+
+
+NCU = 256  # MI355X compute units: one texture-address unit (TA) and one vector L1 (TCP) each
+NXCD = 8   # GRBM_GUI_ACTIVE reads the sum over the 8 XCDs (8 x the dispatch's clocks)
+
+
+def units_table(d):
+    """Busy and stall fractions of the vector-memory units per stencil kernel, as shares of
+    NCU x the dispatch's GPU-active clocks (GRBM_GUI_ACTIVE / NXCD)."""
+    u = counters_by_name(os.path.join(d, "units"))
+    if not u:
+        return []
+    out = ["| kernel | launches (pmc) | clocks | TA busy | TA stalled by TC | TCP stalled by TCR | "
+           "TCP pending stall | vector-memory reads / launch | L1 accesses / launch |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(u):
+        c = u[k]
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / NXCD
+        if cyc <= 0:
+            continue
+        den = NCU * cyc
+
+        def frac(name):
+            return f"{c[name] / den:.2f}" if name in c else "-"
+
+        out.append(f"| `{k}` | {c['_n']} | {cyc:.4g} | {frac('TA_TA_BUSY_sum')} | "
+                   f"{frac('TA_ADDR_STALLED_BY_TC_CYCLES_sum')} | {frac('TCP_TCR_TCP_STALL_CYCLES_sum')} | "
+                   f"{frac('TCP_PENDING_STALL_CYCLES_sum')} | {c.get('SQ_INSTS_VMEM_RD', 0):.4g} | "
+                   f"{c.get('TCP_TOTAL_CACHE_ACCESSES_sum', 0):.4g} |")
+    return out
+
+
 def main(argv):
     d = argv[0]
     keep = "--keep-raw" in argv
@@ -121,8 +168,14 @@ def main(argv):
         f.write("Kernel trace (top 25 by total time, warm-up and timed steps together):\n\n")
         f.write("\n".join(lines) + "\n\nHBM traffic of the stencil kernels (counter passes):\n\n")
         f.write("\n".join(tl) + "\n")
+        ut = units_table(d)
+        if ut:
+            f.write("\nVector-memory units of the stencil kernels (counter pass; fractions of "
+                    f"{NCU} units x the dispatch's clocks, GRBM_GUI_ACTIVE / {NXCD}; reads and accesses summed over "
+                    "the GPU):\n\n")
+            f.write("\n".join(ut) + "\n")
     if not keep:
-        for sub in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
+        for sub in ("trace", "fetch", "write", "copy_fetch", "copy_write", "units"):
             for p in glob.glob(os.path.join(d, sub, "**", "*"), recursive=True):
                 if os.path.isfile(p):
                     os.remove(p)

@@ -1,10 +1,11 @@
-"""Several columns per thread in the full Wilson-Dirac stencil (one link load serves KC
-columns; FP32 KC = 1..4, FP64 KC = 1..2).
+"""Launch shapes of the full Wilson-Dirac stencil: several columns per thread (one link
+load serves KC columns; FP32 KC = 1..4, FP64 KC = 1..2), brick tiles and the order of tiles
+and chunks.
 
 The shape is forced through the launch-shape cache (DD_TUNE_CACHE: key
-"kind:ncol:L:T:nt:whole", then workgroup size, chunk length, XCD remap and KC).  Every
-column's arithmetic is that of the one-column kernel in the same order, so the output is
-bitwise that of KC = 1, and within 1e-13 (FP64) / 2e-6 (FP32) of the oracle's D.  Inside
+"kind:ncol:L:T:nt:whole", then workgroup size, chunk length, XCD remap, KC and tile
+flags).  Every site's arithmetic is the same whatever the shape, so the output is bitwise
+the same for all of them, and within 1e-13 (FP64) / 2e-6 (FP32) of the oracle's D.  Inside
 the unpreconditioned solves every epilogue of the stencil runs with columns that stop at
 different iterations sharing workgroups with running ones: the solutions and iteration
 counts must not change with KC either.
@@ -20,12 +21,16 @@ pytestmark = pytest.mark.gpu
 
 CASES = [
     # T, L, bc, dom: whole lattices and slabs (one across the time wrap); L^3 = 216 and 125
-    # leave a ragged tail in the last 256-site tile
+    # leave a ragged tail in the last 256-site tile; L = 8 and 16 take brick tiles
     (16, 4, -1, None),
     (8, 6, -1, None),
     (16, 4, -1, (12, 8)),
     (10, 5, 0, (3, 4)),
+    (8, 8, -1, None),
+    (8, 16, -1, (6, 4)),
 ]
+# workgroup size, chunk length, XCD remap, tile flags (bit 0 bricks, bit 1 chunk-adjacent order)
+SHAPES = [(256, 4, 1, 0), (128, 3, 0, 0), (256, 2, 1, 1), (128, 4, 0, 3), (256, 1, 1, 2)]
 
 
 def _maxrel(a, b):
@@ -44,8 +49,9 @@ def _key(kind, ncol, T, L, dom):
 
 
 @pytest.mark.parametrize("T,L,bc,dom", CASES)
-@pytest.mark.parametrize("nt,tc,remap", [(256, 4, 1), (128, 3, 0)])
-def test_columns_per_thread_vs_oracle(tmp_path, monkeypatch, T, L, bc, dom, nt, tc, remap):
+def test_columns_per_thread_and_tiles_vs_oracle(tmp_path, monkeypatch, T, L, bc, dom):
+    """Every launch shape (columns per thread, workgroup size, chunk length, remap, brick
+    tiles, chunk-adjacent order) gives bitwise the same D psi, within the oracle's bar."""
     dd = lib()
     ncol = 12
     kappa = 0.1287
@@ -53,22 +59,24 @@ def test_columns_per_thread_vs_oracle(tmp_path, monkeypatch, T, L, bc, dom, nt, 
     nsite = (T if dom is None else dom[1]) * L ** 3
     psi = gaussian_field(nsite, ncol, 4101)
     ref = O.apply_dirac(U, kappa, T, L, bc, psi, dom)
-    outs = {}
     for kind, dtype, kcs, tol in ((0, torch.complex128, (1, 2), 1e-13), (1, torch.complex64, (1, 2, 3, 4), 2e-6)):
+        first = None
         for kc in kcs:
-            step(f"stencil KC={kc} kind={kind} T={T} L={L} dom={dom} shape=({nt},{tc},{remap})")
-            _cache(tmp_path, monkeypatch, f"s_{kind}_{kc}.txt", [(_key(kind, ncol, T, L, dom), f"{nt} {tc} {remap} {kc} 0")])
-            ctx = dd.Context(T, L, bc)
-            dd.set_kernel_timing(ctx, True)
-            out = dd.apply_dirac(ctx, dd.pack_links(U, dtype), kappa, dd.pack_field(psi, dtype), dom)
-            torch.cuda.synchronize()
-            names = list(dd.kernel_timing(ctx))
-            want = f"k_dslash<{'double' if kind == 0 else 'float'}, 0, 0, {nt}" + (f", {kc}>" if kc > 1 else ">")
-            assert names == [want], names
-            assert _maxrel(dd.unpack_field(out), ref) < tol
-            outs[(kind, kc)] = out
-    for (kind, kc), out in outs.items():
-        assert torch.equal(out, outs[(kind, 1)]), (kind, kc)
+            for nt, tc, remap, bl in SHAPES:
+                step(f"stencil KC={kc} kind={kind} T={T} L={L} dom={dom} shape=({nt},{tc},{remap},{bl})")
+                _cache(tmp_path, monkeypatch, f"s_{kind}_{kc}_{nt}_{tc}_{remap}_{bl}.txt",
+                       [(_key(kind, ncol, T, L, dom), f"{nt} {tc} {remap} {kc} {bl}")])
+                ctx = dd.Context(T, L, bc)
+                dd.set_kernel_timing(ctx, True)
+                out = dd.apply_dirac(ctx, dd.pack_links(U, dtype), kappa, dd.pack_field(psi, dtype), dom)
+                torch.cuda.synchronize()
+                names = list(dd.kernel_timing(ctx))
+                want = f"k_dslash<{'double' if kind == 0 else 'float'}, 0, 0, {nt}" + (f", {kc}>" if kc > 1 else ">")
+                assert names == [want], names
+                assert _maxrel(dd.unpack_field(out), ref) < tol
+                if first is None:
+                    first = out
+                assert torch.equal(out, first), (kind, kc, nt, tc, remap, bl)
 
 
 @pytest.mark.parametrize("solver", ["bicgstab", "cgnr"])
@@ -89,6 +97,7 @@ def test_unpreconditioned_solves_do_not_depend_on_columns_per_thread(tmp_path, m
         step(f"unpreconditioned {solver} KC fp64={kc64} fp32={kc32}")
         _cache(tmp_path, monkeypatch, f"sol_{kc64}_{kc32}.txt",
                [(_key(0, ncol, T, L, dom), f"256 4 1 {kc64} 0"), (_key(1, ncol, T, L, dom), f"256 4 1 {kc32} 0")])
+        # (the reductions' grouping depends on the tile shape and order, not on KC)
         ctx = dd.Context(T, L, bc)
         p = dd.solver_params(tol=1e-10, prec=dd.DD_MIXED, solver=method, precond=dd.DD_PRECOND_NONE)
         x, st = dd.block_solve(ctx, Ud, kappa, bd, dom, p)
