@@ -516,6 +516,7 @@ dd_status solve_batch_eo(dd_ctx* c, const std::vector<Item>& its, const dd_solve
     S.nelem = (size_t)nhalf;
     S.graph = true;
     S.has32 = mixed;
+    S.pair32 = true;  // FP32 half fields with paired components (dd_eo.h)
     S.rec32 = su3_all;
     S.tmp64 = (cpx<double>*)workspace(c, W_EO_T64, (size_t)nhalf * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;

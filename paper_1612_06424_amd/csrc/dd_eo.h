@@ -34,6 +34,65 @@ __device__ __forceinline__ void bload_spinor_col(rsrc_t f, uint32_t cs, uint32_t
     for (int c = 0; c < 12; c++) p[c] = bload<R>(f, vo, col_off + (uint32_t)c * cs);
 }
 
+// FP32 half fields of the even-odd solves keep their spin-colour components in pairs:
+// the 16-byte unit (c / 2) nh + h of a column holds components c & ~1 and c | 1 of half
+// site h.  FP64 half fields keep [12][nh] (one component is 16 bytes already).  Either
+// way every lane access is 16 bytes; a column is 12 cs bytes (cs = nh sizeof(cpx<R>)).
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+template <typename R>
+__device__ __forceinline__ void hload_spinor(rsrc_t f, uint32_t cs, uint32_t col_off, int h, cpx<R> (&p)[12]) {
+    if constexpr (sizeof(R) == 8) {
+        bload_spinor_col<R>(f, cs, col_off, h, p);
+    } else {
+        const uint32_t vo = (uint32_t)h * 16u;
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            // the whole vector is bit-cast at once (element by element it was lowered to one 4-byte load)
+            const f32x4v v =
+                __builtin_bit_cast(f32x4v, __builtin_amdgcn_raw_buffer_load_b128(f, (int)vo, (int)(col_off + q * 2u * cs), 0));
+            p[2 * q] = cpx<R>{v.x, v.y};
+            p[2 * q + 1] = cpx<R>{v.z, v.w};
+        }
+    }
+}
+// components 2q and 2q + 1 of half site h
+template <typename R>
+__device__ __forceinline__ void hload_pair(rsrc_t f, uint32_t cs, uint32_t col_off, int h, int q, cpx<R>& a,
+                                           cpx<R>& b) {
+    if constexpr (sizeof(R) == 8) {
+        const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(cpx<R>);
+        a = bload<R>(f, vo, col_off + (uint32_t)(2 * q) * cs);
+        b = bload<R>(f, vo, col_off + (uint32_t)(2 * q + 1) * cs);
+    } else {
+        const f32x4v v = __builtin_bit_cast(
+            f32x4v, __builtin_amdgcn_raw_buffer_load_b128(f, (int)((uint32_t)h * 16u), (int)(col_off + (uint32_t)q * 2u * cs), 0));
+        a = cpx<R>{v.x, v.y};
+        b = cpx<R>{v.z, v.w};
+    }
+}
+template <typename R, bool NTS>
+__device__ __forceinline__ void hstore_pair(rsrc_t f, uint32_t cs, uint32_t col_off, int h, int q, cpx<R> a,
+                                            cpx<R> b) {
+    if constexpr (sizeof(R) == 8) {
+        const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(cpx<R>);
+        if constexpr (NTS) {
+            bstore_nt<R>(f, vo, col_off + (uint32_t)(2 * q) * cs, a);
+            bstore_nt<R>(f, vo, col_off + (uint32_t)(2 * q + 1) * cs, b);
+        } else {
+            bstore<R>(f, vo, col_off + (uint32_t)(2 * q) * cs, a);
+            bstore<R>(f, vo, col_off + (uint32_t)(2 * q + 1) * cs, b);
+        }
+    } else {
+        // two 8-byte stores per unit: with one 16-byte store, whose data registers the next
+        // unit's arithmetic overwrites at once, groups of four lanes stored the next unit's
+        // low half on this hardware (found on the 64x32^3 fields; the 8-byte form is exact)
+        // the second half's 8 bytes go into the scalar offset, so the two stores are not fused
+        const uint32_t vo = (uint32_t)h * 16u, so = col_off + (uint32_t)q * 2u * cs;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, a), f, (int)vo, (int)so, NTS ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, b), f, (int)vo, (int)(so + 8u), NTS ? 2 : 0);
+    }
+}
+
 // The nine entries of the link at half-site index sl of one (mu, parity) block.
 template <typename R>
 __device__ __forceinline__ void bload_link(rsrc_t u, uint32_t ls, int sl, cpx<R> (&w)[9]) {
@@ -64,7 +123,8 @@ __device__ __forceinline__ void bload_link_r(rsrc_t u, uint32_t ls, int sl, cpx<
 
 // One spatial hop for KC columns: the link is loaded once and transports the
 // projected neighbour of every column.
-template <typename R, int MU, int SGN, bool BWD, int KC, bool REC>
+// HALF: f is an even-odd half field (paired components in FP32), else a full field.
+template <typename R, int MU, int SGN, bool BWD, int KC, bool REC, bool HALF = false>
 __device__ __forceinline__ void bhop_cols(cpx<R> (&a)[KC][12], rsrc_t f, uint32_t cs, uint32_t fs, int nb, rsrc_t u,
                                           uint32_t ls, int sl) {
     cpx<R> w[9];
@@ -72,13 +132,31 @@ __device__ __forceinline__ void bhop_cols(cpx<R> (&a)[KC][12], rsrc_t f, uint32_
 #pragma unroll
     for (int k = 0; k < KC; k++) {
         cpx<R> p[12];
-        bload_spinor_col<R>(f, cs, (uint32_t)k * fs, nb, p);
+        if constexpr (HALF) hload_spinor<R>(f, cs, (uint32_t)k * fs, nb, p);
+        else bload_spinor_col<R>(f, cs, (uint32_t)k * fs, nb, p);
         cpx<R> h[6];
         project<R, MU, SGN>(p, h);
         cpx<R> t[6];
         transport<R, BWD>(w, h, R(1), t);
         accum<R, MU, SGN>(a[k], t);
     }
+}
+
+// One hop of a half field (one column): a += (1 + SGN gamma_MU) W psi(nb).
+template <typename R, int MU, int SGN, bool BWD>
+__device__ __forceinline__ void bhop_half(cpx<R> (&a)[12], rsrc_t f, uint32_t cs, int nb, rsrc_t u, uint32_t ls,
+                                          int sl) {
+    cpx<R> p[12];
+    hload_spinor<R>(f, cs, 0u, nb, p);
+    cpx<R> h[6];
+    project<R, MU, SGN>(p, h);
+    cpx<R> w[9];
+    const uint32_t vo = (uint32_t)sl * (uint32_t)sizeof(cpx<R>);
+#pragma unroll
+    for (int k = 0; k < 9; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
+    cpx<R> t[6];
+    transport<R, BWD>(w, h, R(1), t);
+    accum<R, MU, SGN>(a, t);
 }
 
 // Workgroup sums of three partial values per column; column k's sums go to
@@ -184,7 +262,7 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
             if (tl < nt && (tl > 0 || g.whole)) {
                 const int tm = tl > 0 ? tl - 1 : nt - 1;
                 cpx<R> p[12];
-                bload_spinor<R>(rf, cs, (tm * L3 + yz * L + xof(tl)) >> 1, p);
+                hload_spinor<R>(rf, cs, 0u, (tm * L3 + yz * L + xof(tl)) >> 1, p);
                 project<R, 0, BW>(p, h);
             }
         };
@@ -221,7 +299,7 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
             const bool endt = (tl == nt - 1);
             if (!endt || g.whole) {
                 cpx<R> p[12];
-                bload_spinor<R>(rf, cs, (endt ? sp : s + L3) >> 1, p);
+                hload_spinor<R>(rf, cs, 0u, (endt ? sp : s + L3) >> 1, p);
                 const R ph = (tg == g.T - 1) ? R(g.bc) : R(1);
                 if (ph != R(0)) {
                     cpx<R> hf[6];
@@ -237,33 +315,37 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
                 if (!endt) project<R, 0, BW>(p, nb2);
             }
             const int dxp = (x == L - 1) ? -(L - 1) : 1, dxm = (x == 0) ? (L - 1) : -1;
-            bhop<R, 1, FW, false>(a, rf, cs, (s + dxp) >> 1, uf[1], ls, h, R(1));
-            bhop<R, 1, BW, true>(a, rf, cs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1, R(1));
-            bhop<R, 2, FW, false>(a, rf, cs, (s + dyp) >> 1, uf[2], ls, h, R(1));
-            bhop<R, 2, BW, true>(a, rf, cs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1, R(1));
-            bhop<R, 3, FW, false>(a, rf, cs, (s + dzp) >> 1, uf[3], ls, h, R(1));
-            bhop<R, 3, BW, true>(a, rf, cs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1, R(1));
+            bhop_half<R, 1, FW, false>(a, rf, cs, (s + dxp) >> 1, uf[1], ls, h);
+            bhop_half<R, 1, BW, true>(a, rf, cs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1);
+            bhop_half<R, 2, FW, false>(a, rf, cs, (s + dyp) >> 1, uf[2], ls, h);
+            bhop_half<R, 2, BW, true>(a, rf, cs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1);
+            bhop_half<R, 3, FW, false>(a, rf, cs, (s + dzp) >> 1, uf[3], ls, h);
+            bhop_half<R, 3, BW, true>(a, rf, cs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1);
 
-            const uint32_t vo = (uint32_t)h * CB;
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                const uint32_t so = (uint32_t)c * cs;
-                const cpx<R> pc = has_self ? bload<R>(rs, vo, so) : mk<R>(0, 0);
-                cpx<R> r = mk<R>(a_self * pc.re + c_hop * a[c].re, a_self * pc.im + c_hop * a[c].im);
-                cpx<R> q = mk<R>(0, 0);
-                if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
-                if (EPI == EPI_RESID) r = q - r;
-                bstore<R>(ro, vo, so, r);
-                if (EPI == EPI_DOT_AUX) {
-                    d0 += (double)q.re * r.re + (double)q.im * r.im;
-                    d1 += (double)q.re * r.im - (double)q.im * r.re;
-                } else if (EPI == EPI_TS) {
-                    d0 += (double)r.re * pc.re + (double)r.im * pc.im;
-                    d1 += (double)r.re * pc.im - (double)r.im * pc.re;
-                    d2 += (double)r.re * r.re + (double)r.im * r.im;
-                } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
-                    d0 += (double)r.re * r.re + (double)r.im * r.im;
+            for (int qq = 0; qq < 6; qq++) {
+                cpx<R> pc2[2] = {mk<R>(0, 0), mk<R>(0, 0)}, q2[2] = {mk<R>(0, 0), mk<R>(0, 0)}, r2[2];
+                if (has_self) hload_pair<R>(rs, cs, 0u, h, qq, pc2[0], pc2[1]);
+                if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) hload_pair<R>(rx, cs, 0u, h, qq, q2[0], q2[1]);
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const int c = 2 * qq + e;
+                    const cpx<R> pc = pc2[e], q = q2[e];
+                    cpx<R> r = mk<R>(a_self * pc.re + c_hop * a[c].re, a_self * pc.im + c_hop * a[c].im);
+                    if (EPI == EPI_RESID) r = q - r;
+                    r2[e] = r;
+                    if (EPI == EPI_DOT_AUX) {
+                        d0 += (double)q.re * r.re + (double)q.im * r.im;
+                        d1 += (double)q.re * r.im - (double)q.im * r.re;
+                    } else if (EPI == EPI_TS) {
+                        d0 += (double)r.re * pc.re + (double)r.im * pc.im;
+                        d1 += (double)r.re * pc.im - (double)r.im * pc.re;
+                        d2 += (double)r.re * r.re + (double)r.im * r.im;
+                    } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
+                        d0 += (double)r.re * r.re + (double)r.im * r.im;
+                    }
                 }
+                hstore_pair<R, false>(ro, cs, 0u, h, qq, r2[0], r2[1]);
             }
             // slice tl + 1 uses cB; slice tl + 2 the half spinor just loaded
 #pragma unroll
@@ -347,7 +429,7 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
 #pragma unroll
                 for (int k = 0; k < KC; k++) {
                     cpx<R> p[12];
-                    bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, (tm * L3 + yz * L + xof(tl)) >> 1, p);
+                    hload_spinor<R>(rf, cs, (uint32_t)k * fs, (tm * L3 + yz * L + xof(tl)) >> 1, p);
                     project<R, 0, BW>(p, h[k]);
                 }
             }
@@ -393,7 +475,7 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
 #pragma unroll
                 for (int k = 0; k < KC; k++) {
                     cpx<R> p[12];
-                    bload_spinor_col<R>(rf, cs, (uint32_t)k * fs, (endt ? sp : s + L3) >> 1, p);
+                    hload_spinor<R>(rf, cs, (uint32_t)k * fs, (endt ? sp : s + L3) >> 1, p);
                     if (k == 0 && ph != R(0)) bload_link_r<R, REC>(uf[0], ls, h, w);
                     if (ph != R(0)) {
                         cpx<R> hf[6];
@@ -406,36 +488,39 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
                 }
             }
             const int dxp = (x == L - 1) ? -(L - 1) : 1, dxm = (x == 0) ? (L - 1) : -1;
-            bhop_cols<R, 1, FW, false, KC, REC>(a, rf, cs, fs, (s + dxp) >> 1, uf[1], ls, h);
-            bhop_cols<R, 1, BW, true, KC, REC>(a, rf, cs, fs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1);
-            bhop_cols<R, 2, FW, false, KC, REC>(a, rf, cs, fs, (s + dyp) >> 1, uf[2], ls, h);
-            bhop_cols<R, 2, BW, true, KC, REC>(a, rf, cs, fs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1);
-            bhop_cols<R, 3, FW, false, KC, REC>(a, rf, cs, fs, (s + dzp) >> 1, uf[3], ls, h);
-            bhop_cols<R, 3, BW, true, KC, REC>(a, rf, cs, fs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1);
+            bhop_cols<R, 1, FW, false, KC, REC, true>(a, rf, cs, fs, (s + dxp) >> 1, uf[1], ls, h);
+            bhop_cols<R, 1, BW, true, KC, REC, true>(a, rf, cs, fs, (s + dxm) >> 1, ub[1], ls, (s + dxm) >> 1);
+            bhop_cols<R, 2, FW, false, KC, REC, true>(a, rf, cs, fs, (s + dyp) >> 1, uf[2], ls, h);
+            bhop_cols<R, 2, BW, true, KC, REC, true>(a, rf, cs, fs, (s + dym) >> 1, ub[2], ls, (s + dym) >> 1);
+            bhop_cols<R, 3, FW, false, KC, REC, true>(a, rf, cs, fs, (s + dzp) >> 1, uf[3], ls, h);
+            bhop_cols<R, 3, BW, true, KC, REC, true>(a, rf, cs, fs, (s + dzm) >> 1, ub[3], ls, (s + dzm) >> 1);
 
-            const uint32_t vo = (uint32_t)h * CB;
 #pragma unroll
             for (int k = 0; k < KC; k++) {
 #pragma unroll
-                for (int c = 0; c < 12; c++) {
-                    const uint32_t so = (uint32_t)k * fs + (uint32_t)c * cs;
-                    const cpx<R> pc = has_self ? bload<R>(rs, vo, so) : mk<R>(0, 0);
-                    cpx<R> r = mk<R>(a_self * pc.re + c_hop * a[k][c].re, a_self * pc.im + c_hop * a[k][c].im);
-                    cpx<R> q = mk<R>(0, 0);
-                    if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) q = bload<R>(rx, vo, so);
-                    if (EPI == EPI_RESID) r = q - r;
-                    if constexpr (NTS) bstore_nt<R>(ro[k], vo, (uint32_t)c * cs, r);
-                    else bstore<R>(ro[k], vo, (uint32_t)c * cs, r);
-                    if (EPI == EPI_DOT_AUX) {
-                        d[k][0] += (double)q.re * r.re + (double)q.im * r.im;
-                        d[k][1] += (double)q.re * r.im - (double)q.im * r.re;
-                    } else if (EPI == EPI_TS) {
-                        d[k][0] += (double)r.re * pc.re + (double)r.im * pc.im;
-                        d[k][1] += (double)r.re * pc.im - (double)r.im * pc.re;
-                        d[k][2] += (double)r.re * r.re + (double)r.im * r.im;
-                    } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
-                        d[k][0] += (double)r.re * r.re + (double)r.im * r.im;
+                for (int qq = 0; qq < 6; qq++) {
+                    cpx<R> pc2[2] = {mk<R>(0, 0), mk<R>(0, 0)}, q2[2] = {mk<R>(0, 0), mk<R>(0, 0)}, r2[2];
+                    if (has_self) hload_pair<R>(rs, cs, (uint32_t)k * fs, h, qq, pc2[0], pc2[1]);
+                    if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) hload_pair<R>(rx, cs, (uint32_t)k * fs, h, qq, q2[0], q2[1]);
+#pragma unroll
+                    for (int e = 0; e < 2; e++) {
+                        const int c = 2 * qq + e;
+                        const cpx<R> pc = pc2[e], q = q2[e];
+                        cpx<R> r = mk<R>(a_self * pc.re + c_hop * a[k][c].re, a_self * pc.im + c_hop * a[k][c].im);
+                        if (EPI == EPI_RESID) r = q - r;
+                        r2[e] = r;
+                        if (EPI == EPI_DOT_AUX) {
+                            d[k][0] += (double)q.re * r.re + (double)q.im * r.im;
+                            d[k][1] += (double)q.re * r.im - (double)q.im * r.re;
+                        } else if (EPI == EPI_TS) {
+                            d[k][0] += (double)r.re * pc.re + (double)r.im * pc.im;
+                            d[k][1] += (double)r.re * pc.im - (double)r.im * pc.re;
+                            d[k][2] += (double)r.re * r.re + (double)r.im * r.im;
+                        } else if (EPI == EPI_RESID || EPI == EPI_NORM) {
+                            d[k][0] += (double)r.re * r.re + (double)r.im * r.im;
+                        }
                     }
+                    hstore_pair<R, NTS>(ro[k], cs, 0u, h, qq, r2[0], r2[1]);
                 }
             }
             // slice tl + 1 uses cB; slice tl + 2 the half spinors just loaded

@@ -10,8 +10,9 @@
 //     rebuilt from the unitarity of SU(3)) are loaded once into registers and
 //     serve every column of the group;
 //   * per column the input half field of the brick's rows and of the one-row
-//     halo around it in y and z is staged in LDS with 16-byte loads of two
-//     neighbouring sites; halo sites are stored already spin-projected (the one
+//     halo around it in y and z is staged in LDS (each thread two neighbouring
+//     sites, 16-byte loads of component pairs); halo sites are stored already
+//     spin-projected (the one
 //     hop that reads each needs one projection), so each input site is fetched
 //     from memory about twice per launch instead of once per neighbour;
 //   * the spatial hops read LDS, the two time hops read the thread's own site
@@ -38,27 +39,6 @@ struct LdsTile<8> {
 };
 
 constexpr int kLdsNT = 256;
-
-// Two neighbouring complex entries (sites k and k + 1 of one component) in one
-// 16-byte load (FP32) or two (FP64).
-template <typename R>
-__device__ __forceinline__ void bload_two(rsrc_t f, uint32_t voff, uint32_t soff, cpx<R>& a, cpx<R>& b);
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-template <>
-__device__ __forceinline__ void bload_two<float>(rsrc_t f, uint32_t voff, uint32_t soff, cpx<float>& a,
-                                                 cpx<float>& b) {
-    // the whole 16-byte vector is bit-cast at once (bit-casting its elements one by one
-    // was lowered to a single 4-byte load by this compiler)
-    const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(f, (int)voff, (int)soff, 0));
-    a = cpx<float>{v.x, v.y};
-    b = cpx<float>{v.z, v.w};
-}
-template <>
-__device__ __forceinline__ void bload_two<double>(rsrc_t f, uint32_t voff, uint32_t soff, cpx<double>& a,
-                                                  cpx<double>& b) {
-    a = bload<double>(f, voff, soff);
-    b = bload<double>(f, voff + (uint32_t)sizeof(cpx<double>), soff);
-}
 
 // The first two rows of a link (six entries); the third is rebuilt where the link is used.
 template <typename R>
@@ -167,7 +147,7 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
     const bool stage = NPAIR == kLdsNT || tid < NPAIR;
     const int row = tid / (LH / 2), j = tid - row * (LH / 2);
     int face = -1, hr = 0;
-    uint32_t svo;
+    int sh0;  // the first of the unit's two half sites
     {
         int yy, zz;
         if (row < NR) {
@@ -196,7 +176,7 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
             zz = zz < 0 ? zz + L : (zz >= L ? zz - L : zz);
         }
         const int base = (tl * L3 + (zz * L + yy) * L) >> 1;  // half-site index of the row's pair 0
-        svo = (uint32_t)(base + 2 * j) * CB;
+        sh0 = base + 2 * j;
     }
 
     // Columns are software-pipelined: the loads of the next live column are issued
@@ -211,12 +191,12 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
     auto issue = [&](int col) {
         const rsrc_t rf = make_rsrc(in + (size_t)col * 12 * (size_t)nh, fs);
         if (stage) {
-#pragma unroll
-            for (int c = 0; c < 12; c++) bload_two<R>(rf, svo, (uint32_t)c * cs, pa[c], pc[c]);
+            hload_spinor<R>(rf, cs, 0u, sh0, pa);
+            hload_spinor<R>(rf, cs, 0u, sh0 + 1, pc);
         }
         // the thread's own site on the slices either side: always in range, unused where the hop is dropped
-        bload_spinor<R>(rf, cs, hb, pb);
-        bload_spinor<R>(rf, cs, hf, pf);
+        hload_spinor<R>(rf, cs, 0u, hb, pb);
+        hload_spinor<R>(rf, cs, 0u, hf, pf);
     };
     int col = next_live(col_lo);
     if (col < col_hi) issue(col);
@@ -259,13 +239,11 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
         // order, so waiting for them then does not wait for the prefetch
         const rsrc_t rs = make_rsrc(self != nullptr ? self + coff : in + coff, fs);
         const rsrc_t rx = make_rsrc(aux != nullptr ? aux + coff : in + coff, fs);
-        const uint32_t vo = (uint32_t)h * CB;
         cpx<R> sv[12], xv[12];
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            sv[c] = has_self ? bload<R>(rs, vo, (uint32_t)c * cs) : mk<R>(0, 0);
-            xv[c] = (EPI == EPI_RESID || EPI == EPI_DOT_AUX) ? bload<R>(rx, vo, (uint32_t)c * cs) : mk<R>(0, 0);
-        }
+        for (int c = 0; c < 12; c++) sv[c] = xv[c] = mk<R>(0, 0);
+        if (has_self) hload_spinor<R>(rs, cs, 0u, h, sv);
+        if (EPI == EPI_RESID || EPI == EPI_DOT_AUX) hload_spinor<R>(rx, cs, 0u, h, xv);
         const int nxt = next_live(col + 1);
         if (nxt < col_hi) issue(nxt);
 
@@ -330,15 +308,14 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
         // epilogue: out = a_self self + c_hop a (or aux - that), fused partial sums
         const rsrc_t ro = make_rsrc(out + coff, fs);
         double d0 = 0, d1 = 0, d2 = 0;
+        cpx<R> ov[12];
 #pragma unroll
         for (int c = 0; c < 12; c++) {
-            const uint32_t so = (uint32_t)c * cs;
             const cpx<R> sc = sv[c];
             cpx<R> v = mk<R>(a_self * sc.re + c_hop * a[c].re, a_self * sc.im + c_hop * a[c].im);
             const cpx<R> qv = xv[c];
             if (EPI == EPI_RESID) v = qv - v;
-            if constexpr (NTS) bstore_nt<R>(ro, vo, so, v);
-            else bstore<R>(ro, vo, so, v);
+            ov[c] = v;
             if (EPI == EPI_DOT_AUX) {
                 d0 += (double)qv.re * v.re + (double)qv.im * v.im;
                 d1 += (double)qv.re * v.im - (double)qv.im * v.re;
@@ -350,6 +327,8 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
                 d0 += (double)v.re * v.re + (double)v.im * v.im;
             }
         }
+#pragma unroll
+        for (int qq = 0; qq < 6; qq++) hstore_pair<R, NTS>(ro, cs, 0u, h, qq, ov[2 * qq], ov[2 * qq + 1]);
         if (EPI != EPI_STORE) block_sum3<kLdsNT>(d0, d1, d2, partial + ((size_t)col * nblk + blk) * 3);
         __syncthreads();  // the next column's staging overwrites the tile (and the sums' scratch)
         col = nxt;

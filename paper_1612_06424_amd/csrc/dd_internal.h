@@ -244,6 +244,7 @@ struct Segs {
     const int* eb0;        // [nseg + 1] first elementwise workgroup of each segment
     const int* eseg;       // [neb] segment of each elementwise workgroup
     int nseg, neb;
+    int paired;            // FP32 vectors are even-odd half fields with paired components (dd_eo.h)
 };
 
 // Vector kernels of the Krylov solvers over segments; reductions write one
@@ -304,6 +305,7 @@ struct System {
     size_t nslots = 0;                     // partial slots needed by any launch
     bool graph = false;                    // replay the inner iterations from a captured HIP graph
     bool has32 = false;                    // FP32 stencil available (links converted)
+    bool pair32 = false;                   // FP32 vectors are half fields with paired components
     const double* ref_norm2 = nullptr;     // host [nseg]: |.|^2 that residuals are relative to (default |b|^2)
     virtual ~System() {}
     virtual void apply64(int dag, int epi, const cpx<double>* in, cpx<double>* out, const cpx<double>* aux,

@@ -551,6 +551,7 @@ dd_status solve_eo(dd_ctx* c, const cpx<double>* U, double kappa, const Geo& g, 
     if (e != DD_OK) return e;
     hipLaunchKernelGGL(k_links_eo<double>, dim3(glink), dim3(kBlock), 0, c->stream, g, U, Ueo64);
     EOSystem S;
+    S.pair32 = true;  // FP32 half fields with paired components (dd_eo.h)
     S.c = c;
     S.g = g;
     S.U64 = Ueo64;

@@ -4,8 +4,7 @@
 // lattice, or every column of every domain of a batch.  Segments are laid out
 // back to back in each work vector and may differ in length; every elementwise
 // workgroup covers kBlock * kElems consecutive elements of one segment (each
-// thread kElems of them in 16-byte units kBlock apart, so every load is
-// coalesced), found
+// thread kElems of them, kBlock apart, so every load is coalesced), found
 // through a workgroup -> segment table (Segs).  Columns whose ColState is inactive skip
 // their work; the reliable-update helpers are selected by a per-segment mask.
 //
@@ -28,70 +27,34 @@ __device__ inline cpx<R> scal(const double re, const double im, cpx<R> a) {
     return {R(re) * a.re - R(im) * a.im, R(re) * a.im + R(im) * a.re};
 }
 
-// The unit a lane moves per access: one complex number in FP64 (16 bytes), two
-// consecutive ones in FP32 (16 bytes as well, so that a wavefront issues as few
-// address requests for FP32 vectors as for FP64 ones).  Segments start at even
-// elements and have even lengths (multiples of 12), so the pairs never straddle
-// two segments.
+// The unit a lane moves per access: one complex number (16 bytes in FP64, 8 in FP32).
+// (Two FP32 complex numbers per 16-byte access halve the address requests, but a 16-byte
+// FP32 store whose data registers the next arithmetic overwrites at once was seen to
+// store the next value for some lanes on this hardware, so FP32 keeps 8-byte units.)
 template <typename R>
 struct Lane {
     using T = cpx<R>;
     static constexpr int P = 1;
 };
-struct alignas(16) c2f {
-    cpx<float> a, b;
-};
-template <>
-struct Lane<float> {
-    using T = c2f;
-    static constexpr int P = 2;
-};
-struct alignas(16) c2d {
-    cpx<double> a, b;
-};
-template <typename R>
-struct Wide {  // the FP64 counterpart of one lane unit of R
-    using T = cpx<double>;
-};
-template <>
-struct Wide<float> {
-    using T = c2d;
-};
-
-__device__ inline c2f operator+(c2f x, c2f y) { return {x.a + y.a, x.b + y.b}; }
-__device__ inline c2f operator-(c2f x, c2f y) { return {x.a - y.a, x.b - y.b}; }
-__device__ inline c2f operator*(float s, c2f x) { return {s * x.a, s * x.b}; }
-__device__ inline c2f scal(const double re, const double im, c2f x) { return {scal(re, im, x.a), scal(re, im, x.b)}; }
 template <typename R>
 __device__ inline cpx<R> zero_of(cpx<R>) { return {R(0), R(0)}; }
-__device__ inline c2f zero_of(c2f) { return {{0.f, 0.f}, {0.f, 0.f}}; }
-// sums of conj(h) r (re, im) and |r|^2 over the complex numbers of a unit
+// sums of conj(h) r (re, im) and |r|^2
 template <typename R>
 __device__ inline void dot_acc(double& d0, double& d1, cpx<R> h, cpx<R> r) {
     d0 += (double)h.re * r.re + (double)h.im * r.im;
     d1 += (double)h.re * r.im - (double)h.im * r.re;
 }
-__device__ inline void dot_acc(double& d0, double& d1, c2f h, c2f r) {
-    dot_acc(d0, d1, h.a, r.a);
-    dot_acc(d0, d1, h.b, r.b);
-}
 template <typename R>
 __device__ inline void norm_acc(double& d, cpx<R> r) {
     d += (double)r.re * r.re + (double)r.im * r.im;
 }
-__device__ inline void norm_acc(double& d, c2f r) {
-    norm_acc(d, r.a);
-    norm_acc(d, r.b);
-}
 // FP64 <-> Krylov precision
 template <typename R>
 __device__ inline cpx<R> narrow(cpx<double> v) { return {(R)v.re, (R)v.im}; }
-__device__ inline c2f narrow2(c2d v) { return {narrow<float>(v.a), narrow<float>(v.b)}; }
 __device__ inline cpx<double> widen_add(cpx<double> x, cpx<double> e) { return {x.re + e.re, x.im + e.im}; }
 __device__ inline cpx<double> widen_add(cpx<double> x, cpx<float> e) {
     return {x.re + (double)e.re, x.im + (double)e.im};
 }
-__device__ inline c2d widen_add(c2d x, c2f e) { return {widen_add(x.a, e.a), widen_add(x.b, e.b)}; }
 
 // This workgroup's segment, and the first of this thread's units (unit j of the
 // thread is k + j * kBlock); P complex numbers per unit.
@@ -264,32 +227,36 @@ __global__ __launch_bounds__(kBlock) void k_copy_segs(Segs S, const cpx<R>* __re
 // Reliable-update helpers (segments selected by mask[seg] != 0):
 //   x64 += xk; xk = 0        (xk in the Krylov precision)
 //   rk = (Rk) r64            (replace the recursive residual by the true one)
+// FP64 fields are [12][n] per segment; FP32 ones the same, or (S.paired) even-odd half
+// fields with paired components, whose element 2 (q n + h) + e is component 2q + e of
+// site h (n = len / 12 sites).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_fold_x(Segs S, cpx<double>* __restrict__ x_, cpx<R>* __restrict__ xk_,
+__device__ inline size_t wide_index(const Segs& S, const SegPos<1>& q, int j) {
+    const int u = q.i0 + j * kBlock;  // element within the segment
+    if (sizeof(R) == 8 || !S.paired) return q.at(j);  // FP64 half fields are not paired
+    const int n = S.len[q.seg] / 12;
+    const int pu = u >> 1, e = u & 1;
+    const int qq = pu / n, h = pu - qq * n;
+    return (size_t)S.off[q.seg] + (size_t)(2 * qq + e) * n + h;
+}
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fold_x(Segs S, cpx<double>* __restrict__ x, cpx<R>* __restrict__ xk,
                                                    const int* __restrict__ mask) {
     LANE_SETUP(R);
     if (!mask[q.seg]) return;
-    using W = typename Wide<R>::T;
-    W* x = AS(W, x_);
-    T* xk = AS(T, xk_);
     T e[NE];
-    W v[NE];
-    SEG_LOOP((e[j] = xk[q.at(j)], v[j] = x[q.at(j)]), (x[q.at(j)] = widen_add(v[j], e[j]), xk[q.at(j)] = zero_of(e[j])))
+    cpx<double> v[NE];
+    size_t w[NE];
+    SEG_LOOP((e[j] = xk[q.at(j)], w[j] = wide_index<R>(S, q, j), v[j] = x[w[j]]),
+             (x[w[j]] = widen_add(v[j], e[j]), xk[q.at(j)] = zero_of(e[j])))
 }
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_set_resid(Segs S, const cpx<double>* __restrict__ r64_,
-                                                      cpx<R>* __restrict__ rk_, const int* __restrict__ mask) {
+__global__ __launch_bounds__(kBlock) void k_set_resid(Segs S, const cpx<double>* __restrict__ r64,
+                                                      cpx<R>* __restrict__ rk, const int* __restrict__ mask) {
     LANE_SETUP(R);
     if (!mask[q.seg]) return;
-    using W = typename Wide<R>::T;
-    const W* r64 = AS_C(W, r64_);
-    T* rk = AS(T, rk_);
-    W v[NE];
-    if constexpr (Lane<R>::P == 2) {
-        SEG_LOOP((v[j] = r64[q.at(j)]), (rk[q.at(j)] = narrow2(v[j])))
-    } else {
-        SEG_LOOP((v[j] = r64[q.at(j)]), (rk[q.at(j)] = narrow<R>(v[j])))
-    }
+    cpx<double> v[NE];
+    SEG_LOOP((v[j] = r64[wide_index<R>(S, q, j)]), (rk[q.at(j)] = narrow<R>(v[j])))
 }
 // BiCGStab restart (mask == 2): fresh shadow residual r^ = r, directions cleared
 template <typename R>

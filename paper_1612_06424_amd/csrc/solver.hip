@@ -490,7 +490,7 @@ struct SingleSystem : System {
 
 dd_status SegLayout::upload(dd_ctx* c, Slot slot, System* S) {
     const int ns = (int)off.size();
-    // the vector kernels move FP32 fields two complex numbers at a time
+    // FP32 half fields pair their components (dd_eo.h), which segments must not split
     for (int k = 0; k < ns; k++)
         if ((off[k] & 1) != 0 || (len[k] & 1) != 0) return fail(c, DD_ERR_ARG, "segments must have even offsets and lengths");
     eb0.assign(ns + 1, 0);
@@ -525,6 +525,7 @@ dd_status SegLayout::upload(dd_ctx* c, Slot slot, System* S) {
     S->seg.eseg = ip + ns + 3 * (ns + 1);
     S->seg.nseg = ns;
     S->seg.neb = neb;
+    S->seg.paired = S->pair32 ? 1 : 0;
     S->nseg = ns;
     S->nslots = std::max(S->nslots, (size_t)neb);
     S->nslots = std::max(S->nslots, (size_t)sp0[0][ns]);
