@@ -104,14 +104,32 @@ __device__ __forceinline__ void bload_link(rsrc_t u, uint32_t ls, int sl, cpx<R>
 // The same link from its first two rows (REC: links stored as 12 reals).  An
 // SU(3) matrix is unitary with unit determinant, so its third row is the
 // complex conjugate of the cross product of the first two.
+// FP32 two-row links pair their entries as the FP32 half fields do: Ueo12[mu][k / 2]
+// [parity][nsite / 2][k & 1], so that the 16-byte unit (mu, kp, parity, h) holds entries
+// 2 kp and 2 kp + 1; the resource of one (mu, parity) block starts at unit (6 mu + parity)
+// nh (rec_link_base) and a row of units is 2 ls bytes apart (ls = 2 nh sizeof(cpx<float>)).
+__device__ __forceinline__ size_t rec_link_base(int mu, int parity, int nh) {
+    return ((size_t)(6 * mu + parity) * (size_t)nh) * 2;  // in cpx<float>
+}
 template <typename R, bool REC>
 __device__ __forceinline__ void bload_link_r(rsrc_t u, uint32_t ls, int sl, cpx<R> (&w)[9]) {
     if constexpr (!REC) {
         bload_link<R>(u, ls, sl, w);
     } else {
-        const uint32_t vo = (uint32_t)sl * (uint32_t)sizeof(cpx<R>);
+        if constexpr (sizeof(R) == 4) {
+            const uint32_t vo = (uint32_t)sl * 16u;
 #pragma unroll
-        for (int k = 0; k < 6; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
+            for (int kp = 0; kp < 3; kp++) {
+                const f32x4v v = __builtin_bit_cast(
+                    f32x4v, __builtin_amdgcn_raw_buffer_load_b128(u, (int)vo, (int)((uint32_t)kp * 2u * ls), 0));
+                w[2 * kp] = cpx<R>{v.x, v.y};
+                w[2 * kp + 1] = cpx<R>{v.z, v.w};
+            }
+        } else {
+            const uint32_t vo = (uint32_t)sl * (uint32_t)sizeof(cpx<R>);
+#pragma unroll
+            for (int k = 0; k < 6; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
+        }
         const cpx<R> c6 = w[1] * w[5] - w[2] * w[4];
         const cpx<R> c7 = w[2] * w[3] - w[0] * w[5];
         const cpx<R> c8 = w[0] * w[4] - w[1] * w[3];
@@ -365,7 +383,8 @@ __device__ __forceinline__ void eo_sweep_tile(const Geo& g, const cpx<R>* __rest
 // written only if bit k of live is set (a stopped column keeps its vectors):
 // its stores go through a buffer resource of size 0 otherwise, which drops
 // them without a branch.  REC: Ueo holds only the first two rows of every link
-// (Ueo12[mu][k < 6][parity][nsite / 2]) and the third is rebuilt (bload_link_r).
+// (Ueo12, in FP32 with its entries paired, see rec_link_base) and the third is
+// rebuilt (bload_link_r).
 // NTS: the output stores are non-temporal.
 template <typename R, int DAG, int EPI, int NT, bool SELF, int KC, bool REC, bool NTS = false>
 __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __restrict__ Ueo, R a_self, R c_hop,
@@ -381,7 +400,8 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
     const uint32_t fs = 12u * cs;  // column stride (bytes)
     const uint32_t ls = 2u * (uint32_t)nh * CB;
     constexpr int NROW = REC ? 6 : 9;  // stored rows of a link
-    const uint32_t ubytes = (uint32_t)(2 * NROW - 1) * (uint32_t)nh * CB;
+    constexpr bool PAIRED_LINKS = REC && sizeof(R) == 4;  // two-row FP32 links in 16-byte units
+    const uint32_t ubytes = PAIRED_LINKS ? 5u * (uint32_t)nh * 16u : (uint32_t)(2 * NROW - 1) * (uint32_t)nh * CB;
     constexpr int FW = DAG ? +1 : -1;
     constexpr int BW = -FW;
     constexpr bool has_self = SELF || EPI == EPI_TS;
@@ -410,8 +430,10 @@ __device__ __forceinline__ void eo_sweep_cols(const Geo& g, const cpx<R>* __rest
         rsrc_t uf[4], ub[4];
 #pragma unroll
         for (int mu = 0; mu < 4; mu++) {
-            uf[mu] = make_rsrc(Ueo + (size_t)(mu * 2 * NROW + p_out) * nh, ubytes);
-            ub[mu] = make_rsrc(Ueo + (size_t)(mu * 2 * NROW + 1 - p_out) * nh, ubytes);
+            uf[mu] = make_rsrc(Ueo + (PAIRED_LINKS ? rec_link_base(mu, p_out, nh) : (size_t)(mu * 2 * NROW + p_out) * nh),
+                               ubytes);
+            ub[mu] = make_rsrc(
+                Ueo + (PAIRED_LINKS ? rec_link_base(mu, 1 - p_out, nh) : (size_t)(mu * 2 * NROW + 1 - p_out) * nh), ubytes);
         }
         const int dyp = (y == L - 1) ? -(L - 1) * L : L, dym = (y == 0) ? (L - 1) * L : -L;
         const int dzp = (z == L - 1) ? -(L - 1) * L2 : L2, dzm = (z == 0) ? (L - 1) * L2 : -L2;

@@ -41,11 +41,13 @@ struct LdsTile<8> {
 constexpr int kLdsNT = 256;
 
 // The first two rows of a link (six entries); the third is rebuilt where the link is used.
+// (FP32: the paired layout of dd_eo.h, rows of units 2 ls bytes apart.)
 template <typename R>
 __device__ __forceinline__ void bload_link6(rsrc_t u, uint32_t ls, int sl, cpx<R> (&w)[6]) {
-    const uint32_t vo = (uint32_t)sl * (uint32_t)sizeof(cpx<R>);
+    cpx<R> w9[9];
+    bload_link_r<R, true>(u, ls, sl, w9);
 #pragma unroll
-    for (int k = 0; k < 6; k++) w[k] = bload<R>(u, vo, (uint32_t)k * ls);
+    for (int k = 0; k < 6; k++) w[k] = w9[k];
 }
 template <typename R>
 __device__ __forceinline__ void link_full(const cpx<R> (&w6)[6], cpx<R> (&w)[9]) {
@@ -93,7 +95,7 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
     const uint32_t cs = (uint32_t)nh * CB;         // component stride
     const uint32_t fs = 12u * cs;                  // column stride
     const uint32_t ls = 2u * (uint32_t)nh * CB;    // link-row stride (both parities)
-    const uint32_t ubytes = 11u * (uint32_t)nh * CB;
+    const uint32_t ubytes = sizeof(R) == 4 ? 5u * (uint32_t)nh * 16u : 11u * (uint32_t)nh * CB;
     constexpr int FW = DAG ? +1 : -1;  // forward hop projector (1 + FW gamma)
     constexpr int BW = -FW;
     constexpr bool has_self = SELF || EPI == EPI_TS;
@@ -136,8 +138,10 @@ __device__ __forceinline__ void eo_lds_body(const Geo& g, const cpx<R>* __restri
         const int hbk[4] = {hb, (s + dxm) >> 1, (s + dym) >> 1, (s + dzm) >> 1};
 #pragma unroll
         for (int mu = 0; mu < 4; mu++) {
-            bload_link6<R>(make_rsrc(U12 + (size_t)(mu * 12 + p_out) * nh, ubytes), ls, h, wf[mu]);
-            bload_link6<R>(make_rsrc(U12 + (size_t)(mu * 12 + 1 - p_out) * nh, ubytes), ls, hbk[mu], wb[mu]);
+            const size_t bf = sizeof(R) == 4 ? rec_link_base(mu, p_out, nh) : (size_t)(mu * 12 + p_out) * nh;
+            const size_t bb = sizeof(R) == 4 ? rec_link_base(mu, 1 - p_out, nh) : (size_t)(mu * 12 + 1 - p_out) * nh;
+            bload_link6<R>(make_rsrc(U12 + bf, ubytes), ls, h, wf[mu]);
+            bload_link6<R>(make_rsrc(U12 + bb, ubytes), ls, hbk[mu], wb[mu]);
         }
     }
 

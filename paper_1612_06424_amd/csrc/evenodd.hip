@@ -142,7 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_links_eo(Geo g, const cpx<double>* _
     }
 }
 
-// Ueo12[mu][k][parity][nsite / 2], k < 6: rows 0 and 1 of every link in FP32;
+// Ueo12[mu][k / 2][parity][nsite / 2][k & 1], k < 6: rows 0 and 1 of every link in FP32,
+// entries paired in 16-byte units (dd_eo.h, rec_link_base);
 // dev[block] = the largest difference (FP64, max norm) between a link's third
 // row and the conjugated cross product of its first two, over the block's
 // sites (NaN if any entry is not finite)
@@ -161,7 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_links_eo12(Geo g, const cpx<double>*
             cpx<double> w[9];
             for (int k = 0; k < 9; k++) w[k] = U[(size_t)(mu * 9 + k) * g.vlink + sl];
             for (int k = 0; k < 6; k++)
-                Ueo[((size_t)(mu * 6 + k) * 2 + par) * nh + (size_t)(s >> 1)] = cpx<float>{(float)w[k].re, (float)w[k].im};
+                Ueo[((((size_t)(mu * 3 + k / 2) * 2 + par) * nh + (size_t)(s >> 1)) << 1) + (k & 1)] =
+                    cpx<float>{(float)w[k].re, (float)w[k].im};
             const cpx<double> c[3] = {w[1] * w[5] - w[2] * w[4], w[2] * w[3] - w[0] * w[5], w[0] * w[4] - w[1] * w[3]};
             for (int k = 0; k < 3; k++) {
                 d = worse(d, fabs(w[6 + k].re - c[k].re));
