@@ -5,7 +5,8 @@
 Calls only the CPU oracle (oracle/) and the seeded input generators
 (paper_1612_06424_amd/inputs.py); nothing here touches the HIP library.  For
 each workload it solves the point-source columns with the oracle's FP64
-BiCGStab (CGNR where BiCGStab stalls) to a true relative residual of 1e-13 and
+BiCGStab (CGNR where BiCGStab stalls) to a true relative residual of 1e-13
+(64x32^3: CGNR to 1e-12) and
 stores, per source column j (the slabs taken from the one that holds the source),
   C_j(t) = sum_xvec sum_c |S_cj((t_src + t) mod T, xvec)|^2   (Eq. 4, W_Pc, one column)
 for the exact propagator D^-1 eta (whole lattice) and for the factorised one of
@@ -46,8 +47,11 @@ from paper_1612_06424_amd.inputs import WORKLOADS, point_sources, random_links  
 TOL = 1e-13
 PLAN = {
     "32x16^3": dict(file="golden_32x16.json", columns=list(range(12)), sources=[0, 1, 2, 3], nsample=16,
-                    sample_seed=3002),
-    "64x32^3": dict(file="golden_64x32.json", columns=[0, 7], sources=[0], nsample=24, sample_seed=3003),
+                    sample_seed=3002, method=0, tol=TOL),
+    # BiCGStab stalls short of 1e-13 on this near-critical lattice; CGNR to 1e-12 converges
+    # monotonically (exact solve plus the slab chain: about 45 minutes a column on 6 threads)
+    "64x32^3": dict(file="golden_64x32.json", columns=[0, 7], sources=[0], nsample=24, sample_seed=3003,
+                    method=1, tol=1e-12),
 }
 
 
@@ -55,12 +59,12 @@ def log(msg):
     print(f"[golden {time.strftime('%H:%M:%S')}] {msg}", flush=True)
 
 
-def solve_checked(U, kappa, T, L, bc, b, dom):
-    x, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=TOL, method=0)
-    if st != 0 or max(rr) > TOL:
+def solve_checked(U, kappa, T, L, bc, b, dom, method=0, tol=TOL):
+    x, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=tol, method=method)
+    if method == 0 and (st != 0 or max(rr) > tol):
         log(f"  BiCGStab status {st} relres {max(rr):.2e}; CGNR instead")
-        x, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=TOL, method=1)
-    if st != 0 or max(rr) > TOL:
+        x, it, rr, st = O.solve(U, kappa, T, L, bc, b, dom=dom, tol=tol, method=1)
+    if st != 0 or max(rr) > tol:
         raise RuntimeError(f"oracle solve failed: status {st}, relres {max(rr):.3e}")
     return x, it, rr
 
@@ -78,8 +82,10 @@ def run(name):
     U = random_links(T, L, w["eps"], w["link_seed"])
     rng = np.random.default_rng(plan["sample_seed"])
     sites = sorted(int(s) for s in rng.choice(V, size=plan["nsample"], replace=False))
+    method, tol = plan["method"], plan["tol"]
     out = dict(workload=name, T=T, L=L, bc=bc, kappa=kappa, eps=w["eps"], link_seed=w["link_seed"],
-               domains=w["domains"], overlap=0, oracle_tol=TOL, solver="oracle BiCGStab (CGNR fallback)",
+               domains=w["domains"], overlap=0, oracle_tol=tol,
+               solver="oracle BiCGStab (CGNR fallback)" if method == 0 else "oracle CGNR",
                sample_sites=sites, sources=[])
     for si in plan["sources"]:
         src = w["sources"][si]
@@ -91,10 +97,11 @@ def run(name):
         for j in plan["columns"]:
             t0 = time.time()
             eta = np.ascontiguousarray(eta_all[j:j + 1])
-            Se, it_e, rr_e = solve_checked(U, kappa, T, L, bc, eta, None)
-            Sf, info = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=TOL, eta=eta)
+            Se, it_e, rr_e = solve_checked(U, kappa, T, L, bc, eta, None, method, tol)
+            log(f"{name} source {si} column {j}: exact solve {it_e[0]} iters, {time.time() - t0:.0f} s")
+            Sf, info = O.factorized_propagator(U, kappa, T, L, bc, src, doms, tol=tol, eta=eta, method=method)
             for k, inf in info.items():
-                if inf["status"] != 0 or max(inf["relres"]) > TOL:
+                if inf["status"] != 0 or max(inf["relres"]) > tol:
                     # the chain's slab solves use BiCGStab; a stalled one is redone by CGNR
                     raise RuntimeError(f"factorised chain slab {k} failed: {inf}")
             rec["C_exact"].append(column_correlator(T, L, Se, src[0]).tolist())
