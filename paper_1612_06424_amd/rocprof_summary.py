@@ -2,7 +2,8 @@
 
     python -m paper_1612_06424_amd.rocprof_summary DIR [--keep-raw]
 
-DIR holds one rocprofv3 output directory per pass (csv format):
+profile_bench.sh beside this file runs the passes and then this module.  DIR holds one
+rocprofv3 output directory per pass (csv format):
   trace/       --kernel-trace --stats of the bench
   fetch/       --pmc FETCH_SIZE  (stencil kernels: dslash and half-hop instances)
   write/       --pmc WRITE_SIZE  (stencil kernels)
@@ -31,8 +32,8 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 # the sources that decide what the stencil kernels do and how they are launched
-STENCIL_SOURCES = ["csrc/dd_dslash.h", "csrc/dd_eo.h", "csrc/dd_wilson.h", "csrc/dd_internal.h", "csrc/dirac.hip",
-                   "csrc/evenodd.hip", "csrc/batched.hip", "csrc/tune.hip", "tune_cache_mi355x.txt"]
+STENCIL_SOURCES = ["csrc/dd_dslash.h", "csrc/dd_eo.h", "csrc/dd_eo_lds.h", "csrc/dd_wilson.h", "csrc/dd_internal.h",
+                   "csrc/dirac.hip", "csrc/evenodd.hip", "csrc/batched.hip", "csrc/tune.hip", "tune_cache_mi355x.txt"]
 
 
 def kernel_source_hash() -> str:
@@ -49,6 +50,49 @@ def kernel_source_hash() -> str:
 def short_name(n: str) -> str:
     m = re.search(r"(k_\w+<[^()]*>|k_\w+|__amd_\w+)", n)
     return m.group(1) if m else n[:48]
+
+
+def timing_name(k: str) -> str:
+    """The library's HIP-event timing name of a kernel instance: the full stencil with one
+    column per thread drops its last template argument."""
+    return k[:-4] + ">" if k.startswith("k_dslash<") and k.endswith(", 1>") else k
+
+
+HEADER = """# Stencil and solver kernels of the bench workload (64x32^3 lattice, its 16x32^3 slabs, 96 batched domains, 32x16^3 force domain)
+
+Command (repository root, one MI355X): `bash paper_1612_06424_amd/profile_bench.sh OUT`, which runs,
+with `DD_TUNE_CACHE` naming a copy of `paper_1612_06424_amd/tune_cache_mi355x.txt` (so that every pass
+launches the same kernel instances), B = `bench.py --steps 1 --warmup 1 --no-cpu-baseline --parts
+stencil,solve,fact,overlap,batched,force` and SEL = `--kernel-include-regex "dslash|eo_hop|eo_lds"`:
+
+    cd /tmp && export TMPDIR=/tmp
+    rocprofv3 --kernel-trace --stats -f csv -d OUT/trace -o run -- python3 B > OUT/trace.log
+    rocprofv3 --pmc FETCH_SIZE -f csv -d OUT/copy_fetch -o run -- python3 bench.py --copy-calibration
+    rocprofv3 --pmc WRITE_SIZE -f csv -d OUT/copy_write -o run -- python3 bench.py --copy-calibration
+    rocprofv3 --pmc FETCH_SIZE SEL -f csv -d OUT/fetch -o run -- python3 B
+    rocprofv3 --pmc WRITE_SIZE SEL -f csv -d OUT/write -o run -- python3 B
+    rocprofv3 --pmc TA_TA_BUSY_sum TA_ADDR_STALLED_BY_TC_CYCLES_sum TCP_TCR_TCP_STALL_CYCLES_sum \\
+        TCP_PENDING_STALL_CYCLES_sum TCP_TOTAL_CACHE_ACCESSES_sum SQ_INSTS_VMEM_RD GRBM_GUI_ACTIVE SEL \\
+        -f csv -d OUT/units -o run -- python3 B
+    python3 -m paper_1612_06424_amd.rocprof_summary OUT
+
+Kernel names: `k_dslash<real, dagger, epilogue, workgroup size, columns per thread>` is the
+time-sweep stencil (epilogue 0 store, 1 <aux, D in>, 2 <D in, in> and |D in|^2, 3 residual,
+4 |D in|^2, 5 kappa D_hop in); `k_eo_hop<real, dagger, epilogue, workgroup size, self, columns per
+thread, two-row links>` is the even-odd half hop (`k_eo_hop_nt` the same with non-temporal output
+stores; self = true: the second half of the Schur operator, or the source preparation /
+reconstruction), `k_eo_lds<float, dagger, epilogue, self, L/2, non-temporal>` its LDS-tile form
+(one slice per workgroup), `k_beo_hop<real, dagger, epilogue, self, columns per thread, two-row
+links>` its multi-domain form in the batched solve.  The batched solve replays its inner
+iterations as a HIP graph, whose launches the library's HIP-event timing does not see: for
+`k_beo_hop` the HIP-event column averages the eager launches only, the rocprof column all of
+them.  Algorithmic bytes per launch: V ((48 + e) ncol + 72) sizeof(real) for the full stencil,
+(V/2) ((48 + e) ncol + 144) sizeof(real) for a half hop (e = 24 per extra field read: aux for
+epilogues 1 and 3, the self field; 96 instead of 144 with two-row links), with ncol the live
+columns.  `stencil_traffic.json` beside this file holds the per-launch HBM bytes that bench.py
+reports as roofline.traffic while the hashed stencil sources are unchanged.
+
+"""
 
 
 def _rows(pattern):
@@ -130,9 +174,11 @@ def main(argv):
             bench = json.loads(line)
     lines = ["| kernel | calls | avg us | total ms | % time |", "|---|---:|---:|---:|---:|"]
     tot = {}
-    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+    for n, r in enumerate(sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))):
         k = short_name(r["Name"])
         tot[k] = (int(r["Calls"]), float(r["AverageNs"]))
+        if n >= 25:
+            continue
         lines.append(f"| `{k}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.2f} |")
     traffic = {}
@@ -145,9 +191,10 @@ def main(argv):
         fb = fe[k][1] * 1024 * f_scale
         wb = wr[k][1] * 1024 * w_scale
         alg = ev = None
-        if k in kt and kt[k]["launches"]:
-            alg = kt[k]["GBs"] * kt[k]["ms"] * 1e6 / kt[k]["launches"]
-            ev = kt[k]["ms"] / kt[k]["launches"] * 1e3
+        tk = timing_name(k)
+        if tk in kt and kt[tk]["launches"]:
+            alg = kt[tk]["GBs"] * kt[tk]["ms"] * 1e6 / kt[tk]["launches"]
+            ev = kt[tk]["ms"] / kt[tk]["launches"] * 1e3
         traffic[k] = dict(launches=fe[k][0], fetch_bytes=round(fb), write_bytes=round(wb),
                           hbm_bytes=round(fb + wb), algorithmic_bytes=round(alg) if alg else None)
         tl.append(f"| `{k}` | {fe[k][0]} | {fb:.4g} | {wb:.4g} | {fb + wb:.4g} | "
@@ -158,6 +205,7 @@ def main(argv):
         json.dump({"source_hash": src_hash, "fetch_scale": f_scale, "write_scale": w_scale, "kernels": traffic},
                   f, indent=1)
     with open(os.path.join(d, "summary.md"), "w") as f:
+        f.write(HEADER)
         f.write(f"Stencil source hash: `{src_hash}`\n\n")
         if f_scale:
             f.write(f"Copy calibration (1 GiB device copy): FETCH_SIZE x {f_scale:.3f}, WRITE_SIZE x {w_scale:.3f} "
