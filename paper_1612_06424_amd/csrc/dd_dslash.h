@@ -17,6 +17,13 @@
 // (2 spins x 3 colours) before the SU(3) multiply.  All loads and stores go
 // through raw buffer resources (32-bit offsets within one column).
 //
+// XS (L dividing 64, at least 4): a wavefront holds whole x rows, one site per
+// lane, so the two x hops need no loads: each lane projects its own psi(x),
+// hands P psi(x) to the lane of x - 1 (its forward neighbour's hop) and
+// U_1(x)^+ P psi(x) (with the link it loads for its own forward hop) to the lane
+// of x + 1, through cross-lane permutes.  Every product is the one the loading
+// form computes, in the same order, so the result is bitwise the same.
+//
 // Fused epilogues (EPI): the result is stored and, per workgroup, FP64 partial
 // sums are written to slot[0..2]:
 //   EPI_STORE    nothing
@@ -55,7 +62,46 @@ __device__ __forceinline__ int tile_site(int sb, int tid, int NT, int L, int L3,
     return (z * L + y) * L + x;
 }
 
-template <typename R, int DAG, int EPI, int NT, int KC>
+// Value v of the lane whose index is src_lane (all 64 lanes of the wavefront active).
+__device__ __forceinline__ float lane_read(float v, int src_lane) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_read(double v, int src_lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The x hops of a site from the lanes of its x neighbours (XS form): a[k] += the
+// forward hop (1 + FW gamma_1) U_1(x) psi(x + 1), then the backward hop
+// (1 - FW gamma_1) U_1(x - 1)^+ psi(x - 1), as bhop_cols adds them.
+template <typename R, int FW, int KC>
+__device__ __forceinline__ void xhops_lanes(cpx<R> (&a)[KC][12], const cpx<R> (&cur)[KC][12], rsrc_t u, uint32_t ls,
+                                            int sl, int x, int L) {
+    constexpr int BW = -FW;
+    cpx<R> w[9];
+    bload_link<R>(u, ls, sl, w);  // U_1(x)
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int up = x == L - 1 ? lane - (L - 1) : lane + 1;  // the lane of x + 1
+    const int dn = x == 0 ? lane + (L - 1) : lane - 1;      // the lane of x - 1
+#pragma unroll
+    for (int k = 0; k < KC; k++) {
+        cpx<R> h[6], t[6];
+        project<R, 1, FW>(cur[k], h);
+#pragma unroll
+        for (int j = 0; j < 6; j++) h[j] = mk<R>(lane_read(h[j].re, up), lane_read(h[j].im, up));
+        transport<R, false>(w, h, R(1), t);
+        accum<R, 1, FW>(a[k], t);
+        project<R, 1, BW>(cur[k], h);
+        transport<R, true>(w, h, R(1), t);
+#pragma unroll
+        for (int j = 0; j < 6; j++) t[j] = mk<R>(lane_read(t[j].re, dn), lane_read(t[j].im, dn));
+        accum<R, 1, BW>(a[k], t);
+    }
+}
+
+template <typename R, int DAG, int EPI, int NT, int KC, bool XS = false>
 __device__ __forceinline__ void dslash_tile_cols(const Geo& g, const cpx<R>* __restrict__ U, R mass,
                                                  const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                  const cpx<R>* __restrict__ aux, unsigned live, int sb, int tc,
@@ -165,8 +211,12 @@ __device__ __forceinline__ void dslash_tile_cols(const Geo& g, const cpx<R>* __r
 #pragma unroll
                     for (int j = 0; j < 6; j++) hb[k][j] = mk<R>(0, 0);
             }
-            bhop_cols<R, 1, FW, false, KC, false>(a, rf, cs, fs, s + dxp, ru1, ls, sl);
-            bhop_cols<R, 1, BW, true, KC, false>(a, rf, cs, fs, s + dxm, ru1, ls, sl + dxm);
+            if constexpr (XS) {
+                xhops_lanes<R, FW, KC>(a, cur, ru1, ls, sl, x, L);
+            } else {
+                bhop_cols<R, 1, FW, false, KC, false>(a, rf, cs, fs, s + dxp, ru1, ls, sl);
+                bhop_cols<R, 1, BW, true, KC, false>(a, rf, cs, fs, s + dxm, ru1, ls, sl + dxm);
+            }
             bhop_cols<R, 2, FW, false, KC, false>(a, rf, cs, fs, s + dyp, ru2, ls, sl);
             bhop_cols<R, 2, BW, true, KC, false>(a, rf, cs, fs, s + dym, ru2, ls, sl + dym);
             bhop_cols<R, 3, FW, false, KC, false>(a, rf, cs, fs, s + dzp, ru3, ls, sl);

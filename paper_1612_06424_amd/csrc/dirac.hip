@@ -13,9 +13,12 @@ namespace {
 // Workgroup index -> (group of KC columns fastest, spatial block, time chunk),
 // optionally remapped so that each XCD takes a contiguous range of workgroups.
 // ncol is a multiple of KC; the workgroup runs while one column of its group is
-// active (a stopped column keeps its output).
-template <typename R, int DAG, int EPI, int NT, int KC>
-__global__ __launch_bounds__(NT, sweep_waves<R>()) void k_dslash(Geo g, const cpx<R>* __restrict__ U, R mass,
+// active (a stopped column keeps its output).  XS: the x hops through lane
+// permutes (whole x rows per wavefront, see dd_dslash.h).
+// The XS form in FP32 with two columns per thread is held to two waves per SIMD (256
+// registers), where the loading form stores through its epilogue without the bound.
+template <typename R, int DAG, int EPI, int NT, int KC, bool XS>
+__global__ __launch_bounds__(NT, (sizeof(R) == 4 && KC == 2 && XS) ? 2 : sweep_waves<R>()) void k_dslash(Geo g, const cpx<R>* __restrict__ U, R mass,
                                                const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
                                                const cpx<R>* __restrict__ aux, int ncol, int tc_len,
                                                int remap, int blocked, double* __restrict__ partial,
@@ -39,17 +42,17 @@ __global__ __launch_bounds__(NT, sweep_waves<R>()) void k_dslash(Geo g, const cp
     if (live == 0) return;  // uniform over the workgroup
     const size_t off = (size_t)col * 12 * g.nsite;
     double* slot = partial + ((size_t)col * nsb * nchunk + (size_t)tc * nsb + sb) * 3;
-    dslash_tile_cols<R, DAG, EPI, NT, KC>(g, U, mass, in + off, out + off, aux != nullptr ? aux + off : nullptr,
+    dslash_tile_cols<R, DAG, EPI, NT, KC, XS>(g, U, mass, in + off, out + off, aux != nullptr ? aux + off : nullptr,
                                           live, sb, tc, tc_len, slot, (size_t)nsb * nchunk, (blocked & 1) != 0,
                                           blocked >> 8);
 }
 
-template <typename R, int DAG, int NT, int KC>
+template <typename R, int DAG, int NT, int KC, bool XS>
 void launch_epi(dd_ctx* c, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R mass,
                 const cpx<R>* in, cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap, int blocked,
                 double* partial, const ColState* st) {
 #define DD_EPI_CASE(E)                                                                                               \
-    hipLaunchKernelGGL((k_dslash<R, DAG, E, NT, KC>), grid, dim3(NT), 0, c->stream, g, U, mass, in, out, aux, ncol, \
+    hipLaunchKernelGGL((k_dslash<R, DAG, E, NT, KC, XS>), grid, dim3(NT), 0, c->stream, g, U, mass, in, out, aux, ncol, \
                        tc, remap, blocked, partial, st)
     switch (epi) {
         case EPI_STORE: DD_EPI_CASE(EPI_STORE); break;
@@ -62,25 +65,25 @@ void launch_epi(dd_ctx* c, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R 
 #undef DD_EPI_CASE
 }
 
-template <typename R, int DAG, int NT>
+template <typename R, int DAG, int NT, bool XS>
 void launch_kc(dd_ctx* c, int kc, int epi, dim3 grid, const Geo& g, const cpx<R>* U, R mass, const cpx<R>* in,
                cpx<R>* out, const cpx<R>* aux, int ncol, int tc, int remap, int blocked, double* partial,
                const ColState* st) {
     if (kc == 2) {
-        launch_epi<R, DAG, NT, 2>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
+        launch_epi<R, DAG, NT, 2, XS>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
         return;
     }
     if constexpr (sizeof(R) == 4) {
         if (kc == 3) {
-            launch_epi<R, DAG, NT, 3>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
+            launch_epi<R, DAG, NT, 3, XS>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
             return;
         }
         if (kc == 4) {
-            launch_epi<R, DAG, NT, 4>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
+            launch_epi<R, DAG, NT, 4, XS>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
             return;
         }
     }
-    launch_epi<R, DAG, NT, 1>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
+    launch_epi<R, DAG, NT, 1, XS>(c, epi, grid, g, U, mass, in, out, aux, ncol, tc, remap, blocked, partial, st);
 }
 
 }  // namespace
@@ -135,19 +138,27 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
     const int ry = brick_rows(g, sc.nt);
     const int blk = ((sc.blocked & 1) && ry > 0 ? 1 | (ry << 8) : 0) | (sc.blocked & 2);
     const R mass = R(epi == EPI_HOP ? kappa : 1.0 / (2.0 * kappa));  // EPI_HOP scales the hop by kappa
+    // x hops through lane permutes where every wavefront holds whole x rows (NT is 128 or 256)
+    const bool xs = g.L >= 4 && kWave % g.L == 0;
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
-#define DD_NT_CASE(NTV)                                                                                         \
-    if (dag)                                                                                                    \
-        launch_kc<R, 1, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, blk, partial, st); \
-    else                                                                                                        \
-        launch_kc<R, 0, NTV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, blk, partial, st);
+#define DD_KC_CASE(DAGV, NTV, XSV) \
+    launch_kc<R, DAGV, NTV, XSV>(c, kc, epi, grid, g, U, mass, in, out, aux, ncol, sc.tc, sc.remap, blk, partial, st)
+#define DD_NT_CASE(NTV)                                  \
+    if (dag) {                                           \
+        if (xs) DD_KC_CASE(1, NTV, true);                \
+        else DD_KC_CASE(1, NTV, false);                  \
+    } else {                                             \
+        if (xs) DD_KC_CASE(0, NTV, true);                \
+        else DD_KC_CASE(0, NTV, false);                  \
+    }
     if (sc.nt == 256) {
         DD_NT_CASE(256)
     } else {
         DD_NT_CASE(128)
     }
 #undef DD_NT_CASE
+#undef DD_KC_CASE
     if (c->timing) {
         const double extra = (epi == EPI_DOT_AUX || epi == EPI_RESID) ? 24.0 : 0.0;
         const double bytes = (double)g.nsite * ((48.0 + extra) * ncol * c->bill_frac + 72.0) * sizeof(R);
