@@ -53,9 +53,17 @@ def short_name(n: str) -> str:
 
 
 def timing_name(k: str) -> str:
-    """The library's HIP-event timing name of a kernel instance: the full stencil with one
-    column per thread drops its last template argument."""
-    return k[:-4] + ">" if k.startswith("k_dslash<") and k.endswith(", 1>") else k
+    """The library's HIP-event timing name of a kernel instance: the full stencil's timing name
+    omits its last template argument (x hops through lane permutes or not), and with one column
+    per thread the column count as well."""
+    if not k.startswith("k_dslash<"):
+        return k
+    args = [a.strip() for a in k[len("k_dslash<"):-1].split(",")]
+    if len(args) == 6:
+        args = args[:5]
+    if len(args) == 5 and args[4] == "1":
+        args = args[:4]
+    return "k_dslash<" + ", ".join(args) + ">"
 
 
 HEADER = """# Stencil and solver kernels of the bench workload (64x32^3 lattice, its 16x32^3 slabs, 96 batched domains, 32x16^3 force domain)
@@ -76,8 +84,9 @@ stencil,solve,fact,overlap,batched,force` and SEL = `--kernel-include-regex "dsl
         -f csv -d OUT/units -o run -- python3 B
     python3 -m paper_1612_06424_amd.rocprof_summary OUT
 
-Kernel names: `k_dslash<real, dagger, epilogue, workgroup size, columns per thread>` is the
-time-sweep stencil (epilogue 0 store, 1 <aux, D in>, 2 <D in, in> and |D in|^2, 3 residual,
+Kernel names: `k_dslash<real, dagger, epilogue, workgroup size, columns per thread, x hops from
+neighbouring lanes>` is the time-sweep stencil (its HIP-event name omits the last argument, and the
+column count when it is 1) (epilogue 0 store, 1 <aux, D in>, 2 <D in, in> and |D in|^2, 3 residual,
 4 |D in|^2, 5 kappa D_hop in); `k_eo_hop<real, dagger, epilogue, workgroup size, self, columns per
 thread, two-row links>` is the even-odd half hop (`k_eo_hop_nt` the same with non-temporal output
 stores; self = true: the second half of the Schur operator, or the source preparation /
@@ -195,7 +204,7 @@ def main(argv):
         if tk in kt and kt[tk]["launches"]:
             alg = kt[tk]["GBs"] * kt[tk]["ms"] * 1e6 / kt[tk]["launches"]
             ev = kt[tk]["ms"] / kt[tk]["launches"] * 1e3
-        traffic[k] = dict(launches=fe[k][0], fetch_bytes=round(fb), write_bytes=round(wb),
+        traffic[tk] = dict(launches=fe[k][0], fetch_bytes=round(fb), write_bytes=round(wb),
                           hbm_bytes=round(fb + wb), algorithmic_bytes=round(alg) if alg else None)
         tl.append(f"| `{k}` | {fe[k][0]} | {fb:.4g} | {wb:.4g} | {fb + wb:.4g} | "
                   f"{alg:.4g} | {(fb + wb) / alg:.2f} | {ev:.1f} | {tot.get(k, (0, 0))[1] / 1e3:.1f} |"
