@@ -21,8 +21,9 @@
 // lane, so the two x hops need no loads: each lane projects its own psi(x),
 // hands P psi(x) to the lane of x - 1 (its forward neighbour's hop) and
 // U_1(x)^+ P psi(x) (with the link it loads for its own forward hop) to the lane
-// of x + 1, through cross-lane permutes.  Every product is the one the loading
-// form computes, in the same order, so the result is bitwise the same.
+// of x + 1, through cross-lane permutes.  The products and the order of the hop
+// sums are those of the loading form; the compiler's multiply-add contraction
+// differs between the two forms, so they agree to rounding, not bitwise.
 //
 // Fused epilogues (EPI): the result is stored and, per workgroup, FP64 partial
 // sums are written to slot[0..2]:

@@ -123,7 +123,9 @@ struct StencilSched {
     int kc = 1;       // columns per thread
     int blocked = 0;  // tile flags: bit 0 tiles as (y, z) bricks of x rows (even-odd: 4 x 4),
                       // bit 1 the time chunks of a tile in adjacent workgroups, bit 2 non-temporal
-                      // output stores (two columns per thread)
+                      // output stores (half hop, two columns per thread) or, for the full stencil,
+                      // x hops loaded rather than taken from neighbouring lanes; bit 3 the half
+                      // hop's LDS-tile form
 };
 
 struct TimedLaunch {

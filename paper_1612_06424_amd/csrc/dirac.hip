@@ -138,8 +138,9 @@ void launch_dslash_sched(dd_ctx* c, const Geo& g, const StencilSched& sc, const 
     const int ry = brick_rows(g, sc.nt);
     const int blk = ((sc.blocked & 1) && ry > 0 ? 1 | (ry << 8) : 0) | (sc.blocked & 2);
     const R mass = R(epi == EPI_HOP ? kappa : 1.0 / (2.0 * kappa));  // EPI_HOP scales the hop by kappa
-    // x hops through lane permutes where every wavefront holds whole x rows (NT is 128 or 256)
-    const bool xs = g.L >= 4 && kWave % g.L == 0;
+    // x hops through lane permutes where every wavefront holds whole x rows (NT is 128 or 256),
+    // unless tile flag bit 2 asks for the loading form (never set by the tuner)
+    const bool xs = g.L >= 4 && kWave % g.L == 0 && (sc.blocked & 4) == 0;
     hipEvent_t ev = nullptr;
     if (c->timing) timing_begin(c, &ev);
 #define DD_KC_CASE(DAGV, NTV, XSV) \
