@@ -1,5 +1,5 @@
-"""GPU checks of the adjoint row (the fermion force of a domain, the benchmark spec (3); Sec. 5 gives
-D^+ through gamma_5-hermiticity) and of the initial guess of dd_block_solve.
+"""GPU checks of the adjoint (the fermion force of a domain, differentiated through the block
+solve; Sec. 5 gives D^+ through gamma_5-hermiticity) and of the initial guess of dd_block_solve.
 
 - BlockSolveFn (x = D_Lambda^-1 b with the hand-written adjoint solve in its backward) passes
   torch.autograd.gradcheck in U and b on 4 x 2^3 lattices (whole lattice and a slab).
