@@ -12,9 +12,10 @@ already resident in HBM:
   factorised propagator across the four slabs [0,16) [16,32) [32,48) [48,64)
             (mixed solves, frontier hops) and the exact whole-lattice propagator,
             then the pion correlators C_fact(t), C_exact(t)
-  overlap   the same factorised propagator with overlap regions of 8 time slices
-            (Sec. 3.2: the slabs that feed a frontier are also solved on their
-            extension) and the correction of its correlator
+  overlap   (once, after the timed steps) the same factorised propagator with
+            overlap regions of 8 time slices (Sec. 3.2: the slabs that feed a
+            frontier are also solved on their extension) and the correction of
+            its correlator
   batched   96 independent Dirichlet domains of uneven sizes, 12 sources each
   force     S = phi^+ (D^+ D)^-1 phi on a 32x16^3 Dirichlet domain and its link
             force through the hand-written adjoint (torch.autograd)
@@ -227,6 +228,24 @@ def main():
     corr_ref = {}  # the exact correlator of the latest step, for the overlap correction
     stencil_acc = {"bytes": 0.0, "ms": 0.0, "timed": False}  # the 64x32^3 D launches of the timed steps
 
+    def overlap8():
+        # the four-slab factorised propagator with overlap regions Delta = 8 (the first "next" row):
+        # its extended slabs at this kappa need ~1200 CGNR iterations each, so it runs once, after
+        # the timed steps, and is not part of a step
+        t0 = time.perf_counter()
+        Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx, overlap=8)
+        Cf = dd.pion_correlator(ctx, Sf, src[0])
+        nd = len(w["domains"])
+        r = dict(ms=(time.perf_counter() - t0) * 1e3, timed_step=False,
+                 slab_iters=[s["iters"] for s in fst[:nd]],
+                 max_true_rel_resid=max(max(s["true_rel_resid"]) for s in fst[:nd]))
+        if "Ce" in corr_ref:
+            Ce = corr_ref["Ce"]
+            for t in (0, 8, 16, 32):
+                r[f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
+        del Sf
+        return r
+
     def step(record):
         ph = {}
         if "stencil" in parts:
@@ -276,19 +295,6 @@ def main():
                     ph["factorised"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
             corr_ref["Ce"] = Ce
             del Sf, Se
-        if "overlap" in parts:
-            t0 = time.perf_counter()
-            Sf, _, fst = dd.factorized_propagator(ctx, U64, kappa, src, w["domains"], pmx, overlap=8)
-            Cf = dd.pion_correlator(ctx, Sf, src[0])
-            nd = len(w["domains"])
-            ph["factorised_overlap8"] = dict(ms=(time.perf_counter() - t0) * 1e3,
-                                             slab_iters=[s["iters"] for s in fst[:nd]],
-                                             max_true_rel_resid=max(max(s["true_rel_resid"]) for s in fst[:nd]))
-            if record and "Ce" in corr_ref:
-                Ce = corr_ref["Ce"]
-                for t in (0, 8, 16, 32):
-                    ph["factorised_overlap8"][f"C_corr[{t}]/C_exact"] = float((Ce[t] - Cf[t]) / Ce[t])
-            del Sf
         if "projection" in parts:
             t0 = time.perf_counter()
             basis, pst = dd.projection_basis(ctx, U64, kappa, proj_pi, proj_t, +1, proj_v0, proj_iter, pmx)
@@ -451,7 +457,7 @@ def main():
         "dtype": "c128+c64",
         "data": "synthetic",
         "config": {"workload": "64x32^3 Wilson-Dirac, antiperiodic time, eps=0.15, kappa=0.135; "
-                               "12-source solves on the 16x32^3 slab; 4-slab factorised propagator (overlap 0 and 8); "
+                               "12-source solves on the 16x32^3 slab; 4-slab factorised propagator (overlap 0 timed; overlap 8 once, untimed); "
                                "96 uneven Dirichlet domains; 32x16^3 force",
                    "lattice": [T, L, L, L], "kappa": kappa, "tol": w["tol"],
                    "parts": sorted(parts)},
@@ -478,6 +484,9 @@ def main():
         out["roofline"]["traffic"] = traffic
         out["roofline"]["traffic_over_algorithmic"] = round(traffic / max(db / max(dn, 1), 1), 3)
     out["parts"] = last
+    if "overlap" in parts:
+        log("overlap 8 (once, untimed)")
+        out["parts"]["factorised_overlap8"] = overlap8()
     if "overlap_study" in parts:
         out["overlap_study"] = overlap_study(dd, ctx, U64, w, pmx)
     if not args.no_cpu_baseline:
