@@ -276,9 +276,9 @@ dd_status dd_nucleon_lines(dd_ctx* ctx, const void* U, double kappa, const dd_do
  * C = gamma_0 gamma_2 in the library's chiral basis.  s: complex128
  * [nvec][12][nt L^3] (device, read only); B: complex128 [nt][nvec][4][nvec][nvec]
  * (device, output; must not overlap s).  1 <= nvec <= 256.  FP64 (the
- * product over sites runs on the matrix cores through rocBLAS, in chunks of
- * sites whose diquarks stay below 2 GiB; the environment variable
- * DD_BLOCK_CHUNK caps the sites per chunk).  Asynchronous.
+ * product over sites runs on the FP64 matrix cores in the library's own GEMM
+ * kernel, in chunks of sites whose diquarks stay below 2 GiB; the environment
+ * variable DD_BLOCK_CHUNK caps the sites per chunk).  Asynchronous.
  */
 dd_status dd_baryon_blocks(dd_ctx* ctx, int nvec, int nt, const void* s, void* B);
 

@@ -49,7 +49,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             objs = dict(zip(order, pool.map(compile_one, order)))
         tmp = LIB + ".tmp"
         cmd = [hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", *[objs[s] for s in SOURCES], "-o", tmp,
-               "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+               "-Wl,-rpath,/opt/rocm/lib"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

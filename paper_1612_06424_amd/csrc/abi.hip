@@ -252,7 +252,6 @@ void dd_destroy(dd_ctx* c) {
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->host_state) (void)hipHostFree(c->host_state);
     if (c->host_dots) (void)hipHostFree(c->host_dots);
-    blas_release(c);
     delete c;
 }
 

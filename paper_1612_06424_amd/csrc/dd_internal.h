@@ -164,8 +164,6 @@ struct dd_ctx {
     dd::ColState* host_state = nullptr;
     double* host_dots = nullptr;
     int host_n = 0;
-    // rocBLAS handle of the nucleon block products (created on first use)
-    void* blas = nullptr;
     // fraction of a launch's columns whose spinor bytes the kernel timing bills: solvers set
     // it to the share of columns active when they launch (a stopped column's workgroups
     // return at once); 1 outside solves
@@ -448,6 +446,5 @@ dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<doub
 // W_host[w][y][x] (complex) = W1 (w = 0), W2 (w = 1) of the blocks Bx (ntx slices), By (nty)
 dd_status nucleon_contract(dd_ctx* c, int n, int ntx, const cpx<double>* Bx, int nty, const cpx<double>* By,
                            double* W_host);
-void blas_release(dd_ctx* c);
 
 }  // namespace dd

@@ -20,11 +20,14 @@
 //   E_c = eps^{abc} sum_{beta, gamma} s_i^a_beta (C gamma5)_{beta gamma} s_j^b_gamma,
 // a (P x 3 X) by (3 X x 4 N_m) matrix product per chunk of X sites, over the
 // P = N_m (N_m + 1) / 2 pairs i <= j only: B is symmetric in (i, j) (C gamma5 and
-// eps are both antisymmetric).  The diquarks E (a hand-written kernel,
-// HBM-bound) and the packed quark matrix are written per chunk, the product runs
-// as one FP64 complex GEMM (rocBLAS, matrix cores) accumulating into the
-// slice's packed blocks, and a last kernel writes both (i, j) and (j, i).  About
-// N_m / 2 flops per byte of E, so the product, not the diquarks, bounds the time.
+// eps are both antisymmetric).  The diquarks E (HBM-bound) and the packed quark
+// matrix are written per chunk; the product is a complex FP64 GEMM on the matrix
+// cores (k_zgemm_mfma: 64 x 64 tiles of four 16 x 16 x 4 FP64 MFMA blocks per
+// wavefront, operands staged through LDS, the k range split so that the grid
+// fills the chip, the splits added in a fixed order by k_zgemm_reduce)
+// accumulating into the slice's packed blocks, and a last kernel writes both
+// (i, j) and (j, i).  About N_m / 2 flops per byte of E, so the product, not the
+// diquarks, bounds the time.
 //
 // Basis: chiral, component = spin * 3 + colour; gamma_0 = [[0, -1], [-1, 0]]
 // (2 x 2 blocks), gamma5 = diag(1, 1, -1, -1), C = gamma_0 gamma_2 (C gamma_mu
@@ -35,9 +38,8 @@
 #include <cstdlib>
 #include <cstring>
 
-#include <rocblas/rocblas.h>
-
 #include "dd_internal.h"
+#include "dd_wilson.h"
 
 namespace dd {
 
@@ -116,6 +118,169 @@ __global__ __launch_bounds__(kNB) void k_diquarks(int n, long long nsite, long l
             E[r + (size_t)(2 * X + x) * M] = diquark(si, sj, 0, 1) - diquark(si, sj, 1, 0);
         }
     }
+}
+
+// ------------------------------------------------------------------ complex FP64 GEMM
+// C (M x N) = A (M x K) B (K x N), all column-major complex FP64 (lda = M, ldb = K,
+// ldc = M), on the matrix cores.  v_mfma_f64_16x16x4f64 multiplies a 16 x 4 block
+// (lane l holds A[l % 16][l / 16]) by a 4 x 16 block (lane l holds B[l / 16][l % 16])
+// into a 16 x 16 accumulator (lane l holds rows l / 16 + 4 e, e = 0..3, of column l % 16).
+// A complex product is four real ones: re += ar br + ai (-bi), im += ar bi + ai br.
+// A workgroup (four wavefronts, 2 x 2) owns a 64 x 64 tile of C and one of nsplit
+// ranges of k (kps steps of 16); per step the 64 x 16 panel of A and the 16 x 64
+// panel of B go through LDS (the next step's panels are loaded into registers while
+// the current one is multiplied), and each wavefront runs 16 MFMAs per 4 values of
+// k on its 32 x 32 quarter (132 registers: three wavefronts per SIMD; a form holding
+// the step's operands up front took 212 and ran 14 % slower).  Each split writes its own partial C; k_zgemm_reduce
+// adds them in a fixed order, so the result does not depend on scheduling.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+constexpr int kGM = 64, kGN = 64, kGK = 16;  // workgroup tile (complex entries) and k step
+constexpr int kGThreads = 256;
+
+__device__ __forceinline__ dbl2 gload2(rsrc_t r, uint32_t voff) {
+    return __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
+
+__global__ __launch_bounds__(kGThreads, 2) void k_zgemm_mfma(int M, int N, int K, int kps,
+                                                             const cpx<double>* __restrict__ A,
+                                                             const cpx<double>* __restrict__ B,
+                                                             cpx<double>* __restrict__ Cpart) {
+    __shared__ dbl2 As[kGK][kGM + 1];  // As[k][m]; one entry of padding per row
+    __shared__ dbl2 Bs[kGK][kGN + 1];  // Bs[k][n]
+    const int tm = (M + kGM - 1) / kGM, tn = (N + kGN - 1) / kGN;
+    // XCD-contiguous work ranges, the column tiles of one (row tile, split) adjacent: they share the A panel
+    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int nt = w % tn, mt = (w / tn) % tm, sp = w / (tn * tm);
+    const int m0 = mt * kGM, n0 = nt * kGN;
+    const int nkt = (K + kGK - 1) / kGK;
+    const int kt0 = sp * kps, kt1 = min(nkt, kt0 + kps);
+    const rsrc_t ra = make_rsrc(A, (uint32_t)((size_t)M * K * sizeof(cpx<double>)));
+    const rsrc_t rb = make_rsrc(B, (uint32_t)((size_t)K * N * sizeof(cpx<double>)));
+
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    // global -> LDS roles: A entries (m = tid % 64, k = tid / 64 + 4 r), B entries (k = tid % 16, n = tid / 16 + 16 r)
+    const int am = tid & 63, ak = tid >> 6;
+    const int bk = tid & 15, bn = tid >> 4;
+    dbl2 ga[4], gb[4];
+    auto fetch = [&](int kt) {
+        const int k0 = kt * kGK;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int m = m0 + am, k = k0 + ak + 4 * r;
+            const bool ok = m < M && k < K;
+            const dbl2 v = gload2(ra, ok ? (uint32_t)(((size_t)k * M + m) * sizeof(cpx<double>)) : 0u);
+            ga[r] = ok ? v : dbl2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int k = k0 + bk, n = n0 + bn + 16 * r;
+            const bool ok = k < K && n < N;
+            const dbl2 v = gload2(rb, ok ? (uint32_t)(((size_t)n * K + k) * sizeof(cpx<double>)) : 0u);
+            gb[r] = ok ? v : dbl2{0.0, 0.0};
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; r++) As[ak + 4 * r][am] = ga[r];
+#pragma unroll
+        for (int r = 0; r < 4; r++) Bs[bk][bn + 16 * r] = gb[r];
+    };
+
+    dbl4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) cr[i][j] = ci[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    if (kt0 < kt1) {
+        fetch(kt0);
+        stash();
+        __syncthreads();
+    }
+    for (int kt = kt0; kt < kt1; kt++) {
+        if (kt + 1 < kt1) fetch(kt + 1);  // in flight while this step is multiplied
+#pragma unroll
+        for (int ks = 0; ks < kGK / 4; ks++) {
+            const int kk = 4 * ks + (lane >> 4);
+            double ar[2], ai[2], br[2], bi[2], bm[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const dbl2 a = As[kk][wm * 32 + i * 16 + (lane & 15)];
+                ar[i] = a.x;
+                ai[i] = a.y;
+                const dbl2 b = Bs[kk][wn * 32 + i * 16 + (lane & 15)];
+                br[i] = b.x;
+                bi[i] = b.y;
+                bm[i] = -b.y;
+            }
+            // consecutive MFMAs go to different accumulators
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bm[j], cr[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+        }
+        __syncthreads();  // every wavefront is done with the panels
+        if (kt + 1 < kt1) {
+            stash();
+            __syncthreads();
+        }
+    }
+
+    // this split's partial C: two 8-byte stores per entry (re, then im through the scalar offset)
+    const size_t MN = (size_t)M * N;
+    const rsrc_t rc = make_rsrc(Cpart + (size_t)sp * MN, (uint32_t)(MN * sizeof(cpx<double>)));
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * e;
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < M && col < N) {
+                    const uint32_t vo = (uint32_t)(((size_t)col * M + row) * sizeof(cpx<double>));
+                    // the elements go through scalars: a bit cast of a vector element expression
+                    // compiled to element 0 of the vector here
+                    const double re = cr[i][j][e];
+                    const double im = ci[i][j][e];
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, re), rc, (int)vo, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, im), rc, (int)vo, 8, 0);
+                }
+            }
+}
+
+// C (+)= sum over the splits of Cpart, in split order
+__global__ __launch_bounds__(kNB) void k_zgemm_reduce(size_t MN, int nsplit, int acc,
+                                                      const cpx<double>* __restrict__ Cpart,
+                                                      cpx<double>* __restrict__ C) {
+    const size_t f = (size_t)blockIdx.x * kNB + threadIdx.x;
+    if (f >= MN) return;
+    double re = 0.0, im = 0.0;
+    if (acc) {
+        re = C[f].re;
+        im = C[f].im;
+    }
+    for (int s = 0; s < nsplit; s++) {
+        const cpx<double> v = Cpart[(size_t)s * MN + f];
+        re += v.re;
+        im += v.im;
+    }
+    C[f].re = re;
+    C[f].im = im;
 }
 
 // B[t][k][al][i][j] = Bp[t][(4 k + al) P + p(min(i, j), max(i, j))]
@@ -205,29 +370,8 @@ __global__ __launch_bounds__(kNB) void k_nucleon_final(int nty, int ntx, int nch
     W[((size_t)w * nty * ntx + yx) * 2 + 1] = -im;
 }
 
-rocblas_handle blas_handle(dd_ctx* c, dd_status* st) {
-    if (c->blas == nullptr) {
-        rocblas_handle h;
-        if (rocblas_create_handle(&h) != rocblas_status_success) {
-            *st = fail(c, DD_ERR_HIP, "rocblas_create_handle failed");
-            return nullptr;
-        }
-        c->blas = h;
-    }
-    rocblas_handle h = (rocblas_handle)c->blas;
-    if (rocblas_set_stream(h, c->stream) != rocblas_status_success) {
-        *st = fail(c, DD_ERR_HIP, "rocblas_set_stream failed");
-        return nullptr;
-    }
-    return h;
-}
-
 }  // namespace
 
-void blas_release(dd_ctx* c) {
-    if (c->blas) (void)rocblas_destroy_handle((rocblas_handle)c->blas);
-    c->blas = nullptr;
-}
 
 dd_status nucleon_lines(dd_ctx* c, const cpx<double>* U, double kappa, const dd_domain& gbar, const dd_domain& gstar,
                         int t_phi, int nvec, const cpx<double>* phi, int x0, cpx<double>* xi, cpx<double>* eta,
@@ -303,9 +447,14 @@ dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<doub
     cpx<double>* Bp = E + M * 3 * X;  // the packed blocks of one slice
     cpx<double>* Sp = (cpx<double>*)workspace(c, W_DISC3, (size_t)3 * X * 4 * n * sizeof(cpx<double>), &e);
     if (e != DD_OK) return e;
-    rocblas_handle h = blas_handle(c, &e);
-    if (h == nullptr) return e;
-    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    // the k range of a chunk's product is split so that about 16 workgroups per CU run in all
+    const int N = 4 * n;
+    const int ntile = (int)(((M + kGM - 1) / kGM) * ((N + kGN - 1) / kGN));
+    const int nkt_max = (3 * X + kGK - 1) / kGK;
+    const int nsplit_max = std::max(1, std::min(nkt_max, (16 * 256 + ntile - 1) / ntile));
+    cpx<double>* Cpart =
+        (cpx<double>*)workspace(c, W_DISC1, (size_t)nsplit_max * M * N * sizeof(cpx<double>), &e);
+    if (e != DD_OK) return e;
     const size_t nfull = (size_t)4 * n * n * n;
     for (int t = 0; t < nt; t++) {
         for (int x0 = 0; x0 < L3; x0 += X) {
@@ -315,14 +464,16 @@ dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<doub
                                c->stream, n, nsite, off, xc, s, Sp);
             hipLaunchKernelGGL(k_diquarks, dim3((unsigned)((xc + kXT - 1) / kXT)), dim3(kNB), 0, c->stream, n, nsite,
                                off, xc, s, E);
-            DD_HIP(c, hipGetLastError());
             // Bp (P x 4n, column-major) (+)= E (P x 3 xc) Sp (3 xc x 4n)
-            const rocblas_status bs = rocblas_zgemm(
-                h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)M, 4 * n, 3 * xc, &one,
-                (const rocblas_double_complex*)E, (rocblas_int)M, (const rocblas_double_complex*)Sp, 3 * xc,
-                x0 == 0 ? &zero : &one, (rocblas_double_complex*)Bp, (rocblas_int)M);
-            if (bs != rocblas_status_success)
-                return fail(c, DD_ERR_HIP, std::string("rocblas_zgemm failed: ") + rocblas_status_to_string(bs));
+            const int K = 3 * xc;
+            const int nkt = (K + kGK - 1) / kGK;
+            const int kps = (nkt + nsplit_max - 1) / nsplit_max;
+            const int nsplit = (nkt + kps - 1) / kps;
+            hipLaunchKernelGGL(k_zgemm_mfma, dim3((unsigned)(ntile * nsplit)), dim3(kGThreads), 0, c->stream, (int)M, N,
+                               K, kps, E, Sp, Cpart);
+            hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)((M * N + kNB - 1) / kNB)), dim3(kNB), 0, c->stream,
+                               M * (size_t)N, nsplit, x0 == 0 ? 0 : 1, Cpart, Bp);
+            DD_HIP(c, hipGetLastError());
         }
         hipLaunchKernelGGL(k_unpack_blocks, dim3((unsigned)((nfull + kNB - 1) / kNB)), dim3(kNB), 0, c->stream, n, M,
                            Bp, B + (size_t)t * nfull);

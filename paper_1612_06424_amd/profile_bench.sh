@@ -16,7 +16,7 @@ rm -rf "$O"/trace "$O"/fetch "$O"/write "$O"/units "$O"/copy_fetch "$O"/copy_wri
 cp "$R"/paper_1612_06424_amd/tune_cache_mi355x.txt "$O"/tune_cache.txt
 export DD_TUNE_CACHE=$O/tune_cache.txt
 cd /tmp && export TMPDIR=/tmp
-B=(--steps 1 --warmup 1 --no-cpu-baseline --parts stencil,solve,fact,overlap,batched,force)
+B=(--steps 1 --warmup 1 --no-cpu-baseline --parts stencil,solve,fact,batched,force)
 SEL=(--kernel-include-regex "dslash|eo_hop|eo_lds")
 echo "[profile] kernel trace"
 timeout -s KILL 300 rocprofv3 --kernel-trace --stats -f csv -d "$O"/trace -o run -- python3 "$R"/bench.py "${B[@]}" > "$O"/trace.log 2>&1 || exit $?

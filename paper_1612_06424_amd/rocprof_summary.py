@@ -71,7 +71,7 @@ HEADER = """# Stencil and solver kernels of the bench workload (64x32^3 lattice,
 Command (repository root, one MI355X): `bash paper_1612_06424_amd/profile_bench.sh OUT`, which runs,
 with `DD_TUNE_CACHE` naming a copy of `paper_1612_06424_amd/tune_cache_mi355x.txt` (so that every pass
 launches the same kernel instances), B = `bench.py --steps 1 --warmup 1 --no-cpu-baseline --parts
-stencil,solve,fact,overlap,batched,force` and SEL = `--kernel-include-regex "dslash|eo_hop|eo_lds"`:
+stencil,solve,fact,batched,force` and SEL = `--kernel-include-regex "dslash|eo_hop|eo_lds"`:
 
     cd /tmp && export TMPDIR=/tmp
     rocprofv3 --kernel-trace --stats -f csv -d OUT/trace -o run -- python3 B > OUT/trace.log
