@@ -466,6 +466,11 @@ def main():
                      "kernel": dom_name, "launches": dn, "avg_launch_ms": round(dms / max(dn, 1), 5),
                      "bytes_per_launch": round(db / max(dn, 1)),
                      "share_of_stencil_time": round(dms / max(tot_ms, 1e-9), 3)},
+        # the five kernel instances with the most time, each against the same peak
+        "roofline_top": [{"kernel": k, "share_of_stencil_time": round(v[0] / max(tot_ms, 1e-9), 3),
+                          "achieved": round(v[2] / max(v[0], 1e-9) / 1e6, 1),
+                          "frac": round(v[2] / max(v[0], 1e-9) / 1e6 / HBM_PEAK_GBS, 4)}
+                         for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])[:5]],
         "stencil_kernels": {k: {"ms": round(v[0], 2), "launches": v[1], "GBs": round(v[2] / max(v[0], 1e-9) / 1e6, 1)}
                             for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])},
         "value_definition": "algorithmic GB/s of D on the whole 64x32^3 lattice, FP64 and FP32, 1 and 12 "
