@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kNB) void k_diquarks(int n, long long nsite, long l
 // panel of B go through LDS (the next step's panels are loaded into registers while
 // the current one is multiplied), and each wavefront runs 16 MFMAs per 4 values of
 // k on its 32 x 32 quarter (132 registers: three wavefronts per SIMD; a form holding
-// the step's operands up front took 212 and ran 14 % slower).  Each split writes its own partial C; k_zgemm_reduce
+// the step's operands up front took 212 and ran 16 % slower).  Each split writes its own partial C; k_zgemm_reduce
 // adds them in a fixed order, so the result does not depend on scheduling.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
