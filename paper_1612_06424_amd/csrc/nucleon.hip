@@ -440,6 +440,8 @@ dd_status baryon_blocks(dd_ctx* c, int n, int nt, const cpx<double>* s, cpx<doub
     const size_t M = (size_t)n * (n + 1) / 2;  // pairs i <= j
     // sites per chunk: the diquarks of a chunk stay below 2 GiB
     int X = (int)std::min<size_t>((size_t)L3, std::max<size_t>(64, ((size_t)1 << 31) / (M * 3 * sizeof(cpx<double>))));
+    // the packed quarks too (the product addresses both through 32-bit buffer offsets)
+    X = (int)std::min<size_t>((size_t)X, ((size_t)1 << 31) / ((size_t)3 * 4 * n * sizeof(cpx<double>)));
     if (const char* env = std::getenv("DD_BLOCK_CHUNK")) X = std::max(1, std::min(X, std::atoi(env)));  // tests
     dd_status e = DD_OK;
     cpx<double>* E = (cpx<double>*)workspace(c, W_DISC2, (M * 3 * X + M * 4 * n) * sizeof(cpx<double>), &e);
