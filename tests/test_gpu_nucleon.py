@@ -180,3 +180,33 @@ def test_the_maximum_vector_count():
     W1, W2 = dd.nucleon_contract(ctx, _blocks_to_dev(Bx), _blocks_to_dev(By))
     scale = max(np.abs(W1r).max(), np.abs(W2r).max())
     assert np.abs(W1 - W1r).max() < 1e-11 * scale and np.abs(W2 - W2r).max() < 1e-11 * scale
+
+
+def test_the_maximum_vector_count_on_a_32_cubed_slice():
+    """256 vectors on one 32^3 slice: the largest pair count (32 896 rows of the block product)
+    at the bench's slice size, so the site chunks are short (the diquarks of a chunk stay
+    below 2 GiB: 25 chunks of at most 1360 sites, each accumulated onto the previous ones) and
+    every row and column tile of the product is full or ragged at its edge.  Sampled entries,
+    including the last pairs and the last spin-vector column, against sums from the definition,
+    and the (i, j) symmetry."""
+    dd = lib()
+    step("baryon blocks 256 vectors 32^3")
+    L, n = 32, 256
+    L3 = L ** 3
+    ctx = dd.Context(4, L, 0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4600)
+    s = torch.randn((n, 12, L3), dtype=torch.complex128, device="cuda", generator=g)
+    B = dd.baryon_blocks(ctx, s)
+    torch.cuda.synchronize()
+    Bh = B[0]                                          # [k][alpha][i][j]
+    rng = np.random.default_rng(4601)
+    idx = [tuple(int(v) for v in rng.integers(0, n, 3)) + (int(rng.integers(0, 4)),) for _ in range(10)]
+    idx += [(n - 1, n - 1, n - 1, 3), (0, n - 1, n - 2, 2), (n - 2, n - 1, 0, 1)]
+    cg5 = O.charge_conjugation() @ O.gamma_matrices()[4]
+    for i, j, k, al in idx:
+        q = s[[i, j, k]].cpu().numpy().reshape(3, 4, 3, L3)   # [vector][spin][colour][site]
+        want = np.einsum("abc,rax,rs,sbx,cx->", EPS, q[0], cg5, q[1], q[2, al], optimize=True)
+        got = Bh[k, al, i, j].item()
+        assert abs(got - want) < 1e-12 * np.sqrt(6 * 16 * L3) * 4, (i, j, k, al, got, want)
+        assert abs(Bh[k, al, j, i].item() - got) < 1e-12 * max(1.0, abs(got))
